@@ -1,0 +1,228 @@
+"""Imaginary-time march, Lambda adjoint and response derivatives (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Works with any model object that provides delta1/delta2, zeros(), energy(),
+residual(), vjp(), vjp_fock(), occ_derivs(), domega_mf(), omega0(), omega1()
+and `ints.derivative()` (spin-orbital or restricted).
+
+Forward (Algorithm alg:int in panels, with the grid of grid.py):
+  s(0) = 0; for each panel, from the initial guess s_x = E_x s_b iterate
+      s_x <- E_x s_b - sum_x' W_xx' S[s_x']
+  (Picard) until max|change| <= tol * max(1, max|s|), then
+      s_b <- E_e s_b - sum_x' We_x' S[s_x'].
+  Omega_CC = (1/beta) sum_x g_x E[s_x]            (eqn:Ecc with eqn:g)
+
+Adjoint (the stationarity conditions of the discrete form of eqn:Lagrangian):
+  L = Omega_CC + sum_x <lam_x, F_x> + sum_p <a_{p+1}, F_e,p>
+  F_x   = s_x - E_x s_b + sum_x' W_xx' S_x',  F_e = s_b' - E_e s_b + sum We_x' S_x'
+  lam_x = -(g_x/beta) dE/ds(s_x) - J_x^T lamt_x,   J_x = dS/ds at s_x
+  lamt_x = sum_x'' W_x''x lam_x'' + We_x a_{p+1}   (the discrete eqn:ltilde)
+  a_p    = sum_x E_x lam_x + E_e a_{p+1},  a_P = 0
+which is the discrete counterpart of eqn:lmu / eqn:ltilde (lam_x = -L_x).
+
+Derivatives dOmega/dtheta = dL/dtheta at fixed (s, lam, a):
+  d(Omega_0 + Omega_1)/dtheta
+  + sum_x [(g_x/beta) E(s_x; dI) + <lamt_x, S(s_x; dI)>]     (E, S linear in I)
+  + for beta: sum_x <lam_x, -dE_x/dbeta s_b + sum dW_xx'/dbeta S_x'>
+              + sum_p <a_{p+1}, -dE_e/dbeta s_b + sum dWe_x'/dbeta S_x'>
+(the paper's response types 1, 2, 4, 5 and 6 for this discretisation;
+(1/beta) g_x = b_x / P does not depend on beta).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+def _inner(a, b):
+    return float(np.sum(a[0] * b[0]) + np.sum(a[1] * b[1]))
+
+
+def _maxabs(s):
+    return max(float(np.max(np.abs(s[0]), initial=0.0)), float(np.max(np.abs(s[1]), initial=0.0)))
+
+
+@dataclasses.dataclass
+class Solution:
+    nodes: list          # per node (s1, s2)
+    resid: list          # per node (S1, S2) at the converged amplitudes
+    sb: list             # per panel: state at the panel start
+    energies: np.ndarray
+    omega_cc: float
+    omega0: float
+    omega1: float
+    iters: list
+
+    @property
+    def omega(self):
+        return self.omega0 + self.omega1 + self.omega_cc
+
+
+def _panel_weights(model, grid, deriv=False):
+    w1 = grid.weights(model.delta1, deriv=deriv)
+    w2 = grid.weights(model.delta2, deriv=deriv)
+    return w1, w2
+
+
+def solve(model, grid, tol=1e-13, max_iter=400, mix=1.0):
+    """Forward march.  `mix` < 1 applies linear damping to the Picard update."""
+    (E1, Ee1, W1, We1), (E2, Ee2, W2, We2) = _panel_weights(model, grid)
+    m = grid.m
+    sb = model.zeros()
+    nodes, resid, starts, iters = [], [], [], []
+    for p in range(grid.P):
+        starts.append(sb)
+        s = [(E1[x] * sb[0], E2[x] * sb[1]) for x in range(m)]
+        for it in range(1, max_iter + 1):
+            S = [model.residual(s[x]) for x in range(m)]
+            new = []
+            for x in range(m):
+                n1 = E1[x] * sb[0] - sum(W1[x, y] * S[y][0] for y in range(m))
+                n2 = E2[x] * sb[1] - sum(W2[x, y] * S[y][1] for y in range(m))
+                if mix != 1.0:
+                    n1 = mix * n1 + (1.0 - mix) * s[x][0]
+                    n2 = mix * n2 + (1.0 - mix) * s[x][1]
+                new.append((n1, n2))
+            change = max(_maxabs((new[x][0] - s[x][0], new[x][1] - s[x][1])) for x in range(m))
+            scale = max(1.0, max(_maxabs(v) for v in new))
+            s = new
+            if not np.isfinite(change):
+                raise FloatingPointError(f"panel {p}: non-finite amplitudes")
+            if change <= tol * scale:
+                break
+        else:
+            raise RuntimeError(f"panel {p}: Picard iteration did not converge (last change {change:.3e})")
+        iters.append(it)
+        S = [model.residual(s[x]) for x in range(m)]
+        nodes.extend(s)
+        resid.extend(S)
+        sb = (Ee1 * sb[0] - sum(We1[y] * S[y][0] for y in range(m)),
+              Ee2 * sb[1] - sum(We2[y] * S[y][1] for y in range(m)))
+    wts = np.tile(grid.b / grid.P, grid.P)            # (1/beta) g_x
+    energies = np.array([model.energy(s) for s in nodes])
+    return Solution(nodes, resid, starts, energies, float(wts @ energies),
+                    float(model.omega0()), float(model.omega1()), iters)
+
+
+@dataclasses.dataclass
+class Adjoint:
+    lam: list        # per node
+    lamt: list       # per node (lambda tilde)
+    a: list          # per panel boundary p = 1..P (a[p] multiplies F_e of panel p-1); a[P] = 0
+    iters: list
+
+
+def adjoint(model, grid, sol: Solution, tol=1e-13, max_iter=400):
+    (E1, Ee1, W1, We1), (E2, Ee2, W2, We2) = _panel_weights(model, grid)
+    m, P = grid.m, grid.P
+    z = model.zeros()
+    lam = [None] * (m * P)
+    lamt = [None] * (m * P)
+    a = [None] * (P + 1)
+    a[P] = z
+    iters = [0] * P
+    for p in reversed(range(P)):
+        idx = [p * m + x for x in range(m)]
+        dE = []
+        for x, k in enumerate(idx):
+            g = model.vjp(sol.nodes[k], grid.b[x] / P, (None, None))
+            dE.append(g)
+        l = [(-g[0], -g[1]) for g in dE]
+        an = a[p + 1]
+        for it in range(1, max_iter + 1):
+            lt = []
+            for x in range(m):
+                t1 = We1[x] * an[0] + sum(W1[y, x] * l[y][0] for y in range(m))
+                t2 = We2[x] * an[1] + sum(W2[y, x] * l[y][1] for y in range(m))
+                lt.append((t1, t2))
+            new = []
+            for x, k in enumerate(idx):
+                j = model.vjp(sol.nodes[k], None, lt[x])
+                new.append((-dE[x][0] - j[0], -dE[x][1] - j[1]))
+            change = max(_maxabs((new[x][0] - l[x][0], new[x][1] - l[x][1])) for x in range(m))
+            scale = max(1e-300, max(_maxabs(v) for v in new))
+            l = new
+            if change <= tol * max(scale, 1e-30) or change == 0.0:
+                break
+        else:
+            raise RuntimeError(f"panel {p}: adjoint iteration did not converge")
+        iters[p] = it
+        lt = []
+        for x in range(m):
+            t1 = We1[x] * an[0] + sum(W1[y, x] * l[y][0] for y in range(m))
+            t2 = We2[x] * an[1] + sum(W2[y, x] * l[y][1] for y in range(m))
+            lt.append((t1, t2))
+        for x, k in enumerate(idx):
+            lam[k], lamt[k] = l[x], lt[x]
+        a[p] = (Ee1 * an[0] + sum(E1[x] * l[x][0] for x in range(m)),
+                Ee2 * an[1] + sum(E2[x] * l[x][1] for x in range(m)))
+    return Adjoint(lam, lamt, a, iters)
+
+
+def _integral_term(model, grid, sol, adj, dints):
+    """sum_x [(g_x/beta) E(s_x; dI) + <lamt_x, S(s_x; dI)>]."""
+    tot = 0.0
+    m, P = grid.m, grid.P
+    for k, s in enumerate(sol.nodes):
+        x = k % m
+        tot += grid.b[x] / P * model.energy(s, dints)
+        tot += _inner(adj.lamt[k], model.residual(s, dints))
+    return tot
+
+
+def d_omega(model, grid, sol, adj, theta, dh=None, deri=None):
+    """dOmega/dtheta for theta in {'mu', 'beta', 'h'} (frozen reference).
+
+    theta='h' takes a direction (dh, deri) of the one-body matrix and the
+    two-electron integrals (for example deri = eri/U for d/dU).
+    """
+    ints = model.ints
+    dn_mu, dn_beta = model.occ_derivs()
+    if theta == "mu":
+        dn = dn_mu
+        return (model.domega0("mu") + model.domega_mf(dn)
+                + _integral_term(model, grid, sol, adj, ints.derivative(dn=dn)))
+    if theta == "h":
+        d = model.domega_mf(np.zeros_like(dn_mu), dh=dh, deri=deri)
+        return d + _integral_term(model, grid, sol, adj, ints.derivative(dh=dh, deri=deri))
+    if theta == "beta":
+        dn = dn_beta
+        tot = (model.domega0("beta") + model.domega_mf(dn)
+               + _integral_term(model, grid, sol, adj, ints.derivative(dn=dn)))
+        tot += _grid_beta_term(model, grid, sol, adj)
+        return tot
+    raise ValueError(theta)
+
+
+def _grid_beta_term(model, grid, sol, adj):
+    """Explicit beta dependence of E_x, E_e, W, We through h = beta / P."""
+    w1, w2 = _panel_weights(model, grid, deriv=True)
+    _, _, _, _, dE1, dEe1, dW1, dWe1 = w1
+    _, _, _, _, dE2, dEe2, dW2, dWe2 = w2
+    m, P = grid.m, grid.P
+    tot = 0.0
+    for p in range(P):
+        sb = sol.sb[p]
+        S = [sol.resid[p * m + y] for y in range(m)]
+        for x in range(m):
+            lam = adj.lam[p * m + x]
+            f1 = -dE1[x] * sb[0] + sum(dW1[x, y] * S[y][0] for y in range(m))
+            f2 = -dE2[x] * sb[1] + sum(dW2[x, y] * S[y][1] for y in range(m))
+            tot += _inner(lam, (f1, f2))
+        an = adj.a[p + 1]
+        fe1 = -dEe1 * sb[0] + sum(dWe1[y] * S[y][0] for y in range(m))
+        fe2 = -dEe2 * sb[1] + sum(dWe2[y] * S[y][1] for y in range(m))
+        tot += _inner(an, (fe1, fe2))
+    return tot / P
+
+
+def d_omega_dh(model, grid, sol, adj):
+    """dOmega/dh_pq (matrix) at frozen reference: n_p delta_pq + one-body response density."""
+    m, P = grid.m, grid.P
+    out = model.dmf_dh()
+    for k, s in enumerate(sol.nodes):
+        x = k % m
+        out = out + model.vjp_fock(s, grid.b[x] / P, adj.lamt[k])
+    return out
