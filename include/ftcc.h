@@ -1,0 +1,145 @@
+/* FT-CCSD hot path on one AMD Instinct MI355X (gfx950): C ABI.
+ *
+ * Finite-temperature coupled cluster singles and doubles in the formulation of
+ * White and Chan (2020): the grand potential
+ *     Omega = Omega_0 + Omega_1 + Omega_CC,  Omega_CC = (1/beta) int_0^beta E[s(tau)] dtau   (eqn:Ecc)
+ * with amplitudes s(tau) from the imaginary-time integral equation
+ *     s_mu(tau) = -int_0^tau exp(Delta_mu (tau' - tau)) S_mu[s(tau')] dtau'                  (eqn:smu)
+ * on thermal integrals scaled by sqrt(n_p) and sqrt(1 - n_p) (Section II.A,
+ * Appendix A), the Lambda adjoint of the Lagrangian (eqn:Lagrangian, eqn:lmu,
+ * eqn:ltilde) and the response derivatives of Section II.D / Appendix B.
+ *
+ * Discretisation (Section II.C leaves G open for Gauss-Legendre nodes): [0, beta]
+ * is cut into n_tau / nodes_per_panel panels of m = nodes_per_panel Gauss-Legendre
+ * nodes; inside a panel the integral equation is collocated at the nodes with
+ * the source interpolated by the degree-(m-1) Lagrange polynomial and the
+ * exponential integrated exactly (propagator 0), or with the whole integrand
+ * interpolated (propagator 1, the paper's G^y_x exp(Delta (tau_x - tau_y))).
+ * The implicit panel system is solved by fixed-point (Picard) sweeps.
+ *
+ * The reference is spin-restricted: h, <pq|rs> and eps are spatial, amplitudes
+ * are closed-shell t1[i][a] = s_{i alpha}^{a alpha} and
+ * t2[i][j][a][b] = s_{i alpha, j beta}^{a alpha, b beta}.
+ *
+ * Conventions of every entry point
+ *   - return 0 on success, a negative FTCC_E* code on failure; the message of
+ *     the last failure on the calling thread is ftcc_last_error();
+ *   - pointer arguments are HOST memory owned by the caller, read or written
+ *     only during the call; the library keeps its own device copies;
+ *   - a context owns all device memory it allocates and frees it in ftcc_destroy;
+ *   - one context must not be used by two threads at once;
+ *   - required order: create -> set_hamiltonian (every instance) ->
+ *     solve_amplitudes -> grand_potential -> lambda -> response.
+ *     set_hamiltonian invalidates amplitudes and Lambda.
+ *   - a GPU that is missing or not gfx950 is an error (FTCC_EDEVICE); there is
+ *     no CPU fallback.
+ */
+#ifndef FTCC_H
+#define FTCC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FTCC_ABI_VERSION 1
+
+#define FTCC_OK 0
+#define FTCC_EINVAL -1      /* bad argument */
+#define FTCC_ESTATE -2      /* wrong call order */
+#define FTCC_ENOMEM -3      /* device allocation failed */
+#define FTCC_EDEVICE -4     /* HIP runtime error or unsupported device */
+#define FTCC_ENOCONV -5     /* an instance hit max_iter (per-instance status) */
+#define FTCC_ENONFINITE -6  /* NaN or Inf in the amplitudes (per-instance status) */
+
+typedef struct ftcc_ctx ftcc_ctx;
+
+typedef struct {
+  int n_tau;            /* total imaginary-time nodes n_g (multiple of nodes_per_panel) */
+  int nodes_per_panel;  /* m, 1..6 */
+  int propagator;       /* 0: exponential collocation, 1: integrating factor (Lawson) */
+  double occ_thresh;    /* Section III.A: hole slot kept if n_p > thr, particle slot if 1 - n_p > thr */
+  double tol;           /* Picard stop: max|change| <= tol * max(1, max|s|) over the panel */
+  int max_iter;         /* Picard sweeps per panel */
+  int checkpoint;       /* 0: keep every node; 1: keep panel-start states only and
+                           recompute each panel in the adjoint (HBM checkpointing) */
+} ftcc_options;
+
+/* Defaults: n_tau 16, m 4, propagator 0, thr 0, tol 1e-12, max_iter 200, checkpoint 0. */
+void ftcc_default_options(ftcc_options* opt);
+
+/* Create a context for n_instances independent (Hamiltonian, mu, beta) problems
+ * on HIP device `device`.  opt may be NULL (defaults).  All instances share the
+ * options and are advanced together (one grouped launch per step). */
+int ftcc_create(ftcc_ctx** ctx, int device, int n_instances, const ftcc_options* opt);
+int ftcc_destroy(ftcc_ctx* ctx);
+
+/* Run all device work on this hipStream_t (NULL: the context's own stream).
+ * The stream must stay valid until it is replaced or the context destroyed. */
+int ftcc_set_stream(ftcc_ctx* ctx, void* hip_stream);
+
+/* Instance `inst` (0 <= inst < n_instances) with n spatial orbitals:
+ *   h    n*n row-major one-body matrix (reference orbital basis)
+ *   eri  n^4 row-major <pq|rs> = int phi_p*(1) phi_q*(2) r12^-1 phi_r(1) phi_s(2);
+ *        real, with <pq|rs> = <qp|sr> (plane waves and Bloch waves need not
+ *        satisfy the real-orbital symmetry <pq|rs> = <rq|ps>)
+ *   eps  n reference orbital energies (H_0 = sum_p eps_p a_p^+ a_p, Section II.B)
+ * All instances of one context must have the same n in this version. */
+int ftcc_set_hamiltonian(ftcc_ctx* ctx, int inst, int n, const double* h, const double* eri, const double* eps);
+
+/* Thermal integrals for (mu[i], beta[i]) and the forward imaginary-time march
+ * (Algorithm alg:int in panels).  iters_out[i]: total Picard sweeps of instance
+ * i; status_out[i]: 0, FTCC_ENOCONV or FTCC_ENONFINITE.  Either output may be
+ * NULL.  Returns FTCC_ENOCONV / FTCC_ENONFINITE if any instance failed. */
+int ftcc_solve_amplitudes(ftcc_ctx* ctx, const double* mu, const double* beta, int* iters_out, int* status_out);
+
+/* omega[i] = Omega; parts (optional, [n_instances][3]) = Omega_0, Omega_1, Omega_CC. */
+int ftcc_grand_potential(ftcc_ctx* ctx, double* omega, double* parts);
+
+/* Converged amplitudes of node k (0 <= k < n_tau) of one instance: t1 n*n, t2 n^4.
+ * Needs checkpoint == 0. */
+int ftcc_get_amplitudes(ftcc_ctx* ctx, int inst, int node, double* t1, double* t2);
+
+/* The Lambda adjoint, swept backward in tau panel by panel (stationarity of the
+ * discrete Lagrangian; lambda_x = -L[s(tau_x), lambda-tilde(tau_x)] with
+ * lambda-tilde the discrete eqn:ltilde).  Same output conventions as solve. */
+int ftcc_lambda(ftcc_ctx* ctx, int* iters_out, int* status_out);
+
+/* Lambda and lambda-tilde of node k of one instance (n*n then n^4 each). */
+int ftcc_get_lambda(ftcc_ctx* ctx, int inst, int node, double* lam1, double* lam2, double* lamt1, double* lamt2);
+
+/* Derivatives of Omega at a frozen reference (orbitals, eps and the dropped
+ * slots fixed; Section II.D types 1, 2, 4, 5, 6 for this discretisation):
+ *   dO_dmu[i], dO_dbeta[i]   (either may be NULL)
+ *   dO_dh                    [n_instances][n*n] dOmega/dh_pq, or NULL
+ *   deri_dtheta, dh_dtheta   optional direction of a scalar parameter theta per
+ *                            instance (arrays of n_instances host pointers to n^4
+ *                            and n*n arrays; an entry may be NULL), e.g.
+ *                            deri = eri / U for theta = U; result in dO_dtheta[i]. */
+int ftcc_response(ftcc_ctx* ctx, double* dO_dmu, double* dO_dbeta, double* dO_dh,
+                  const double* const* deri_dtheta, const double* const* dh_dtheta, double* dO_dtheta);
+
+/* One evaluation of the kernels E, S1, S2 (eqn:E, eqn:ccS1, eqn:ccS2) of instance
+ * `inst` at the given amplitudes and the thermal integrals of (mu, beta):
+ * t1, S1 n*n; t2, S2 n^4; E scalar. */
+int ftcc_eval_residual(ftcc_ctx* ctx, int inst, double mu, double beta, const double* t1, const double* t2,
+                       double* S1, double* S2, double* E);
+
+/* Timing of the kernels alone: evaluate S for every node slot of every
+ * instance `reps` times at the amplitudes currently in the slots (after
+ * ftcc_eval_residual or a solve) on device-resident data, between HIP events.
+ * seconds_out: elapsed seconds; flops_out: algorithmic GEMM flops per sweep
+ * (all slots).  Either may be NULL. */
+int ftcc_time_residual(ftcc_ctx* ctx, int reps, double* seconds_out, double* flops_out);
+
+/* Counters of the last solve / lambda: residual evaluations (instance x node),
+ * backward evaluations, and device seconds spent in each phase. */
+int ftcc_stats(ftcc_ctx* ctx, long* resid_evals, long* vjp_evals, double* solve_seconds, double* lambda_seconds);
+
+const char* ftcc_last_error(void);
+int ftcc_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTCC_H */

@@ -1,0 +1,151 @@
+// A small tensor-program engine for the FT-CCSD residual.
+//
+// A Program is a list of tensor contractions written with index letters
+//     out[oi] (+)= alpha * A[ai] * B[bi]      (einsum semantics, one or two operands)
+// over tensors whose every axis has length n (hole and particle slots both run
+// over all orbitals at finite temperature).  An Executor binds the symbolic
+// tensors of one Program to device buffers for a list of problems (one
+// instance and one imaginary-time node each) and lowers every op once into
+// grouped kernel launches: LDS-tiled index permutes, FP64-MFMA GEMMs (split-K
+// when M*N is small) and dot reductions.  The launch lists are replayed on
+// every sweep.
+//
+// Reverse mode: every op is linear in each operand, so its vector-Jacobian
+// product is a contraction of the same form,
+//     dA[ai] += alpha * dOut[oi] * B[bi],   dB[bi] += alpha * A[ai] * dOut[oi],
+// and the backward launch list is the forward program reversed.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+namespace ftcc {
+
+enum TensorKind { T_INPUT = 0, T_CONST = 1, T_INTER = 2, T_OUTPUT = 3 };
+
+struct TensorDecl {
+  std::string name;
+  int rank;
+  TensorKind kind;
+  bool derived = false;   // computed from constants only (set-up ops)
+};
+
+struct SymOp {
+  int out;
+  std::string oi;
+  double alpha;
+  int a;
+  std::string ai;
+  int b;  // -1: single operand
+  std::string bi;
+  bool accumulate;
+  bool setup;
+};
+
+class Program {
+ public:
+  int tensor(const std::string& name, int rank, TensorKind kind);
+  int id(const std::string& name) const;
+  // out[oi] (+)= alpha * A[ai] (* B[bi]); the first op on `out` must have acc = false
+  void op(const std::string& out, const std::string& oi, double alpha, const std::string& a,
+          const std::string& ai, const std::string& b, const std::string& bi, bool acc);
+  void set(const std::string& out, const std::string& oi, double alpha, const std::string& a,
+           const std::string& ai, const std::string& b = "", const std::string& bi = "") {
+    op(out, oi, alpha, a, ai, b, bi, false);
+  }
+  void add(const std::string& out, const std::string& oi, double alpha, const std::string& a,
+           const std::string& ai, const std::string& b = "", const std::string& bi = "") {
+    op(out, oi, alpha, a, ai, b, bi, true);
+  }
+  void finalize();
+  bool finalized() const { return finalized_; }
+  std::vector<TensorDecl> t;
+  std::vector<SymOp> ops;
+
+ private:
+  bool finalized_ = false;
+};
+
+// The spin-restricted FT-CCSD kernels E, S1, S2 as a Program.
+Program build_residual_program();
+
+struct Launch {
+  enum Kind { PERM, GEMM, DOT, FILL } kind = PERM;
+  int n_prob = 0;
+  int total = 0;
+  int cfg = 0;
+  bool ta = false, tb = false;
+  int splitk_blocks = 0;
+  int dot_blocks = 0;
+  void* d_desc = nullptr;
+  int* d_prefix = nullptr;
+  int* d_prefix2 = nullptr;
+  double* d_partial = nullptr;
+  double flops = 0.0;
+  std::string tag;
+};
+
+struct ProblemRef {
+  int inst;
+  int node;
+  int n;
+};
+
+// (tensor id, problem index, gradient buffer?) -> device pointer
+using Binder = std::function<double*(int tensor, int prob, bool grad)>;
+
+struct Scratch {
+  std::vector<double*> a, b, c, part;   // per problem: n^4 doubles each
+  double* dot_partial = nullptr;        // >= n_prob * 64 doubles
+};
+
+class Executor {
+ public:
+  Executor() = default;
+  ~Executor();
+  Executor(const Executor&) = delete;
+  Executor& operator=(const Executor&) = delete;
+
+  // const_alloc(inst, count) returns a persistent per-instance buffer for a
+  // permuted copy of a constant.  const_grads lists constants whose gradients
+  // the backward list must produce.
+  void build(const Program* prog, const std::vector<ProblemRef>& probs, Binder bind, Scratch* scratch,
+             std::function<double*(int inst, size_t count)> const_alloc, bool want_backward,
+             const std::vector<int>& const_grads);
+
+  void run_setup(hipStream_t s) const { run(setup_, s); }
+  void run_forward(hipStream_t s) const { run(fwd_, s); }
+  void run_backward(hipStream_t s) const { run(bwd_, s); }
+
+  double gemm_flops_forward() const;
+  double gemm_flops_backward() const;
+  int n_launches_forward() const { return (int)fwd_.size(); }
+
+ private:
+  using PerProb = std::vector<double*>;
+  void run(const std::vector<Launch>& L, hipStream_t s) const;
+  void contract(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
+                const PerProb& A, const std::string& ai, int a_const, const PerProb* B, const std::string& bi,
+                int b_const, bool acc, const std::string& tag);
+  void perm(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
+            const std::string& yi, double alpha, double beta, const std::vector<const double*>* scale,
+            const std::string& tag);
+  void fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag);
+  PerProb const_permuted(int tensor, const PerProb& X, const std::string& xi, const std::string& yi);
+  void* upload(const void* host, size_t bytes);
+
+  const Program* prog_ = nullptr;
+  std::vector<ProblemRef> probs_;
+  Scratch* scratch_ = nullptr;
+  std::function<double*(int, size_t)> const_alloc_;
+  std::map<std::pair<int, std::string>, PerProb> const_cache_;
+  std::vector<Launch> setup_, fwd_, bwd_;
+  std::vector<void*> owned_;
+};
+
+}  // namespace ftcc

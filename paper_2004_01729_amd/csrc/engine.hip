@@ -1,0 +1,541 @@
+// Tensor-program engine: lowering of contractions to grouped kernel launches.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+#include "util.h"
+
+namespace ftcc {
+
+// ------------------------------------------------------------------ Program
+int Program::tensor(const std::string& name, int rank, TensorKind kind) {
+  for (size_t i = 0; i < t.size(); ++i)
+    if (t[i].name == name) throw std::runtime_error("duplicate tensor " + name);
+  t.push_back({name, rank, kind, false});
+  return (int)t.size() - 1;
+}
+
+int Program::id(const std::string& name) const {
+  for (size_t i = 0; i < t.size(); ++i)
+    if (t[i].name == name) return (int)i;
+  throw std::runtime_error("unknown tensor " + name);
+}
+
+void Program::op(const std::string& out, const std::string& oi, double alpha, const std::string& a,
+                 const std::string& ai, const std::string& b, const std::string& bi, bool acc) {
+  SymOp o;
+  o.out = id(out);
+  o.oi = oi;
+  o.alpha = alpha;
+  o.a = id(a);
+  o.ai = ai;
+  o.b = b.empty() ? -1 : id(b);
+  o.bi = bi;
+  o.accumulate = acc;
+  if ((int)oi.size() != t[o.out].rank || (int)ai.size() != t[o.a].rank ||
+      (o.b >= 0 && (int)bi.size() != t[o.b].rank))
+    throw std::runtime_error("rank mismatch in op on " + out);
+  o.setup = false;
+  ops.push_back(o);
+}
+
+// An intermediate is derived (a constant combination) when every op writing it
+// reads only constants or derived tensors; those ops form the set-up list.
+void Program::finalize() {
+  for (auto& d : t) d.derived = false;
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    for (size_t k = 0; k < t.size(); ++k) {
+      if (t[k].kind != T_INTER || t[k].derived) continue;
+      bool any = false, all_const = true;
+      for (const SymOp& o : ops) {
+        if (o.out != (int)k) continue;
+        any = true;
+        auto c = [&](int x) { return x < 0 || t[x].kind == T_CONST || t[x].derived; };
+        if (!c(o.a) || !c(o.b)) all_const = false;
+      }
+      if (any && all_const) {
+        t[k].derived = true;
+        changed = true;
+      }
+    }
+  }
+  for (SymOp& o : ops) o.setup = t[o.out].derived;
+  finalized_ = true;
+}
+
+// ------------------------------------------------------------------ helpers
+static long ipow(long n, int r) {
+  long v = 1;
+  for (int k = 0; k < r; ++k) v *= n;
+  return v;
+}
+
+static bool has(const std::string& s, char c) { return s.find(c) != std::string::npos; }
+
+static std::string filter(const std::string& src, const std::string& a, const std::string& b, bool in_a,
+                          bool in_b) {
+  std::string out;
+  for (char c : src)
+    if (has(a, c) == in_a && has(b, c) == in_b) out.push_back(c);
+  return out;
+}
+
+Executor::~Executor() {
+  for (void* p : owned_) (void)hipFree(p);
+}
+
+void* Executor::upload(const void* host, size_t bytes) {
+  void* d = nullptr;
+  FTCC_HIP(hipMalloc(&d, bytes > 0 ? bytes : 8));
+  if (bytes) FTCC_HIP(hipMemcpy(d, host, bytes, hipMemcpyHostToDevice));
+  owned_.push_back(d);
+  return d;
+}
+
+// ------------------------------------------------------------------ lowering: permute / fill
+void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
+                    const std::string& yi, double alpha, double beta, const std::vector<const double*>* scale,
+                    const std::string& tag) {
+  const int np = (int)probs_.size();
+  const int r = (int)yi.size();
+  if ((int)xi.size() != r) throw std::runtime_error("permute rank mismatch " + xi + "->" + yi);
+  std::vector<PermProblem> ps(np);
+  std::vector<int> prefix(np);
+  int total = 0;
+  for (int p = 0; p < np; ++p) {
+    const long n = probs_[p].n;
+    PermProblem& q = ps[p];
+    q.X = X[p];
+    q.Y = Y[p];
+    q.scale = scale ? (*scale)[p] : nullptr;
+    q.alpha = alpha;
+    q.beta = beta;
+    // Y axes padded on the left to 4; X strides of each Y axis
+    for (int k = 0; k < 4; ++k) {
+      q.d[k] = 1;
+      q.xs[k] = 0;
+    }
+    for (int k = 0; k < r; ++k) {
+      const int ya = 4 - r + k;
+      const size_t pos = xi.find(yi[k]);
+      if (pos == std::string::npos) throw std::runtime_error("permute letter mismatch " + xi + "->" + yi);
+      q.d[ya] = (int)n;
+      q.xs[ya] = ipow(n, r - 1 - (int)pos);
+    }
+    q.tb = -1;
+    if (q.xs[3] != 1 && q.d[3] > 1) {
+      for (int k = 0; k < 3; ++k)
+        if (q.xs[k] == 1 && q.d[k] > 1) q.tb = k;
+    }
+    prefix[p] = total;
+    if (q.tb < 0) {
+      const long el = (long)q.d[0] * q.d[1] * q.d[2] * q.d[3];
+      total += (int)((el + 1023) / 1024);
+    } else {
+      int oth[2], c = 0;
+      for (int k = 0; k < 3; ++k)
+        if (k != q.tb) oth[c++] = k;
+      total += ((q.d[3] + 31) / 32) * ((q.d[q.tb] + 31) / 32) * q.d[oth[0]] * q.d[oth[1]];
+    }
+  }
+  Launch L;
+  L.kind = Launch::PERM;
+  L.n_prob = np;
+  L.total = total;
+  L.d_desc = upload(ps.data(), sizeof(PermProblem) * np);
+  L.d_prefix = (int*)upload(prefix.data(), sizeof(int) * np);
+  L.tag = tag;
+  dst.push_back(L);
+}
+
+void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag) {
+  // zero fill: the contiguous permute path with alpha = 0 and beta = 0 reads neither X nor Y
+  const int np = (int)probs_.size();
+  std::vector<PermProblem> ps(np);
+  std::vector<int> prefix(np);
+  int total = 0;
+  for (int p = 0; p < np; ++p) {
+    const long n = probs_[p].n;
+    PermProblem& q = ps[p];
+    std::memset(&q, 0, sizeof(q));
+    q.X = Y[p];
+    q.Y = Y[p];
+    q.d[0] = 1;
+    q.d[1] = 1;
+    q.d[2] = 1;
+    q.d[3] = (int)ipow(n, rank);
+    q.xs[3] = 1;
+    q.tb = -1;
+    q.alpha = 0.0;
+    q.beta = 0.0;
+    prefix[p] = total;
+    total += (int)((q.d[3] + 1023) / 1024);
+  }
+  Launch L;
+  L.kind = Launch::FILL;
+  L.n_prob = np;
+  L.total = total;
+  L.d_desc = upload(ps.data(), sizeof(PermProblem) * np);
+  L.d_prefix = (int*)upload(prefix.data(), sizeof(int) * np);
+  L.tag = tag;
+  dst.push_back(L);
+}
+
+Executor::PerProb Executor::const_permuted(int tensor, const PerProb& X, const std::string& xi,
+                                           const std::string& yi) {
+  // canonical key: the permutation as positions
+  std::string key;
+  for (char c : yi) key.push_back((char)('0' + xi.find(c)));
+  auto k = std::make_pair(tensor, key);
+  auto it = const_cache_.find(k);
+  if (it != const_cache_.end()) return it->second;
+  const int np = (int)probs_.size();
+  PerProb Y(np);
+  std::map<int, double*> per_inst;
+  for (int p = 0; p < np; ++p) {
+    const int inst = probs_[p].inst;
+    if (!per_inst.count(inst)) per_inst[inst] = const_alloc_(inst, (size_t)ipow(probs_[p].n, (int)xi.size()));
+    Y[p] = per_inst[inst];
+  }
+  // one permute per instance: restrict to the first problem of each instance
+  std::vector<ProblemRef> saved = probs_;
+  std::vector<ProblemRef> firsts;
+  PerProb Xf, Yf;
+  std::map<int, bool> seen;
+  for (int p = 0; p < np; ++p) {
+    if (seen[probs_[p].inst]) continue;
+    seen[probs_[p].inst] = true;
+    firsts.push_back(probs_[p]);
+    Xf.push_back(X[p]);
+    Yf.push_back(Y[p]);
+  }
+  probs_ = firsts;
+  perm(setup_, Xf, xi, Yf, yi, 1.0, 0.0, nullptr, "const-permute");
+  probs_ = saved;
+  const_cache_[k] = Y;
+  return Y;
+}
+
+// ------------------------------------------------------------------ lowering: contraction
+void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
+                        const PerProb& A, const std::string& ai, int a_const, const PerProb* B,
+                        const std::string& bi, int b_const, bool acc, const std::string& tag) {
+  const double beta = acc ? 1.0 : 0.0;
+  const int np = (int)probs_.size();
+  if (!B) {
+    for (char c : ai)
+      if (!has(oi, c)) throw std::runtime_error("single-operand reduction unsupported: " + tag);
+    perm(dst, A, ai, out, oi, alpha, beta, nullptr, tag);
+    return;
+  }
+  // scalar operand: scaled permute with a device scalar
+  if (ai.empty() || bi.empty()) {
+    const PerProb& S = ai.empty() ? A : *B;
+    const PerProb& X = ai.empty() ? *B : A;
+    const std::string& xi = ai.empty() ? bi : ai;
+    std::vector<const double*> sc(S.begin(), S.end());
+    perm(dst, X, xi, out, oi, alpha, beta, &sc, tag);
+    return;
+  }
+  for (char c : ai)
+    if (!has(bi, c) && !has(oi, c)) throw std::runtime_error("letter summed in one operand only: " + tag);
+  for (char c : bi)
+    if (!has(ai, c) && !has(oi, c)) throw std::runtime_error("letter summed in one operand only: " + tag);
+  for (char c : oi)
+    if (has(ai, c) && has(bi, c)) throw std::runtime_error("batch letters unsupported: " + tag);
+
+  // full contraction -> dot
+  if (oi.empty()) {
+    PerProb Bp = *B;
+    if (bi != ai) {
+      if (b_const >= 0) Bp = const_permuted(b_const, *B, bi, ai);
+      else {
+        perm(dst, *B, bi, scratch_->b, ai, 1.0, 0.0, nullptr, tag + ":permB");
+        Bp = scratch_->b;
+      }
+    }
+    std::vector<DotProblem> ds(np);
+    for (int p = 0; p < np; ++p) {
+      ds[p].X = A[p];
+      ds[p].Y = Bp[p];
+      ds[p].out = out[p];
+      ds[p].len = ipow(probs_[p].n, (int)ai.size());
+      ds[p].alpha = alpha;
+      ds[p].beta = beta;
+    }
+    Launch L;
+    L.kind = Launch::DOT;
+    L.n_prob = np;
+    L.dot_blocks = 64;
+    L.d_desc = upload(ds.data(), sizeof(DotProblem) * np);
+    L.d_partial = scratch_->dot_partial;
+    L.tag = tag;
+    dst.push_back(L);
+    return;
+  }
+
+  const std::string M_a = filter(ai, bi, oi, false, true);   // in A and out only
+  const std::string K_a = filter(ai, bi, oi, true, false);   // in A and B only
+  const std::string N_b = filter(bi, ai, oi, false, true);
+  const std::string K_b = filter(bi, ai, oi, true, false);
+  const std::string M_o = filter(oi, ai, bi, true, false);
+  const std::string N_o = filter(oi, bi, ai, true, false);
+
+  struct Choice {
+    std::string M, N, K;
+    bool swap;
+    double cost;
+  };
+  Choice best{"", "", "", false, 1e300};
+  const long n0 = probs_[0].n;
+  auto sz = [&](const std::string& s) { return (double)ipow(n0, (int)s.size()); };
+  for (int im = 0; im < 2; ++im)
+    for (int in = 0; in < 2; ++in)
+      for (int ik = 0; ik < 2; ++ik) {
+        std::string M = im ? M_o : M_a, N = in ? N_o : N_b, K = ik ? K_b : K_a;
+        double cost = 0.0;
+        const bool a_ok = (ai == M + K) || (ai == K + M);
+        const bool b_ok = (bi == K + N) || (bi == N + K);
+        if (!a_ok && a_const < 0) cost += sz(ai);
+        if (!b_ok && b_const < 0) cost += sz(bi);
+        bool swap = false;
+        if (oi == M + N) {
+        } else if (oi == N + M) {
+          swap = true;
+        } else {
+          cost += 2.0 * sz(oi);
+        }
+        if (cost < best.cost) best = {M, N, K, swap, cost};
+      }
+
+  // operands in GEMM layout
+  auto place = [&](const PerProb& X, const std::string& xi, int xconst, const std::string& first,
+                   const std::string& second, PerProb& scratch, bool& trans, std::string& lay) -> PerProb {
+    if (xi == first + second) {
+      trans = false;
+      lay = xi;
+      return X;
+    }
+    if (xi == second + first) {
+      trans = true;
+      lay = xi;
+      return X;
+    }
+    trans = false;
+    lay = first + second;
+    if (xconst >= 0) return const_permuted(xconst, X, xi, lay);
+    perm(dst, X, xi, scratch, lay, 1.0, 0.0, nullptr, tag + ":perm");
+    return scratch;
+  };
+  // C[M][N] = A[M][K] B[K][N]; with swap, C^T[N][M] = B^T[N][K] A^T[K][M]
+  std::string M = best.M, N = best.N, K = best.K;
+  PerProb Ap, Bp;
+  bool ta = false, tb = false;
+  std::string alay, blay;
+  if (!best.swap) {
+    Ap = place(A, ai, a_const, M, K, scratch_->a, ta, alay);     // ta: stored [K][M]
+    Bp = place(*B, bi, b_const, K, N, scratch_->b, tb, blay);    // tb: stored [N][K]
+  } else {
+    // rows of C = N letters (from B), cols = M letters (from A)
+    Ap = place(*B, bi, b_const, N, K, scratch_->b, ta, alay);
+    Bp = place(A, ai, a_const, K, M, scratch_->a, tb, blay);
+    std::swap(M, N);
+  }
+  const bool c_direct = (oi == M + N);
+  const double galpha = alpha;
+  const double gbeta = c_direct ? beta : 0.0;
+  const PerProb& Cp = c_direct ? out : scratch_->c;
+
+  std::vector<GemmProblem> gs(np);
+  std::vector<int> prefix(np), prefix2(np);
+  int cfg = 0;
+  {
+    const long m = ipow(n0, (int)M.size()), nn = ipow(n0, (int)N.size());
+    cfg = (m >= 128 && nn >= 128) ? 0 : 1;
+  }
+  const int BM = gemm_bm(cfg), BN = gemm_bn(cfg);
+  int total = 0, total2 = 0;
+  bool any_split = false;
+  double flops = 0.0;
+  // split-K when the grouped launch would not fill the device
+  long tiles_all = 0;
+  for (int p = 0; p < np; ++p) {
+    const long n = probs_[p].n;
+    tiles_all += ((ipow(n, (int)M.size()) + BM - 1) / BM) * ((ipow(n, (int)N.size()) + BN - 1) / BN);
+  }
+  for (int p = 0; p < np; ++p) {
+    const long n = probs_[p].n;
+    GemmProblem& g = gs[p];
+    g.M = (int)ipow(n, (int)M.size());
+    g.N = (int)ipow(n, (int)N.size());
+    g.K = (int)ipow(n, (int)K.size());
+    g.A = Ap[p];
+    g.B = Bp[p];
+    g.C = Cp[p];
+    g.lda = ta ? g.M : g.K;
+    g.ldb = tb ? g.K : g.N;
+    g.ldc = g.N;
+    g.alpha = galpha;
+    g.beta = gbeta;
+    g.tiles_m = (g.M + BM - 1) / BM;
+    g.tiles_n = (g.N + BN - 1) / BN;
+    int ks = 1;
+    if (tiles_all < 512 && g.K >= 512) {
+      ks = (int)std::min<long>((512 + tiles_all - 1) / tiles_all, g.K / 256);
+      // the partial buffer holds n^4 doubles
+      while (ks > 1 && (long)ks * g.M * g.N > ipow(n, 4)) --ks;
+      ks = std::max(ks, 1);
+    }
+    g.ksplit = ks;
+    g.kchunk = (g.K + ks - 1) / ks;
+    g.kchunk = ((g.kchunk + 15) / 16) * 16;
+    g.ksplit = (g.K + g.kchunk - 1) / g.kchunk;
+    g.partial = scratch_->part[p];
+    if (g.ksplit > 1) any_split = true;
+    prefix[p] = total;
+    total += g.tiles_m * g.tiles_n * g.ksplit;
+    prefix2[p] = total2;
+    total2 += (int)(((long)g.M * g.N + 1023) / 1024);
+    flops += 2.0 * g.M * (double)g.N * g.K;
+  }
+  Launch L;
+  L.kind = Launch::GEMM;
+  L.n_prob = np;
+  L.total = total;
+  L.cfg = cfg;
+  L.ta = ta;
+  L.tb = tb;
+  L.d_desc = upload(gs.data(), sizeof(GemmProblem) * np);
+  L.d_prefix = (int*)upload(prefix.data(), sizeof(int) * np);
+  if (any_split) {
+    // problems without a split still need their own reduce pass skipped: mark via ksplit
+    L.splitk_blocks = total2;
+    L.d_prefix2 = (int*)upload(prefix2.data(), sizeof(int) * np);
+  }
+  L.flops = flops;
+  L.tag = tag;
+  dst.push_back(L);
+  if (!c_direct) perm(dst, scratch_->c, M + N, out, oi, 1.0, beta, nullptr, tag + ":permC");
+}
+
+// ------------------------------------------------------------------ build
+void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, Binder bind, Scratch* scratch,
+                     std::function<double*(int, size_t)> const_alloc, bool want_backward,
+                     const std::vector<int>& const_grads) {
+  if (!prog->finalized()) throw std::runtime_error("Program::finalize() not called");
+  prog_ = prog;
+  probs_ = probs;
+  scratch_ = scratch;
+  const_alloc_ = const_alloc;
+  const int np = (int)probs.size();
+  const int nt = (int)prog->t.size();
+  std::vector<PerProb> fwd(nt, PerProb(np)), grd(nt, PerProb(np));
+  std::vector<bool> need_grad(nt, false);
+  for (int k = 0; k < nt; ++k) {
+    const TensorDecl& d = prog->t[k];
+    for (int p = 0; p < np; ++p) fwd[k][p] = bind(k, p, false);
+    bool g = (d.kind == T_INPUT || d.kind == T_OUTPUT || (d.kind == T_INTER && !d.derived));
+    if (std::find(const_grads.begin(), const_grads.end(), k) != const_grads.end()) g = true;
+    need_grad[k] = g && want_backward;
+    if (need_grad[k])
+      for (int p = 0; p < np; ++p) grd[k][p] = bind(k, p, true);
+  }
+  auto cidx = [&](int k) { return (k >= 0 && (prog->t[k].kind == T_CONST || prog->t[k].derived)) ? k : -1; };
+  // set-up ops first (constants only), once per instance
+  {
+    std::vector<ProblemRef> firsts;
+    std::vector<int> idx;
+    std::vector<bool> seen_inst;
+    for (int p = 0; p < np; ++p) {
+      const int inst = probs[p].inst;
+      if (inst >= (int)seen_inst.size()) seen_inst.resize(inst + 1, false);
+      if (seen_inst[inst]) continue;
+      seen_inst[inst] = true;
+      firsts.push_back(probs[p]);
+      idx.push_back(p);
+    }
+    auto sub = [&](const PerProb& v) {
+      PerProb r;
+      for (int p : idx) r.push_back(v[p]);
+      return r;
+    };
+    Scratch firsts_scratch;
+    firsts_scratch.a = sub(scratch->a);
+    firsts_scratch.b = sub(scratch->b);
+    firsts_scratch.c = sub(scratch->c);
+    firsts_scratch.part = sub(scratch->part);
+    firsts_scratch.dot_partial = scratch->dot_partial;
+    probs_ = firsts;
+    scratch_ = &firsts_scratch;
+    for (const SymOp& o : prog->ops) {
+      if (!o.setup) continue;
+      PerProb ob;
+      if (o.b >= 0) ob = sub(fwd[o.b]);
+      contract(setup_, sub(fwd[o.out]), o.oi, o.alpha, sub(fwd[o.a]), o.ai, -1, o.b >= 0 ? &ob : nullptr, o.bi,
+               -1, o.accumulate, "setup:" + prog->t[o.out].name);
+    }
+    probs_ = probs;
+    scratch_ = scratch;
+  }
+  for (const SymOp& o : prog->ops) {
+    if (o.setup) continue;
+    contract(fwd_, fwd[o.out], o.oi, o.alpha, fwd[o.a], o.ai, cidx(o.a), o.b >= 0 ? &fwd[o.b] : nullptr, o.bi,
+             cidx(o.b), o.accumulate, prog->t[o.out].name);
+  }
+  if (!want_backward) return;
+  // zero every gradient buffer except the cotangents of the outputs
+  for (int k = 0; k < nt; ++k)
+    if (need_grad[k] && prog->t[k].kind != T_OUTPUT) fill(bwd_, grd[k], prog->t[k].rank, "zero:" + prog->t[k].name);
+  for (int i = (int)prog->ops.size() - 1; i >= 0; --i) {
+    const SymOp& o = prog->ops[i];
+    if (o.setup) continue;
+    const std::string tag = "bwd:" + prog->t[o.out].name;
+    if (o.b < 0) {
+      if (need_grad[o.a]) contract(bwd_, grd[o.a], o.ai, o.alpha, grd[o.out], o.oi, -1, nullptr, "", -1, true, tag);
+      continue;
+    }
+    if (need_grad[o.a])
+      contract(bwd_, grd[o.a], o.ai, o.alpha, grd[o.out], o.oi, -1, &fwd[o.b], o.bi, cidx(o.b), true, tag + ":dA");
+    if (need_grad[o.b])
+      contract(bwd_, grd[o.b], o.bi, o.alpha, fwd[o.a], o.ai, cidx(o.a), &grd[o.out], o.oi, -1, true, tag + ":dB");
+  }
+}
+
+// ------------------------------------------------------------------ run
+void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
+  for (const Launch& l : L) {
+    switch (l.kind) {
+      case Launch::PERM:
+      case Launch::FILL:
+        launch_permute((const PermProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
+        break;
+      case Launch::GEMM:
+        launch_gemm(l.cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
+        if (l.splitk_blocks > 0)
+          launch_splitk_reduce((const GemmProblem*)l.d_desc, l.d_prefix2, l.n_prob, l.splitk_blocks, s);
+        break;
+      case Launch::DOT:
+        launch_dot((const DotProblem*)l.d_desc, l.n_prob, l.dot_blocks, l.d_partial, s);
+        break;
+    }
+  }
+}
+
+double Executor::gemm_flops_forward() const {
+  double f = 0.0;
+  for (const Launch& l : fwd_) f += l.flops;
+  return f;
+}
+
+double Executor::gemm_flops_backward() const {
+  double f = 0.0;
+  for (const Launch& l : bwd_) f += l.flops;
+  return f;
+}
+
+}  // namespace ftcc

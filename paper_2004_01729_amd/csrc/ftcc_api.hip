@@ -1,0 +1,1194 @@
+// C ABI of the FT-CCSD hot path: context, thermal set-up, forward march,
+// Lambda adjoint and response derivatives.  All arithmetic runs in the HIP
+// kernels of this directory; the host only sequences launches and tests the
+// convergence flags.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <functional>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "ftcc.h"
+#include "kernels.h"
+#include "tau_kernels.h"
+#include "util.h"
+
+using namespace ftcc;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Fail{code, msg}; }
+
+const char* kU[4] = {"u_oo", "u_ov", "u_vo", "u_vv"};
+const char* kG[12] = {"g_oooo", "g_ooov", "g_oovo", "g_oovv", "g_ovov", "g_ovvo",
+                      "g_ovvv", "g_vovv", "g_vvvv", "g_vvvo", "g_ovoo", "g_vvoo"};
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton on P_m)
+void gauss_legendre(int m, double* c, double* b) {
+  for (int i = 0; i < m; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (m + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= m; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pm = (m == 1) ? x : p1;
+      double pm1 = (m == 1) ? 1.0 : p0;
+      double dp = m * (x * pm - pm1) / (x * x - 1.0);
+      double dx = pm / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= m; ++k) {
+      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pm = (m == 1) ? x : p1, pm1 = (m == 1) ? 1.0 : p0;
+    double dp = m * (x * pm - pm1) / (x * x - 1.0);
+    c[m - 1 - i] = 0.5 * (x + 1.0);
+    b[m - 1 - i] = 1.0 / ((1.0 - x * x) * dp * dp);   // 2/((1-x^2)P'^2) on [-1,1], halved
+  }
+}
+
+PanelRule make_rule(int m, int lawson) {
+  PanelRule R;
+  std::memset(&R, 0, sizeof(R));
+  R.m = m;
+  R.lawson = lawson;
+  gauss_legendre(m, R.c, R.b);
+  for (int y = 0; y < m; ++y) {
+    // l_y(u) = prod_{j != y} (u - c_j) / (c_y - c_j) as monomial coefficients
+    double poly[kMaxNodes + 1] = {0};
+    poly[0] = 1.0;
+    int deg = 0;
+    for (int j = 0; j < m; ++j) {
+      if (j == y) continue;
+      const double den = R.c[y] - R.c[j];
+      double nw[kMaxNodes + 1] = {0};
+      for (int k = 0; k <= deg; ++k) {
+        nw[k + 1] += poly[k] / den;
+        nw[k] -= poly[k] * R.c[j] / den;
+      }
+      ++deg;
+      std::memcpy(poly, nw, sizeof(nw));
+    }
+    for (int k = 0; k < m; ++k) R.lc[y][k] = poly[k];
+  }
+  for (int x = 0; x < m; ++x)
+    for (int y = 0; y < m; ++y) {
+      double a = 0.0, p = R.c[x];
+      for (int k = 0; k < m; ++k) {
+        a += R.lc[y][k] * p / (k + 1);
+        p *= R.c[x];
+      }
+      R.A[x][y] = a;
+    }
+  return R;
+}
+
+// ------------------------------------------------------------------ mean-field kernel
+// out[0] Omega_0, out[1] Omega_1, out[2] d(Omega_0+Omega_1)/dmu, out[3] .../dbeta,
+// out[4] dOmega_1/dtheta for the direction (dh, deri) at frozen occupations.
+__global__ void meanfield_kernel(int n, const double* eps, const double* h, const double* eri, const double* occ,
+                                 const double* fock, double mu, double beta, const double* dh, const double* deri,
+                                 double* out) {
+  __shared__ double red[5][256];
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
+  const long nn = (long)n * n;
+  for (long e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int p = (int)(e / n), q = (int)(e % n);
+    const double gd = eri[(((long)p * n + q) * n + p) * n + q];   // <pq|pq>
+    const double gx = eri[(((long)p * n + q) * n + q) * n + p];   // <pq|qp>
+    a1 += (2.0 * gd - gx) * occ[p] * occ[q];
+    if (deri) {
+      const double dd = deri[(((long)p * n + q) * n + p) * n + q];
+      const double dx = deri[(((long)p * n + q) * n + q) * n + p];
+      a4 += (2.0 * dd - dx) * occ[p] * occ[q];
+    }
+  }
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const double x = beta * (eps[p] - mu);
+    const double sp = (x > 0.0) ? log1p(exp(-x)) : (-x + log1p(exp(x)));   // ln(1 + e^-x)
+    const double nocc = occ[p], nvir = 1.0 - occ[p];
+    a0 += sp;
+    a1 += 2.0 * (h[(long)p * n + p] - eps[p]) * nocc;
+    const double fq = fock[(long)p * n + p] - eps[p];
+    const double nn1 = (x > 0.0) ? nocc * (1.0 / (1.0 + exp(-x))) : nocc * (exp(x) / (1.0 + exp(x)));
+    (void)nvir;
+    // d(Omega_0)/dmu = -2 n ; d(Omega_1)/dmu = 2 (f_qq - eps_q) beta n (1-n)
+    a2 += -2.0 * nocc + 2.0 * fq * beta * nn1;
+    // d(Omega_0)/dbeta = -Omega_0/beta + 2 (eps - mu) n / beta ; d(Omega_1)/dbeta = 2 fq (-(eps-mu) n(1-n))
+    a3 += 2.0 * (eps[p] - mu) * nocc / beta - 2.0 * fq * (eps[p] - mu) * nn1;
+    if (dh) a4 += 2.0 * dh[(long)p * n + p] * nocc;
+  }
+  red[0][threadIdx.x] = a0;
+  red[1][threadIdx.x] = a1;
+  red[2][threadIdx.x] = a2;
+  red[3][threadIdx.x] = a3;
+  red[4][threadIdx.x] = a4;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double om0 = -2.0 * red[0][0] / beta;
+    out[0] = om0;
+    out[1] = red[1][0];
+    out[2] = red[2][0];
+    out[3] = red[3][0] - om0 / beta;
+    out[4] = red[4][0];
+  }
+}
+
+// dn/dmu = beta n (1-n), dn/dbeta = -(eps - mu) n (1-n); dw = dn / (2 w) on kept slots
+__global__ void occ_deriv_kernel(int n, const double* eps, const double* occ, const double* wo, const double* wv,
+                                 double mu, double beta, int which, double* dn, double* dwo, double* dwv) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double x = beta * (eps[p] - mu);
+  const double nvir = (x > 0.0) ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x));
+  const double nn1 = occ[p] * nvir;
+  const double d = (which == 0) ? beta * nn1 : -(eps[p] - mu) * nn1;
+  dn[p] = d;
+  dwo[p] = (wo[p] > 0.0) ? d / (2.0 * wo[p]) : 0.0;
+  dwv[p] = (wv[p] > 0.0) ? -d / (2.0 * wv[p]) : 0.0;
+}
+
+// dO/dh_pq = 2 n_p delta_pq + sum_XY w^X_p w^Y_q G^XY_pq
+__global__ void dh_assemble_kernel(int n, const double* occ, const double* wo, const double* wv, const double* goo,
+                                   const double* gov, const double* gvo, const double* gvv, double* out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int p = (int)(e / n), q = (int)(e % n);
+  double v = (p == q) ? 2.0 * occ[p] : 0.0;
+  v += wo[p] * wo[q] * goo[e] + wo[p] * wv[q] * gov[e] + wv[p] * wo[q] * gvo[e] + wv[p] * wv[q] * gvv[e];
+  out[e] = v;
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct Instance {
+  int n = 0;
+  bool has_ham = false;
+  double mu = 0.0, beta = 1.0;
+  double *h = nullptr, *eri = nullptr, *eps = nullptr;
+  double *occ = nullptr, *wo = nullptr, *wv = nullptr, *fock = nullptr;
+  double *dn = nullptr, *dwo = nullptr, *dwv = nullptr, *du_raw = nullptr, *u_raw = nullptr;
+  std::map<std::string, double*> blk, dblk;
+  std::vector<double*> grid, resid, sb, lam, lamt, abuf;
+  double* mf = nullptr;          // meanfield outputs (5)
+  double* acc = nullptr;         // response accumulators: [0] mu, [1] beta, [2] theta, [3] beta grid
+  std::vector<double> energies;  // per node
+  double omega0 = 0, omega1 = 0, omega_cc = 0;
+  int iters = 0, status = 0, lam_iters = 0, lam_status = 0;
+  double* ugrad_acc[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+struct ftcc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  ftcc_options opt;
+  int B = 0, m = 4, P = 4;
+  PanelRule rule;
+  PanelRule* d_rule = nullptr;
+  std::vector<Instance> inst;
+  std::vector<void*> allocs;
+  Program prog;
+  std::unique_ptr<Executor> ex_main, ex_d;
+  bool built = false, solved = false, have_lambda = false;
+  // per problem (instance * m + slot)
+  std::vector<double*> amp, S, e, gr, cot, ebar, dS, de;
+  std::map<std::pair<int, int>, double*> inter, inter_grad, dderived;   // (tensor, problem) / (tensor, inst)
+  std::map<std::pair<int, int>, double*> derived;
+  std::vector<std::array<double*, 4>> ugrad;
+  Scratch scratch;
+  unsigned long long* d_maxbits = nullptr;    // [B][2]
+  double* d_partial = nullptr;                // TAU_BETA partial sums
+  std::vector<int> tau_prefix_host;
+  // descriptor sets for the propagator (uploaded once)
+  std::map<int, std::pair<TauProblem*, int*>> tau_desc;
+  std::map<int, int> tau_blocks;
+  int* d_active = nullptr;                    // [B]
+  long resid_evals = 0, vjp_evals = 0;
+  double t_solve = 0.0, t_lambda = 0.0;
+  size_t bytes = 0;
+
+  double* dalloc(size_t count) {
+    void* p = nullptr;
+    const size_t nb = std::max<size_t>(count, 1) * sizeof(double);
+    if (hipMalloc(&p, nb) != hipSuccess) {
+      (void)hipGetLastError();
+      fail(FTCC_ENOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed (" + std::to_string(bytes) +
+                            " bytes already held)");
+    }
+    bytes += nb;
+    allocs.push_back(p);
+    return (double*)p;
+  }
+};
+
+namespace {
+
+long ipow(long n, int r) {
+  long v = 1;
+  for (int k = 0; k < r; ++k) v *= n;
+  return v;
+}
+
+int run_guarded(const std::function<void()>& f) {
+  try {
+    f();
+    return FTCC_OK;
+  } catch (const Fail& e) {
+    g_err = e.msg;
+    return e.code;
+  } catch (const HipError& e) {
+    g_err = e.what();
+    return FTCC_EDEVICE;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return FTCC_EINVAL;
+  }
+}
+
+void sync(ftcc_ctx* c) { FTCC_HIP(hipStreamSynchronize(c->stream)); }
+
+// ------------------------------------------------------------------ thermal set-up
+void thermal_setup(ftcc_ctx* c, int i) {
+  Instance& I = c->inst[i];
+  const int n = I.n;
+  ThermalProblem tp;
+  tp.n = n;
+  tp.eps = I.eps;
+  tp.h = I.h;
+  tp.eri = I.eri;
+  tp.mu = I.mu;
+  tp.beta = I.beta;
+  tp.thr = c->opt.occ_thresh;
+  tp.occ = I.occ;
+  tp.wo = I.wo;
+  tp.wv = I.wv;
+  tp.fock = I.fock;
+  launch_thermal(tp, c->stream);
+  launch_u_from_fock(n, I.fock, I.eps, I.u_raw, c->stream);
+  for (int k = 0; k < 4; ++k) {
+    BlockSpec b;
+    b.n = n;
+    b.rank = 2;
+    b.pat[0] = kU[k][2];
+    b.pat[1] = kU[k][3];
+    b.base = I.u_raw;
+    b.dbase = I.u_raw;
+    b.wo = I.wo;
+    b.wv = I.wv;
+    b.dwo = b.dwv = nullptr;
+    b.out = I.blk[kU[k]];
+    launch_block(b, c->stream);
+  }
+  for (int k = 0; k < 12; ++k) {
+    BlockSpec b;
+    b.n = n;
+    b.rank = 4;
+    for (int s = 0; s < 4; ++s) b.pat[s] = kG[k][2 + s];
+    b.base = I.eri;
+    b.dbase = I.eri;
+    b.wo = I.wo;
+    b.wv = I.wv;
+    b.dwo = b.dwv = nullptr;
+    b.out = I.blk[kG[k]];
+    launch_block(b, c->stream);
+  }
+  hipLaunchKernelGGL(meanfield_kernel, dim3(1), dim3(256), 0, c->stream, n, I.eps, I.h, I.eri, I.occ, I.fock, I.mu,
+                     I.beta, nullptr, nullptr, I.mf);
+  FTCC_HIP(hipGetLastError());
+}
+
+// derivative blocks for theta: which = 0 (mu), 1 (beta), 2 (direction dh, deri)
+void deriv_setup(ftcc_ctx* c, int i, int which, const double* d_dh, const double* d_deri) {
+  Instance& I = c->inst[i];
+  const int n = I.n;
+  if (which < 2) {
+    hipLaunchKernelGGL(occ_deriv_kernel, dim3((n + 63) / 64), dim3(64), 0, c->stream, n, I.eps, I.occ, I.wo, I.wv,
+                       I.mu, I.beta, which, I.dn, I.dwo, I.dwv);
+    launch_fock_deriv(n, I.eri, nullptr, nullptr, I.occ, I.dn, I.du_raw, c->stream);
+  } else {
+    launch_fock_deriv(n, I.eri, d_deri, d_dh, I.occ, nullptr, I.du_raw, c->stream);
+  }
+  for (int k = 0; k < 4; ++k) {
+    BlockSpec b;
+    b.n = n;
+    b.rank = 2;
+    b.pat[0] = kU[k][2];
+    b.pat[1] = kU[k][3];
+    b.base = I.u_raw;
+    b.dbase = I.du_raw;
+    b.wo = I.wo;
+    b.wv = I.wv;
+    b.dwo = (which < 2) ? I.dwo : nullptr;
+    b.dwv = (which < 2) ? I.dwv : nullptr;
+    b.out = I.dblk[kU[k]];
+    launch_block(b, c->stream);
+  }
+  for (int k = 0; k < 12; ++k) {
+    BlockSpec b;
+    b.n = n;
+    b.rank = 4;
+    for (int s = 0; s < 4; ++s) b.pat[s] = kG[k][2 + s];
+    b.base = I.eri;
+    b.dbase = (which < 2) ? nullptr : d_deri;
+    b.wo = I.wo;
+    b.wv = I.wv;
+    b.dwo = (which < 2) ? I.dwo : nullptr;
+    b.dwv = (which < 2) ? I.dwv : nullptr;
+    b.out = I.dblk[kG[k]];
+    launch_block(b, c->stream);
+  }
+  FTCC_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ build
+void build(ftcc_ctx* c) {
+  if (c->built) return;
+  for (int i = 0; i < c->B; ++i)
+    if (!c->inst[i].has_ham) fail(FTCC_ESTATE, "instance " + std::to_string(i) + " has no Hamiltonian");
+  const int n = c->inst[0].n;
+  for (int i = 0; i < c->B; ++i)
+    if (c->inst[i].n != n) fail(FTCC_EINVAL, "all instances of a context must have the same n");
+  const int m = c->m, P = c->P, B = c->B;
+  const long n2 = (long)n * n, n4 = n2 * n2, len = n2 + n4;
+  c->prog = build_residual_program();
+  const Program& prog = c->prog;
+
+  for (int i = 0; i < B; ++i) {
+    Instance& I = c->inst[i];
+    I.occ = c->dalloc(n);
+    I.wo = c->dalloc(n);
+    I.wv = c->dalloc(n);
+    I.dn = c->dalloc(n);
+    I.dwo = c->dalloc(n);
+    I.dwv = c->dalloc(n);
+    I.fock = c->dalloc(n2);
+    I.u_raw = c->dalloc(n2);
+    I.du_raw = c->dalloc(n2);
+    for (int k = 0; k < 4; ++k) {
+      I.blk[kU[k]] = c->dalloc(n2);
+      I.dblk[kU[k]] = c->dalloc(n2);
+    }
+    for (int k = 0; k < 12; ++k) {
+      I.blk[kG[k]] = c->dalloc(n4);
+      I.dblk[kG[k]] = c->dalloc(n4);
+    }
+    I.mf = c->dalloc(5);
+    I.acc = c->dalloc(8);
+    for (int k = 0; k < 4; ++k) I.ugrad_acc[k] = c->dalloc(n2);
+    I.sb.resize(P + 1);
+    for (int p = 0; p <= P; ++p) I.sb[p] = c->dalloc(len);
+    if (!c->opt.checkpoint) {
+      I.grid.resize(P * m);
+      I.resid.resize(P * m);
+      for (int k = 0; k < P * m; ++k) {
+        I.grid[k] = c->dalloc(len);
+        I.resid[k] = c->dalloc(len);
+      }
+    }
+    I.energies.assign(P * m, 0.0);
+  }
+  const int np = B * m;
+  c->amp.resize(np);
+  c->S.resize(np);
+  c->e.resize(np);
+  c->gr.resize(np);
+  c->cot.resize(np);
+  c->ebar.resize(np);
+  c->dS.resize(np);
+  c->de.resize(np);
+  c->ugrad.resize(np);
+  c->scratch.a.resize(np);
+  c->scratch.b.resize(np);
+  c->scratch.c.resize(np);
+  c->scratch.part.resize(np);
+  std::vector<ProblemRef> probs;
+  for (int i = 0; i < B; ++i)
+    for (int x = 0; x < m; ++x) {
+      const int p = i * m + x;
+      probs.push_back({i, x, n});
+      c->amp[p] = c->dalloc(len);
+      c->S[p] = c->dalloc(len);
+      c->e[p] = c->dalloc(1);
+      c->gr[p] = c->dalloc(len);
+      c->cot[p] = c->dalloc(len);
+      c->ebar[p] = c->dalloc(1);
+      c->dS[p] = c->dalloc(len);
+      c->de[p] = c->dalloc(1);
+      for (int k = 0; k < 4; ++k) c->ugrad[p][k] = c->dalloc(n2);
+      c->scratch.a[p] = c->dalloc(n4);
+      c->scratch.b[p] = c->dalloc(n4);
+      c->scratch.c[p] = c->dalloc(n4);
+      c->scratch.part[p] = c->dalloc(n4);
+      const double eb = c->rule.b[x] / P;   // (1/beta) g_x
+      FTCC_HIP(hipMemcpy(c->ebar[p], &eb, sizeof(double), hipMemcpyHostToDevice));
+    }
+  c->scratch.dot_partial = c->dalloc((size_t)np * 64 + 64);
+  c->d_maxbits = (unsigned long long*)c->dalloc(2 * B);
+  c->d_active = (int*)c->dalloc(B);
+  {
+    std::vector<int> ones(2 * B, 1);
+    FTCC_HIP(hipMemcpy(c->d_active, ones.data(), sizeof(int) * B, hipMemcpyHostToDevice));
+  }
+  c->d_rule = (PanelRule*)c->dalloc(sizeof(PanelRule) / sizeof(double) + 1);
+  FTCC_HIP(hipMemcpy(c->d_rule, &c->rule, sizeof(PanelRule), hipMemcpyHostToDevice));
+  c->d_partial = c->dalloc((size_t)B * 2 * ((len + 1023) / 1024) + 16);
+
+  std::vector<int> ugrads;
+  for (int k = 0; k < 4; ++k) ugrads.push_back(prog.id(kU[k]));
+  const int id_t1 = prog.id("t1"), id_t2 = prog.id("t2"), id_S1 = prog.id("S1"), id_S2 = prog.id("S2"),
+            id_E = prog.id("E");
+
+  auto tensor_buf = [c, &probs](std::map<std::pair<int, int>, double*>& store, int t, int key, long count) {
+    auto k = std::make_pair(t, key);
+    auto it = store.find(k);
+    if (it != store.end()) return it->second;
+    double* p = c->dalloc(count);
+    store[k] = p;
+    return p;
+  };
+  auto bind_common = [&, c](int t, int p, bool grad) -> double* {
+    const TensorDecl& d = prog.t[t];
+    const long cnt = ipow(n, d.rank);
+    if (t == id_t1) return grad ? c->gr[p] : c->amp[p];
+    if (t == id_t2) return grad ? c->gr[p] + n2 : c->amp[p] + n2;
+    if (grad) {
+      if (t == id_S1) return c->cot[p];
+      if (t == id_S2) return c->cot[p] + n2;
+      if (t == id_E) return c->ebar[p];
+      if (d.kind == T_CONST) {
+        for (int k = 0; k < 4; ++k)
+          if (d.name == kU[k]) return c->ugrad[p][k];
+        fail(FTCC_EINVAL, "no gradient buffer for " + d.name);
+      }
+      return tensor_buf(c->inter_grad, t, p, cnt);
+    }
+    if (d.kind == T_INTER && !d.derived) return tensor_buf(c->inter, t, p, cnt);
+    return nullptr;
+  };
+  Binder bind_main = [&, c](int t, int p, bool grad) -> double* {
+    const TensorDecl& d = prog.t[t];
+    if (double* q = bind_common(t, p, grad)) return q;
+    const int i = probs[p].inst;
+    if (d.kind == T_CONST) return c->inst[i].blk[d.name];
+    if (d.derived) return tensor_buf(c->derived, t, i, ipow(n, d.rank));
+    if (t == id_S1) return c->S[p];
+    if (t == id_S2) return c->S[p] + n2;
+    if (t == id_E) return c->e[p];
+    fail(FTCC_EINVAL, "unbound tensor " + d.name);
+  };
+  Binder bind_d = [&, c](int t, int p, bool grad) -> double* {
+    const TensorDecl& d = prog.t[t];
+    if (double* q = bind_common(t, p, grad)) return q;
+    const int i = probs[p].inst;
+    if (d.kind == T_CONST) return c->inst[i].dblk[d.name];
+    if (d.derived) return tensor_buf(c->dderived, t, i, ipow(n, d.rank));
+    if (t == id_S1) return c->dS[p];
+    if (t == id_S2) return c->dS[p] + n2;
+    if (t == id_E) return c->de[p];
+    fail(FTCC_EINVAL, "unbound tensor " + d.name);
+  };
+  auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
+  c->ex_main.reset(new Executor());
+  c->ex_main->build(&prog, probs, bind_main, &c->scratch, calloc_, true, ugrads);
+  c->ex_d.reset(new Executor());
+  c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {});
+
+  // propagator descriptors: one per (instance, segment) for each mode's buffer roles
+  c->built = true;
+}
+
+enum Roles { R_FWD = 0, R_END, R_INIT, R_LAMT, R_LSTEP, R_APREV, R_BETA };
+
+// Descriptor set for the propagator: per instance two segments (t1, t2).
+// `panel` selects per-panel buffers (sb, lam, a, ...).
+void tau_run(ftcc_ctx* c, int mode, int panel, bool use_active) {
+  const int B = c->B, m = c->m;
+  const int n = c->inst[0].n;
+  const long n2 = (long)n * n, n4 = n2 * n2;
+  std::vector<TauProblem> ps;
+  std::vector<int> prefix;
+  int total = 0;
+  for (int i = 0; i < B; ++i) {
+    Instance& I = c->inst[i];
+    for (int seg = 0; seg < 2; ++seg) {
+      TauProblem t;
+      std::memset(&t, 0, sizeof(t));
+      const long off = seg ? n2 : 0;
+      t.eps = I.eps;
+      t.n = n;
+      t.rank = seg ? 4 : 2;
+      t.len = seg ? n4 : n2;
+      t.h = I.beta / c->P;
+      t.maxbits = c->d_maxbits + 2 * i;
+      for (int x = 0; x < m; ++x) {
+        const int p = i * m + x;
+        switch (mode) {
+          case TAU_INIT:
+          case TAU_STEP:
+            t.S[x] = c->S[p] + off;
+            t.s[x] = c->amp[p] + off;
+            break;
+          case TAU_END:
+            t.S[x] = c->S[p] + off;
+            break;
+          case TAU_LAMT:      // S = lambda (node storage), s = lambda-tilde (cotangent slots)
+            t.S[x] = I.lam[panel * m + x] + off;
+            t.s[x] = c->cot[p] + off;
+            break;
+          case TAU_LSTEP:     // s = lambda (node storage), R = gradient
+            t.s[x] = I.lam[panel * m + x] + off;
+            t.R[x] = c->gr[p] + off;
+            break;
+          case TAU_APREV:
+            t.S[x] = I.lam[panel * m + x] + off;
+            break;
+          case TAU_BETA:      // S = lambda, R = converged residuals
+            t.S[x] = I.lam[panel * m + x] + off;
+            t.R[x] = c->S[p] + off;
+            break;
+        }
+      }
+      if (mode == TAU_INIT || mode == TAU_STEP || mode == TAU_END || mode == TAU_BETA) t.sb = I.sb[panel] + off;
+      if (mode == TAU_END) t.out = I.sb[panel + 1] + off;
+      if (mode == TAU_LAMT || mode == TAU_APREV) t.sb = I.abuf[panel + 1] + off;
+      if (mode == TAU_APREV) t.out = I.abuf[panel] + off;
+      if (mode == TAU_BETA) t.lam_a = I.abuf[panel + 1] + off;
+      const int nb = (int)((t.len + 1023) / 1024);
+      t.partial = c->d_partial + (long)total;
+      prefix.push_back(total);
+      total += nb;
+      ps.push_back(t);
+      (void)use_active;
+    }
+  }
+  // upload descriptors (small) and launch
+  TauProblem* d_ps = nullptr;
+  int* d_pre = nullptr;
+  FTCC_HIP(hipMallocAsync((void**)&d_ps, sizeof(TauProblem) * ps.size(), c->stream));
+  FTCC_HIP(hipMallocAsync((void**)&d_pre, sizeof(int) * prefix.size(), c->stream));
+  FTCC_HIP(hipMemcpyAsync(d_ps, ps.data(), sizeof(TauProblem) * ps.size(), hipMemcpyHostToDevice, c->stream));
+  FTCC_HIP(hipMemcpyAsync(d_pre, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice, c->stream));
+  launch_tau(c->d_rule, mode, d_ps, d_pre, (int)ps.size(), total, c->stream);
+  FTCC_HIP(hipGetLastError());
+  FTCC_HIP(hipFreeAsync(d_ps, c->stream));
+  FTCC_HIP(hipFreeAsync(d_pre, c->stream));
+}
+
+void reset_maxbits(ftcc_ctx* c) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, c->stream, c->d_maxbits, 2 * c->B);
+}
+
+std::vector<double> read_maxbits(ftcc_ctx* c) {
+  std::vector<unsigned long long> bits(2 * c->B);
+  FTCC_HIP(hipMemcpyAsync(bits.data(), c->d_maxbits, sizeof(unsigned long long) * bits.size(),
+                          hipMemcpyDeviceToHost, c->stream));
+  sync(c);
+  std::vector<double> v(bits.size());
+  for (size_t k = 0; k < bits.size(); ++k) std::memcpy(&v[k], &bits[k], sizeof(double));
+  return v;
+}
+
+void copy_d(ftcc_ctx* c, double* dst, const double* src, long count) {
+  FTCC_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToDevice, c->stream));
+}
+
+void zero_d(ftcc_ctx* c, double* dst, long count) { launch_axpby(count, 0.0, dst, 0.0, dst, c->stream); }
+
+// Converge the Picard iteration of one panel for all instances (amplitudes in
+// the slots, residuals at the final amplitudes in S).  Returns per-instance sweeps.
+std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
+  const int B = c->B;
+  std::vector<int> its(B, 0);
+  std::vector<bool> active(B, true);
+  for (int i = 0; i < B; ++i)
+    if (status[i] != 0) active[i] = false;
+  tau_run(c, TAU_INIT, panel, false);
+  for (int it = 1; it <= c->opt.max_iter; ++it) {
+    c->ex_main->run_forward(c->stream);
+    c->resid_evals += (long)B * c->m;
+    reset_maxbits(c);
+    tau_run(c, TAU_STEP, panel, true);
+    std::vector<double> mb = read_maxbits(c);
+    bool any = false;
+    for (int i = 0; i < B; ++i) {
+      if (!active[i]) continue;
+      its[i] = it;
+      const double chg = mb[2 * i], val = mb[2 * i + 1];
+      if (!std::isfinite(chg) || !std::isfinite(val)) {
+        status[i] = FTCC_ENONFINITE;
+        active[i] = false;
+        continue;
+      }
+      if (chg <= c->opt.tol * std::max(1.0, val)) {
+        active[i] = false;
+        continue;
+      }
+      any = true;
+    }
+    if (!any) break;
+    if (it == c->opt.max_iter)
+      for (int i = 0; i < B; ++i)
+        if (active[i]) status[i] = FTCC_ENOCONV;
+  }
+  c->ex_main->run_forward(c->stream);
+  c->resid_evals += (long)B * c->m;
+  return its;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+void ftcc_default_options(ftcc_options* opt) {
+  if (!opt) return;
+  opt->n_tau = 16;
+  opt->nodes_per_panel = 4;
+  opt->propagator = 0;
+  opt->occ_thresh = 0.0;
+  opt->tol = 1e-12;
+  opt->max_iter = 200;
+  opt->checkpoint = 0;
+}
+
+int ftcc_abi_version(void) { return FTCC_ABI_VERSION; }
+
+const char* ftcc_last_error(void) { return g_err.c_str(); }
+
+int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options* opt) {
+  return run_guarded([&] {
+    if (!out || n_instances <= 0) fail(FTCC_EINVAL, "ftcc_create: bad arguments");
+    ftcc_options o;
+    ftcc_default_options(&o);
+    if (opt) o = *opt;
+    if (o.nodes_per_panel < 1 || o.nodes_per_panel > kMaxNodes) fail(FTCC_EINVAL, "nodes_per_panel must be 1..6");
+    if (o.n_tau < o.nodes_per_panel || o.n_tau % o.nodes_per_panel)
+      fail(FTCC_EINVAL, "n_tau must be a positive multiple of nodes_per_panel");
+    if (o.propagator < 0 || o.propagator > 1) fail(FTCC_EINVAL, "propagator must be 0 or 1");
+    if (!(o.tol > 0.0) || o.max_iter < 1) fail(FTCC_EINVAL, "tol must be > 0 and max_iter >= 1");
+    if (!(o.occ_thresh >= 0.0)) fail(FTCC_EINVAL, "occ_thresh must be >= 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) fail(FTCC_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) fail(FTCC_EINVAL, "device index out of range");
+    FTCC_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    FTCC_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
+      fail(FTCC_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    FTCC_HIP(init_tau_constants());
+    std::unique_ptr<ftcc_ctx> c(new ftcc_ctx());
+    c->device = device;
+    c->opt = o;
+    c->B = n_instances;
+    c->m = o.nodes_per_panel;
+    c->P = o.n_tau / o.nodes_per_panel;
+    c->rule = make_rule(c->m, o.propagator);
+    c->inst.resize(n_instances);
+    FTCC_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+    c->stream = c->own_stream;
+    *out = c.release();
+  });
+}
+
+int ftcc_destroy(ftcc_ctx* c) {
+  if (!c) return FTCC_OK;
+  return run_guarded([&] {
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    c->ex_main.reset();
+    c->ex_d.reset();
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+  });
+}
+
+int ftcc_set_stream(ftcc_ctx* c, void* s) {
+  return run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    c->stream = s ? (hipStream_t)s : c->own_stream;
+  });
+}
+
+int ftcc_set_hamiltonian(ftcc_ctx* c, int i, int n, const double* h, const double* eri, const double* eps) {
+  return run_guarded([&] {
+    if (!c || !h || !eri || !eps) fail(FTCC_EINVAL, "null argument");
+    if (i < 0 || i >= c->B) fail(FTCC_EINVAL, "instance index out of range");
+    if (n < 1 || n > 256) fail(FTCC_EINVAL, "n must be 1..256");
+    FTCC_HIP(hipSetDevice(c->device));
+    Instance& I = c->inst[i];
+    if (c->built && n != I.n) fail(FTCC_EINVAL, "n cannot change after the first solve");
+    const long n2 = (long)n * n, n4 = n2 * n2;
+    for (long k = 0; k < n2; ++k)
+      if (!std::isfinite(h[k])) fail(FTCC_EINVAL, "h has a non-finite entry");
+    for (long k = 0; k < n; ++k)
+      if (!std::isfinite(eps[k])) fail(FTCC_EINVAL, "eps has a non-finite entry");
+    for (long k = 0; k < n4; ++k)
+      if (!std::isfinite(eri[k])) fail(FTCC_EINVAL, "eri has a non-finite entry");
+    if (!I.h) {
+      I.n = n;
+      I.h = c->dalloc(n2);
+      I.eri = c->dalloc(n4);
+      I.eps = c->dalloc(n);
+    }
+    FTCC_HIP(hipMemcpy(I.h, h, sizeof(double) * n2, hipMemcpyHostToDevice));
+    FTCC_HIP(hipMemcpy(I.eri, eri, sizeof(double) * n4, hipMemcpyHostToDevice));
+    FTCC_HIP(hipMemcpy(I.eps, eps, sizeof(double) * n, hipMemcpyHostToDevice));
+    I.has_ham = true;
+    c->solved = false;
+    c->have_lambda = false;
+  });
+}
+
+int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int* iters_out, int* status_out) {
+  int any_fail = 0;
+  int rc = run_guarded([&] {
+    if (!c || !mu || !beta) fail(FTCC_EINVAL, "null argument");
+    FTCC_HIP(hipSetDevice(c->device));
+    for (int i = 0; i < c->B; ++i)
+      if (!std::isfinite(mu[i]) || !(beta[i] > 0.0) || !std::isfinite(beta[i]))
+        fail(FTCC_EINVAL, "mu must be finite and beta positive");
+    build(c);
+    const int B = c->B, m = c->m, P = c->P;
+    const int n = c->inst[0].n;
+    const long n2 = (long)n * n, len = n2 + n2 * n2;
+    hipEvent_t e0, e1;
+    FTCC_HIP(hipEventCreate(&e0));
+    FTCC_HIP(hipEventCreate(&e1));
+    FTCC_HIP(hipEventRecord(e0, c->stream));
+    c->resid_evals = 0;
+    for (int i = 0; i < B; ++i) {
+      Instance& I = c->inst[i];
+      I.mu = mu[i];
+      I.beta = beta[i];
+      thermal_setup(c, i);
+      zero_d(c, I.sb[0], len);
+      I.iters = 0;
+      I.status = 0;
+    }
+    c->ex_main->run_setup(c->stream);
+    std::vector<int> status(B, 0), total(B, 0);
+    std::vector<double> ebuf(B * m);
+    for (int p = 0; p < P; ++p) {
+      std::vector<int> its = panel_solve(c, p, status);
+      for (int i = 0; i < B; ++i) total[i] += its[i];
+      for (int i = 0; i < B; ++i) {
+        Instance& I = c->inst[i];
+        for (int x = 0; x < m; ++x) {
+          FTCC_HIP(hipMemcpyAsync(&ebuf[i * m + x], c->e[i * m + x], sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream));
+          if (!c->opt.checkpoint) {
+            copy_d(c, I.grid[p * m + x], c->amp[i * m + x], len);
+            copy_d(c, I.resid[p * m + x], c->S[i * m + x], len);
+          }
+        }
+      }
+      tau_run(c, TAU_END, p, false);
+      sync(c);
+      for (int i = 0; i < B; ++i)
+        for (int x = 0; x < m; ++x) c->inst[i].energies[p * m + x] = ebuf[i * m + x];
+    }
+    FTCC_HIP(hipEventRecord(e1, c->stream));
+    sync(c);
+    float ms = 0.f;
+    FTCC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    c->t_solve = ms * 1e-3;
+    FTCC_HIP(hipEventDestroy(e0));
+    FTCC_HIP(hipEventDestroy(e1));
+    for (int i = 0; i < B; ++i) {
+      Instance& I = c->inst[i];
+      double mf[5];
+      FTCC_HIP(hipMemcpy(mf, I.mf, sizeof(mf), hipMemcpyDeviceToHost));
+      I.omega0 = mf[0];
+      I.omega1 = mf[1];
+      double occ_cc = 0.0;
+      for (int p = 0; p < P; ++p)
+        for (int x = 0; x < m; ++x) occ_cc += c->rule.b[x] / P * I.energies[p * m + x];
+      I.omega_cc = occ_cc;
+      I.iters = total[i];
+      I.status = status[i];
+      if (iters_out) iters_out[i] = total[i];
+      if (status_out) status_out[i] = status[i];
+      if (status[i] != 0) any_fail = status[i];
+    }
+    c->solved = true;
+    c->have_lambda = false;
+  });
+  if (rc == FTCC_OK && any_fail) {
+    g_err = "at least one instance did not converge (see status_out)";
+    return any_fail;
+  }
+  return rc;
+}
+
+int ftcc_grand_potential(ftcc_ctx* c, double* omega, double* parts) {
+  return run_guarded([&] {
+    if (!c || !omega) fail(FTCC_EINVAL, "null argument");
+    if (!c->solved) fail(FTCC_ESTATE, "call ftcc_solve_amplitudes first");
+    for (int i = 0; i < c->B; ++i) {
+      const Instance& I = c->inst[i];
+      omega[i] = I.omega0 + I.omega1 + I.omega_cc;
+      if (parts) {
+        parts[3 * i] = I.omega0;
+        parts[3 * i + 1] = I.omega1;
+        parts[3 * i + 2] = I.omega_cc;
+      }
+    }
+  });
+}
+
+int ftcc_get_amplitudes(ftcc_ctx* c, int i, int k, double* t1, double* t2) {
+  return run_guarded([&] {
+    if (!c || !t1 || !t2) fail(FTCC_EINVAL, "null argument");
+    if (!c->solved) fail(FTCC_ESTATE, "call ftcc_solve_amplitudes first");
+    if (c->opt.checkpoint) fail(FTCC_ESTATE, "amplitudes are not kept with checkpoint = 1");
+    if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
+    const long n = c->inst[i].n, n2 = n * n;
+    FTCC_HIP(hipSetDevice(c->device));
+    sync(c);
+    FTCC_HIP(hipMemcpy(t1, c->inst[i].grid[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
+    FTCC_HIP(hipMemcpy(t2, c->inst[i].grid[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Bring the converged amplitudes of panel p into the slots and evaluate the
+// forward program there (tape for the backward, residuals in S).
+void load_panel(ftcc_ctx* c, int p) {
+  const int B = c->B, m = c->m;
+  const long n = c->inst[0].n, len = n * n + n * n * n * n;
+  if (!c->opt.checkpoint) {
+    for (int i = 0; i < B; ++i)
+      for (int x = 0; x < m; ++x) copy_d(c, c->amp[i * m + x], c->inst[i].grid[p * m + x], len);
+    c->ex_main->run_forward(c->stream);
+  } else {
+    std::vector<int> st(B, 0);
+    panel_solve(c, p, st);   // deterministic: reproduces the forward sweep
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
+  int any_fail = 0;
+  int rc = run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    if (!c->solved) fail(FTCC_ESTATE, "call ftcc_solve_amplitudes first");
+    FTCC_HIP(hipSetDevice(c->device));
+    const int B = c->B, m = c->m, P = c->P;
+    const long n = c->inst[0].n, n2 = n * n, len = n2 + n2 * n2;
+    for (int i = 0; i < B; ++i) {
+      Instance& I = c->inst[i];
+      if (I.lam.empty()) {
+        I.lam.resize(P * m);
+        I.lamt.resize(P * m);
+        for (int k = 0; k < P * m; ++k) {
+          I.lam[k] = c->dalloc(len);
+          I.lamt[k] = c->dalloc(len);
+        }
+        I.abuf.resize(P + 1);
+        for (int p = 0; p <= P; ++p) I.abuf[p] = c->dalloc(len);
+      }
+      zero_d(c, I.abuf[P], len);
+    }
+    hipEvent_t e0, e1;
+    FTCC_HIP(hipEventCreate(&e0));
+    FTCC_HIP(hipEventCreate(&e1));
+    FTCC_HIP(hipEventRecord(e0, c->stream));
+    c->vjp_evals = 0;
+    std::vector<int> total(B, 0), status(B, 0);
+    for (int p = P - 1; p >= 0; --p) {
+      load_panel(c, p);
+      // lambda_x = -(g_x/beta) dE/ds : backward with zero S-cotangent
+      for (int q = 0; q < B * m; ++q) zero_d(c, c->cot[q], len);
+      c->ex_main->run_backward(c->stream);
+      c->vjp_evals += (long)B * m;
+      reset_maxbits(c);
+      tau_run(c, TAU_LSTEP, p, false);
+      std::vector<bool> active(B, true);
+      for (int it = 1; it <= c->opt.max_iter; ++it) {
+        tau_run(c, TAU_LAMT, p, false);
+        c->ex_main->run_backward(c->stream);
+        c->vjp_evals += (long)B * m;
+        reset_maxbits(c);
+        tau_run(c, TAU_LSTEP, p, false);
+        std::vector<double> mb = read_maxbits(c);
+        bool any = false;
+        for (int i = 0; i < B; ++i) {
+          if (!active[i]) continue;
+          total[i] += 1;
+          const double chg = mb[2 * i], val = mb[2 * i + 1];
+          if (!std::isfinite(chg) || !std::isfinite(val)) {
+            status[i] = FTCC_ENONFINITE;
+            active[i] = false;
+            continue;
+          }
+          if (chg <= c->opt.tol * std::max(val, 1e-30) || chg == 0.0) {
+            active[i] = false;
+            continue;
+          }
+          any = true;
+        }
+        if (!any) break;
+        if (it == c->opt.max_iter)
+          for (int i = 0; i < B; ++i)
+            if (active[i]) status[i] = FTCC_ENOCONV;
+      }
+      tau_run(c, TAU_LAMT, p, false);   // lambda-tilde of the converged lambda
+      for (int i = 0; i < B; ++i)
+        for (int x = 0; x < m; ++x) copy_d(c, c->inst[i].lamt[p * m + x], c->cot[i * m + x], len);
+      tau_run(c, TAU_APREV, p, false);
+    }
+    FTCC_HIP(hipEventRecord(e1, c->stream));
+    sync(c);
+    float ms = 0.f;
+    FTCC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    c->t_lambda = ms * 1e-3;
+    FTCC_HIP(hipEventDestroy(e0));
+    FTCC_HIP(hipEventDestroy(e1));
+    for (int i = 0; i < B; ++i) {
+      c->inst[i].lam_iters = total[i];
+      c->inst[i].lam_status = status[i];
+      if (iters_out) iters_out[i] = total[i];
+      if (status_out) status_out[i] = status[i];
+      if (status[i]) any_fail = status[i];
+    }
+    c->have_lambda = true;
+  });
+  if (rc == FTCC_OK && any_fail) {
+    g_err = "at least one instance did not converge in the adjoint (see status_out)";
+    return any_fail;
+  }
+  return rc;
+}
+
+int ftcc_get_lambda(ftcc_ctx* c, int i, int k, double* l1, double* l2, double* lt1, double* lt2) {
+  return run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
+    if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
+    const long n = c->inst[i].n, n2 = n * n;
+    sync(c);
+    if (l1) FTCC_HIP(hipMemcpy(l1, c->inst[i].lam[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
+    if (l2) FTCC_HIP(hipMemcpy(l2, c->inst[i].lam[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+    if (lt1) FTCC_HIP(hipMemcpy(lt1, c->inst[i].lamt[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
+    if (lt2) FTCC_HIP(hipMemcpy(lt2, c->inst[i].lamt[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+  });
+}
+
+int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, const double* const* deri_dtheta,
+                  const double* const* dh_dtheta, double* dO_dtheta) {
+  return run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
+    FTCC_HIP(hipSetDevice(c->device));
+    const int B = c->B, m = c->m, P = c->P;
+    const long n = c->inst[0].n, n2 = n * n, n4 = n2 * n2, len = n2 + n4;
+    const bool want_theta = dO_dtheta && (deri_dtheta || dh_dtheta);
+    // device copies of the theta directions
+    std::vector<double*> d_deri(B, nullptr), d_dh(B, nullptr);
+    std::vector<void*> tmp;
+    if (want_theta) {
+      for (int i = 0; i < B; ++i) {
+        if (deri_dtheta && deri_dtheta[i]) {
+          FTCC_HIP(hipMalloc((void**)&d_deri[i], sizeof(double) * n4));
+          tmp.push_back(d_deri[i]);
+          FTCC_HIP(hipMemcpy(d_deri[i], deri_dtheta[i], sizeof(double) * n4, hipMemcpyHostToDevice));
+        }
+        if (dh_dtheta && dh_dtheta[i]) {
+          FTCC_HIP(hipMalloc((void**)&d_dh[i], sizeof(double) * n2));
+          tmp.push_back(d_dh[i]);
+          FTCC_HIP(hipMemcpy(d_dh[i], dh_dtheta[i], sizeof(double) * n2, hipMemcpyHostToDevice));
+        }
+      }
+    }
+    for (int i = 0; i < B; ++i) {
+      zero_d(c, c->inst[i].acc, 8);
+      for (int k = 0; k < 4; ++k) zero_d(c, c->inst[i].ugrad_acc[k], n2);
+    }
+    // dot launches: <lamt_x, dS_x> and (g_x/beta) dE_x accumulated into acc[slot]
+    auto accumulate = [&](int slot) {
+      std::vector<DotProblem> ds;
+      for (int i = 0; i < B; ++i)
+        for (int x = 0; x < m; ++x) {
+          const int q = i * m + x;
+          DotProblem d;
+          d.X = c->cot[q];
+          d.Y = c->dS[q];
+          d.out = c->inst[i].acc + slot;
+          d.len = len;
+          d.alpha = 1.0;
+          d.beta = 1.0;
+          ds.push_back(d);
+        }
+      // sequential per problem to keep a fixed summation order into one scalar
+      for (const DotProblem& d : ds) {
+        DotProblem* dd = nullptr;
+        FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem), c->stream));
+        FTCC_HIP(hipMemcpyAsync(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice, c->stream));
+        launch_dot(dd, 1, 64, c->scratch.dot_partial, c->stream);
+        FTCC_HIP(hipFreeAsync(dd, c->stream));
+      }
+      for (int i = 0; i < B; ++i)
+        for (int x = 0; x < m; ++x)
+          launch_axpby(1, c->rule.b[x] / P, c->de[i * m + x], 1.0, c->inst[i].acc + slot, c->stream);
+    };
+    for (int p = 0; p < P; ++p) {
+      load_panel(c, p);
+      for (int i = 0; i < B; ++i)
+        for (int x = 0; x < m; ++x) copy_d(c, c->cot[i * m + x], c->inst[i].lamt[p * m + x], len);
+      if (dO_dh) {
+        c->ex_main->run_backward(c->stream);
+        for (int i = 0; i < B; ++i)
+          for (int x = 0; x < m; ++x)
+            for (int k = 0; k < 4; ++k)
+              launch_axpby(n2, 1.0, c->ugrad[i * m + x][k], 1.0, c->inst[i].ugrad_acc[k], c->stream);
+      }
+      // beta: explicit dependence of the propagator weights (needs S at converged s)
+      if (dO_dbeta) {
+        tau_run(c, TAU_BETA, p, false);
+        // partial sums per (instance, segment) -> acc[3]
+        const int nb1 = (int)((n2 + 1023) / 1024), nb2 = (int)((n4 + 1023) / 1024);
+        for (int i = 0; i < B; ++i) {
+          const long base = (long)i * (nb1 + nb2);
+          launch_sum(c->d_partial + base, nb1 + nb2, c->inst[i].acc + 4, c->stream);
+          launch_axpby(1, 1.0 / P, c->inst[i].acc + 4, 1.0, c->inst[i].acc + 3, c->stream);
+        }
+      }
+      for (int which = 0; which < 3; ++which) {
+        if (which == 0 && !dO_dmu) continue;
+        if (which == 1 && !dO_dbeta) continue;
+        if (which == 2 && !want_theta) continue;
+        for (int i = 0; i < B; ++i) deriv_setup(c, i, which, d_dh[i], d_deri[i]);
+        c->ex_d->run_setup(c->stream);
+        c->ex_d->run_forward(c->stream);
+        accumulate(which);
+      }
+    }
+    // mean-field parts and assembly
+    std::vector<double> accs(8 * B), mfv(5 * B);
+    for (int i = 0; i < B; ++i) {
+      Instance& I = c->inst[i];
+      hipLaunchKernelGGL(meanfield_kernel, dim3(1), dim3(256), 0, c->stream, (int)n, I.eps, I.h, I.eri, I.occ,
+                         I.fock, I.mu, I.beta, d_dh[i], d_deri[i], I.mf);
+      FTCC_HIP(hipMemcpyAsync(&mfv[5 * i], I.mf, sizeof(double) * 5, hipMemcpyDeviceToHost, c->stream));
+      FTCC_HIP(hipMemcpyAsync(&accs[8 * i], I.acc, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
+      if (dO_dh) {
+        double* dd = nullptr;
+        FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(double) * n2, c->stream));
+        hipLaunchKernelGGL(dh_assemble_kernel, dim3((n2 + 255) / 256), dim3(256), 0, c->stream, (int)n, I.occ, I.wo,
+                           I.wv, I.ugrad_acc[0], I.ugrad_acc[1], I.ugrad_acc[2], I.ugrad_acc[3], dd);
+        FTCC_HIP(hipMemcpyAsync(dO_dh + (long)i * n2, dd, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
+        FTCC_HIP(hipFreeAsync(dd, c->stream));
+      }
+    }
+    sync(c);
+    for (void* t : tmp) (void)hipFree(t);
+    for (int i = 0; i < B; ++i) {
+      if (dO_dmu) dO_dmu[i] = mfv[5 * i + 2] + accs[8 * i + 0];
+      if (dO_dbeta) dO_dbeta[i] = mfv[5 * i + 3] + accs[8 * i + 1] + accs[8 * i + 3];
+      if (want_theta) dO_dtheta[i] = mfv[5 * i + 4] + accs[8 * i + 2];
+    }
+  });
+}
+
+int ftcc_eval_residual(ftcc_ctx* c, int i, double mu, double beta, const double* t1, const double* t2, double* S1,
+                       double* S2, double* E) {
+  return run_guarded([&] {
+    if (!c || !t1 || !t2) fail(FTCC_EINVAL, "null argument");
+    if (i < 0 || i >= c->B) fail(FTCC_EINVAL, "instance index out of range");
+    FTCC_HIP(hipSetDevice(c->device));
+    build(c);
+    Instance& I = c->inst[i];
+    const long n = I.n, n2 = n * n, n4 = n2 * n2;
+    I.mu = mu;
+    I.beta = beta;
+    thermal_setup(c, i);
+    c->ex_main->run_setup(c->stream);
+    for (int x = 0; x < c->m; ++x) {
+      FTCC_HIP(hipMemcpyAsync(c->amp[i * c->m + x], t1, sizeof(double) * n2, hipMemcpyHostToDevice, c->stream));
+      FTCC_HIP(
+          hipMemcpyAsync(c->amp[i * c->m + x] + n2, t2, sizeof(double) * n4, hipMemcpyHostToDevice, c->stream));
+    }
+    c->ex_main->run_forward(c->stream);
+    const int q = i * c->m;
+    if (S1) FTCC_HIP(hipMemcpyAsync(S1, c->S[q], sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
+    if (S2) FTCC_HIP(hipMemcpyAsync(S2, c->S[q] + n2, sizeof(double) * n4, hipMemcpyDeviceToHost, c->stream));
+    if (E) FTCC_HIP(hipMemcpyAsync(E, c->e[q], sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    c->solved = false;
+    c->have_lambda = false;
+  });
+}
+
+int ftcc_time_residual(ftcc_ctx* c, int reps, double* seconds_out, double* flops_out) {
+  return run_guarded([&] {
+    if (!c || reps < 1) fail(FTCC_EINVAL, "bad argument");
+    if (!c->built) fail(FTCC_ESTATE, "evaluate a residual or solve first");
+    FTCC_HIP(hipSetDevice(c->device));
+    hipEvent_t e0, e1;
+    FTCC_HIP(hipEventCreate(&e0));
+    FTCC_HIP(hipEventCreate(&e1));
+    FTCC_HIP(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) c->ex_main->run_forward(c->stream);
+    FTCC_HIP(hipEventRecord(e1, c->stream));
+    sync(c);
+    float ms = 0.f;
+    FTCC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    FTCC_HIP(hipEventDestroy(e0));
+    FTCC_HIP(hipEventDestroy(e1));
+    if (seconds_out) *seconds_out = ms * 1e-3;
+    if (flops_out) *flops_out = c->ex_main->gemm_flops_forward();
+  });
+}
+
+int ftcc_stats(ftcc_ctx* c, long* resid_evals, long* vjp_evals, double* solve_seconds, double* lambda_seconds) {
+  return run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    if (resid_evals) *resid_evals = c->resid_evals;
+    if (vjp_evals) *vjp_evals = c->vjp_evals;
+    if (solve_seconds) *solve_seconds = c->t_solve;
+    if (lambda_seconds) *lambda_seconds = c->t_lambda;
+  });
+}
+
+}  // extern "C"

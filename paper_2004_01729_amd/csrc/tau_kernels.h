@@ -1,0 +1,94 @@
+// Imaginary-time kernels: thermal integral blocks and the panel propagator.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ftcc {
+
+constexpr int kMaxNodes = 6;
+
+// Panel quadrature shared by all instances: m Gauss-Legendre nodes c_x on [0,1],
+// weights b_x, and the monomial coefficients of the Lagrange basis,
+// l_y(u) = sum_k lc[y][k] u^k.
+struct PanelRule {
+  int m;
+  int lawson;               // 0: exponential collocation, 1: integrating factor
+  double c[kMaxNodes];
+  double b[kMaxNodes];
+  double lc[kMaxNodes][kMaxNodes];
+  double A[kMaxNodes][kMaxNodes];   // int_0^{c_x} l_y(u) du (Lawson)
+};
+
+enum TauMode {
+  TAU_INIT = 0,     // s_x = E_x s_b
+  TAU_STEP = 1,     // s_x = E_x s_b - sum_y W_xy S_y   (+ max|change|, max|s|)
+  TAU_END = 2,      // out = E_e s_b - sum_y We_y S_y
+  TAU_LAMT = 3,     // s_x (lambda tilde) = sum_y W_yx S_y (lambda) + We_x s_b (a)
+  TAU_APREV = 4,    // out = E_e s_b (a) + sum_x E_x S_x (lambda)
+  TAU_BETA = 5,     // partial += sum_x <S_x(lam), -dE_x sb + sum_y dW_xy R_y> + <a, -dEe sb + sum dWe_y R_y>
+  TAU_LSTEP = 6,    // s_x (lambda) = -R_x (gradient), with max|change|, max|lambda|
+};
+
+// One amplitude segment of one instance (t1: n^2 elements, t2: n^4 elements).
+struct TauProblem {
+  const double* eps;
+  int n;
+  int rank;           // 2 or 4
+  long len;
+  double h;           // panel width beta / P
+  const double* sb;   // panel-start state s_b (or adjoint a_{p+1})
+  const double* S[kMaxNodes];   // residuals (or lambda)
+  const double* R[kMaxNodes];   // residuals for TAU_BETA / gradients for TAU_LSTEP
+  double* s[kMaxNodes];         // node amplitudes (or lambda-tilde / lambda)
+  double* out;                  // end state / previous adjoint state
+  const double* lam_a;          // a_{p+1} for TAU_BETA
+  unsigned long long* maxbits;  // [0] max |change|, [1] max |value| (bit patterns of doubles >= 0)
+  double* partial;              // TAU_BETA: one partial sum per block
+};
+
+// blocks: 1024 elements each, per problem; d_rule is a device copy of the rule
+void launch_tau(const PanelRule* d_rule, int mode, const TauProblem* d_probs, const int* d_prefix, int n_prob,
+                int total_blocks, hipStream_t s);
+hipError_t init_tau_constants();
+
+// Thermal quantities of one instance.
+struct ThermalProblem {
+  int n;
+  const double* eps;
+  const double* h;     // n x n
+  const double* eri;   // n^4, <pq|rs>
+  double mu, beta, thr;
+  double* occ;         // n_p
+  double* wo;          // sqrt(n_p) or 0 when dropped
+  double* wv;          // sqrt(1 - n_p) or 0 when dropped
+  double* fock;        // n x n
+};
+void launch_thermal(const ThermalProblem& p, hipStream_t s);
+
+// out[p,q,r,s] = sum over the product rule of prod_k w_k(slot) * base:
+//   out = (prod w) * dbase + sum_k (prod_{j != k} w_j) dw_k * base
+// For plain blocks pass dbase = base and dw = nullptr.
+struct BlockSpec {
+  int n;
+  int rank;            // 2 or 4
+  char pat[4];         // 'o' or 'v' per slot
+  const double* base;  // unweighted tensor
+  const double* dbase; // derivative of the unweighted tensor (may equal base)
+  const double* wo;
+  const double* wv;
+  const double* dwo;   // may be nullptr
+  const double* dwv;
+  double* out;
+};
+void launch_block(const BlockSpec& b, hipStream_t s);
+
+// u = f - diag(eps) and its derivative du = dh + J[dn] + dJ[n] (restricted Fock)
+void launch_fock_deriv(int n, const double* eri, const double* deri, const double* dh, const double* occ,
+                       const double* docc, double* du, hipStream_t s);
+void launch_u_from_fock(int n, const double* fock, const double* eps, double* u, hipStream_t s);
+
+// sum of `count` doubles into *out (single block, deterministic)
+void launch_sum(const double* x, int count, double* out, hipStream_t s);
+// element-wise: y = a * x + b * y over len doubles
+void launch_axpby(long len, double a, const double* x, double b, double* y, hipStream_t s);
+
+}  // namespace ftcc

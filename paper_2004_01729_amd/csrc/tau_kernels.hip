@@ -1,0 +1,393 @@
+// Imaginary-time kernels: thermal blocks and the exponential-collocation propagator.
+//
+// Propagator weights for one amplitude with orbital-energy difference D and
+// panel width h (composite exponential Gauss collocation of the integral
+// equation eqn:smu; nodes c_x, Lagrange basis l_y(u) = sum_k lc[y][k] u^k):
+//   E_x  = exp(-D h c_x)
+//   W_xy = h int_0^{c_x} exp(D h (u - c_x)) l_y(u) du
+//        = h sum_k lc[y][k] c_x^(k+1) k! phi_{k+1}(-D h c_x)
+//   We_y = h sum_k lc[y][k] k! phi_{k+1}(-D h)
+// with phi_k(z) = int_0^1 exp((1-t) z) t^(k-1) / (k-1)! dt.  phi_k is summed by
+// its Taylor series for |z| <= 4 and by the recurrence
+// phi_{k+1} = (phi_k - 1/k!) / z from phi_1 = expm1(z)/z otherwise (both
+// directions are well conditioned there).  The h-derivative used by the beta
+// response is d/dh [h phi_{k+1}(a h)] = (z - k) phi_{k+1}(z) + 1/k!.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "tau_kernels.h"
+
+namespace ftcc {
+
+__constant__ double c_inv_fact[48];
+
+// 1/k! table; must be uploaded on each device before the first propagator launch
+hipError_t init_tau_constants() {
+  double f[48];
+  f[0] = 1.0;
+  for (int k = 1; k < 48; ++k) f[k] = f[k - 1] / k;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_inv_fact), f, sizeof(f));
+}
+
+// phi[k] = phi_k(z) for k = 1..kmax
+__device__ __forceinline__ void phi_all(double z, int kmax, double* phi) {
+  if (fabs(z) <= 4.0) {
+    for (int k = 1; k <= kmax; ++k) {
+      double acc = c_inv_fact[k + 34];
+#pragma unroll 4
+      for (int j = 33; j >= 0; --j) acc = fma(acc, z, c_inv_fact[j + k]);
+      phi[k] = acc;
+    }
+  } else {
+    double p = expm1(z) / z;
+    phi[1] = p;
+    for (int k = 1; k < kmax; ++k) {
+      p = (p - c_inv_fact[k]) / z;
+      phi[k + 1] = p;
+    }
+  }
+}
+
+struct Weights {
+  double E[kMaxNodes], W[kMaxNodes][kMaxNodes], We[kMaxNodes], Ee;
+};
+
+// coefficients gx[x][y][k] = lc[y][k] c_x^(k+1) k!  (x = m: the panel end, c = 1)
+__device__ __forceinline__ double gcoef(const PanelRule& R, int x, int y, int k) {
+  const double cx = (x < R.m) ? R.c[x] : 1.0;
+  double p = cx;
+  for (int t = 0; t < k; ++t) p *= cx;
+  return R.lc[y][k] * p / c_inv_fact[k];
+}
+
+__device__ void weights(const PanelRule& R, double D, double h, Weights& w, bool deriv) {
+  const int m = R.m;
+  double phi[kMaxNodes + 1];
+  for (int x = 0; x <= m; ++x) {
+    const double cx = (x < m) ? R.c[x] : 1.0;
+    const double z = -D * h * cx;
+    double e = exp(z);
+    if (deriv) e = -D * cx * e;            // dE/dh
+    if (x < m) w.E[x] = e; else w.Ee = e;
+    if (R.lawson) {
+      for (int y = 0; y < m; ++y) {
+        const double arg = D * h * (R.c[y] - cx);
+        const double a = (x < m) ? R.A[x][y] : R.b[y];
+        const double v = deriv ? a * exp(arg) * (1.0 + arg) : h * a * exp(arg);
+        if (x < m) w.W[x][y] = v; else w.We[y] = v;
+      }
+      continue;
+    }
+    phi_all(z, m, phi);
+    for (int y = 0; y < m; ++y) {
+      double acc = 0.0;
+      for (int k = 0; k < m; ++k) {
+        const double g = gcoef(R, x, y, k);
+        acc += deriv ? g * ((z - k) * phi[k + 1] + c_inv_fact[k]) : g * phi[k + 1];
+      }
+      if (!deriv) acc *= h;
+      if (x < m) w.W[x][y] = acc; else w.We[y] = acc;
+    }
+  }
+}
+
+__device__ __forceinline__ double delta_of(const TauProblem& P, long e) {
+  const int n = P.n;
+  if (P.rank == 2) {
+    const int a = (int)(e % n), i = (int)(e / n);
+    return P.eps[a] - P.eps[i];
+  }
+  const int b = (int)(e % n);
+  long r = e / n;
+  const int a = (int)(r % n);
+  r /= n;
+  const int j = (int)(r % n);
+  const int i = (int)(r / n);
+  return P.eps[a] + P.eps[b] - P.eps[i] - P.eps[j];
+}
+
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax(p, (unsigned long long)__double_as_longlong(v));
+}
+
+__global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ rule, int mode,
+                                                  const TauProblem* __restrict__ probs,
+                                                  const int* __restrict__ prefix, int n_prob) {
+  int lo = 0, hi = n_prob - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const TauProblem& P = probs[lo];
+  const PanelRule R = *rule;
+  const int m = R.m;
+  const long base = (long)(b - prefix[lo]) * 1024;
+  double mchg = 0.0, mval = 0.0, acc = 0.0;
+  for (int u = 0; u < 4; ++u) {
+    const long e = base + u * 256 + threadIdx.x;
+    if (e >= P.len) break;
+    const double sb = P.sb ? P.sb[e] : 0.0;
+    double Sv[kMaxNodes];
+    bool any = (sb != 0.0);
+    for (int y = 0; y < m; ++y) {
+      Sv[y] = P.S[y] ? P.S[y][e] : 0.0;
+      any = any || (Sv[y] != 0.0);
+    }
+    if (mode == TAU_LSTEP) {
+      for (int x = 0; x < m; ++x) {
+        const double nv = -P.R[x][e];
+        mchg = fmax(mchg, fabs(nv - P.s[x][e]));
+        mval = fmax(mval, fabs(nv));
+        P.s[x][e] = nv;
+      }
+      continue;
+    }
+    if (mode == TAU_BETA) {
+      double Rv[kMaxNodes];
+      bool anyb = any || (P.lam_a && P.lam_a[e] != 0.0);
+      for (int y = 0; y < m; ++y) {
+        Rv[y] = P.R[y][e];
+        anyb = anyb || (Rv[y] != 0.0);
+      }
+      if (!anyb) continue;
+      Weights w;
+      weights(R, delta_of(P, e), P.h, w, true);
+      for (int x = 0; x < m; ++x) {
+        double f = (sb != 0.0) ? -w.E[x] * sb : 0.0;
+        for (int y = 0; y < m; ++y)
+          if (Rv[y] != 0.0) f += w.W[x][y] * Rv[y];
+        acc += Sv[x] * f;
+      }
+      if (P.lam_a) {
+        double f = (sb != 0.0) ? -w.Ee * sb : 0.0;
+        for (int y = 0; y < m; ++y)
+          if (Rv[y] != 0.0) f += w.We[y] * Rv[y];
+        acc += P.lam_a[e] * f;
+      }
+      continue;
+    }
+    if (!any) {
+      // structurally zero (dropped slots, or zero start): outputs stay zero
+      if (mode == TAU_INIT || mode == TAU_LAMT) {
+        for (int x = 0; x < m; ++x) P.s[x][e] = 0.0;
+      } else if (mode == TAU_STEP) {
+        for (int x = 0; x < m; ++x) {
+          mchg = fmax(mchg, fabs(P.s[x][e]));
+          P.s[x][e] = 0.0;
+        }
+      } else {
+        P.out[e] = 0.0;
+      }
+      continue;
+    }
+    Weights w;
+    weights(R, delta_of(P, e), P.h, w, false);
+    if (mode == TAU_INIT) {
+      for (int x = 0; x < m; ++x) P.s[x][e] = (sb != 0.0) ? w.E[x] * sb : 0.0;
+    } else if (mode == TAU_STEP) {
+      for (int x = 0; x < m; ++x) {
+        double v = (sb != 0.0) ? w.E[x] * sb : 0.0;
+        for (int y = 0; y < m; ++y)
+          if (Sv[y] != 0.0) v -= w.W[x][y] * Sv[y];
+        mchg = fmax(mchg, fabs(v - P.s[x][e]));
+        mval = fmax(mval, fabs(v));
+        P.s[x][e] = v;
+      }
+    } else if (mode == TAU_END) {
+      double v = (sb != 0.0) ? w.Ee * sb : 0.0;
+      for (int y = 0; y < m; ++y)
+        if (Sv[y] != 0.0) v -= w.We[y] * Sv[y];
+      P.out[e] = v;
+    } else if (mode == TAU_LAMT) {
+      for (int x = 0; x < m; ++x) {
+        double v = (sb != 0.0) ? w.We[x] * sb : 0.0;
+        for (int y = 0; y < m; ++y)
+          if (Sv[y] != 0.0) v += w.W[y][x] * Sv[y];
+        P.s[x][e] = v;
+      }
+    } else if (mode == TAU_APREV) {
+      double v = (sb != 0.0) ? w.Ee * sb : 0.0;
+      for (int x = 0; x < m; ++x)
+        if (Sv[x] != 0.0) v += w.E[x] * Sv[x];
+      P.out[e] = v;
+    }
+  }
+  // block reductions
+  __shared__ double r0[256], r1[256];
+  if (mode == TAU_STEP || mode == TAU_LSTEP) {
+    r0[threadIdx.x] = mchg;
+    r1[threadIdx.x] = mval;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) {
+        r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + s]);
+        r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + s]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      atomic_max_pos(P.maxbits, r0[0]);
+      atomic_max_pos(P.maxbits + 1, r1[0]);
+    }
+  } else if (mode == TAU_BETA) {
+    r0[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) r0[threadIdx.x] += r0[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) P.partial[b - prefix[lo]] = r0[0];
+  }
+}
+
+void launch_tau(const PanelRule* d_rule, int mode, const TauProblem* d_probs, const int* d_prefix, int n_prob,
+                int total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(tau_kernel, dim3(total_blocks), dim3(256), 0, s, d_rule, mode, d_probs, d_prefix, n_prob);
+}
+
+// ------------------------------------------------------------------ thermal quantities
+__global__ void occ_kernel(ThermalProblem P) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P.n) return;
+  const double x = P.beta * (P.eps[p] - P.mu);
+  // n = 1 / (1 + e^x), 1 - n = 1 / (1 + e^-x), each without cancellation
+  double nocc, nvir;
+  if (x > 0.0) {
+    const double t = exp(-x);
+    nocc = t / (1.0 + t);
+    nvir = 1.0 / (1.0 + t);
+  } else {
+    const double t = exp(x);
+    nocc = 1.0 / (1.0 + t);
+    nvir = t / (1.0 + t);
+  }
+  P.occ[p] = nocc;
+  P.wo[p] = (nocc > P.thr) ? sqrt(nocc) : 0.0;
+  P.wv[p] = (nvir > P.thr) ? sqrt(nvir) : 0.0;
+}
+
+// f_pq = h_pq + sum_r (2 <pr|qr> - <pr|rq>) n_r
+__global__ void fock_kernel(ThermalProblem P) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  const int n = P.n;
+  if (q >= n) return;
+  double acc = P.h[(long)p * n + q];
+  for (int r = 0; r < n; ++r) {
+    const double d = P.eri[(((long)p * n + r) * n + q) * n + r];
+    const double x = P.eri[(((long)p * n + r) * n + r) * n + q];
+    acc += (2.0 * d - x) * P.occ[r];
+  }
+  P.fock[(long)p * n + q] = acc;
+}
+
+void launch_thermal(const ThermalProblem& p, hipStream_t s) {
+  hipLaunchKernelGGL(occ_kernel, dim3((p.n + 63) / 64), dim3(64), 0, s, p);
+  hipLaunchKernelGGL(fock_kernel, dim3((p.n + 63) / 64, p.n), dim3(64), 0, s, p);
+}
+
+// du_pq = dh_pq + sum_r (2 <pr|qr> - <pr|rq>) dn_r + sum_r (2 d<pr|qr> - d<pr|rq>) n_r
+__global__ void fock_deriv_kernel(int n, const double* eri, const double* deri, const double* dh,
+                                  const double* occ, const double* docc, double* du) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (q >= n) return;
+  double acc = dh ? dh[(long)p * n + q] : 0.0;
+  for (int r = 0; r < n; ++r) {
+    const long id = (((long)p * n + r) * n + q) * n + r;
+    const long ix = (((long)p * n + r) * n + r) * n + q;
+    if (docc) acc += (2.0 * eri[id] - eri[ix]) * docc[r];
+    if (deri) acc += (2.0 * deri[id] - deri[ix]) * occ[r];
+  }
+  du[(long)p * n + q] = acc;
+}
+
+void launch_fock_deriv(int n, const double* eri, const double* deri, const double* dh, const double* occ,
+                       const double* docc, double* du, hipStream_t s) {
+  hipLaunchKernelGGL(fock_deriv_kernel, dim3((n + 63) / 64, n), dim3(64), 0, s, n, eri, deri, dh, occ, docc, du);
+}
+
+__global__ void u_from_fock_kernel(int n, const double* fock, const double* eps, double* u) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long)n * n) return;
+  const int p = (int)(e / n), q = (int)(e % n);
+  u[e] = fock[e] - (p == q ? eps[p] : 0.0);
+}
+
+void launch_u_from_fock(int n, const double* fock, const double* eps, double* u, hipStream_t s) {
+  const long len = (long)n * n;
+  hipLaunchKernelGGL(u_from_fock_kernel, dim3((len + 255) / 256), dim3(256), 0, s, n, fock, eps, u);
+}
+
+// ------------------------------------------------------------------ weighted blocks
+__global__ void block_kernel(BlockSpec B) {
+  const long len = (B.rank == 4) ? (long)B.n * B.n * B.n * B.n : (long)B.n * B.n;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  int idx[4];
+  long r = e;
+  for (int k = B.rank - 1; k >= 0; --k) {
+    idx[k] = (int)(r % B.n);
+    r /= B.n;
+  }
+  double w[4], dw[4];
+  for (int k = 0; k < B.rank; ++k) {
+    const bool o = (B.pat[k] == 'o');
+    w[k] = o ? B.wo[idx[k]] : B.wv[idx[k]];
+    const double* dv = o ? B.dwo : B.dwv;
+    dw[k] = dv ? dv[idx[k]] : 0.0;
+  }
+  double prod = 1.0;
+  for (int k = 0; k < B.rank; ++k) prod *= w[k];
+  double v = B.dbase ? prod * B.dbase[e] : 0.0;
+  if (B.dwo || B.dwv) {
+    for (int k = 0; k < B.rank; ++k) {
+      if (dw[k] == 0.0) continue;
+      double pk = dw[k];
+      for (int j = 0; j < B.rank; ++j)
+        if (j != k) pk *= w[j];
+      v += pk * B.base[e];
+    }
+  }
+  B.out[e] = v;
+}
+
+void launch_block(const BlockSpec& b, hipStream_t s) {
+  const long len = (b.rank == 4) ? (long)b.n * b.n * b.n * b.n : (long)b.n * b.n;
+  hipLaunchKernelGGL(block_kernel, dim3((len + 255) / 256), dim3(256), 0, s, b);
+}
+
+// ------------------------------------------------------------------ small utilities
+__global__ void sum_kernel(const double* x, int count, double* out) {
+  __shared__ double r[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) a += x[i];
+  r[threadIdx.x] = a;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) r[threadIdx.x] += r[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = r[0];
+}
+
+void launch_sum(const double* x, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, s, x, count, out);
+}
+
+__global__ void axpby_kernel(long len, double a, const double* x, double b, double* y) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  const double xv = (a != 0.0) ? a * x[e] : 0.0;
+  y[e] = (b != 0.0) ? xv + b * y[e] : xv;
+}
+
+void launch_axpby(long len, double a, const double* x, double b, double* y, hipStream_t s) {
+  if (len <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3((len + 255) / 256), dim3(256), 0, s, len, a, x, b, y);
+}
+
+}  // namespace ftcc

@@ -1,0 +1,237 @@
+"""Python binding of libftcc.so (argument marshalling only).
+
+Every function here converts numpy arrays to host pointers and calls the C ABI
+declared in include/ftcc.h; all arithmetic runs in the library's HIP kernels.
+The library is loaded from this package directory; if it is missing the import
+fails with an error telling how to build it (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libftcc.so")
+
+_lib = None
+
+OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
+          ENOCONV: "ENOCONV", ENONFINITE: "ENONFINITE"}
+
+
+class FTCCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("n_tau", ctypes.c_int), ("nodes_per_panel", ctypes.c_int), ("propagator", ctypes.c_int),
+                ("occ_thresh", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("checkpoint", ctypes.c_int)]
+
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+_L = ctypes.POINTER(ctypes.c_long)
+
+
+def library():
+    """Load libftcc.so once (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2004_01729_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "ftcc_default_options": (None, [ctypes.POINTER(Options)]),
+        "ftcc_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(Options)]),
+        "ftcc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+        "ftcc_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+        "ftcc_set_hamiltonian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
+        "ftcc_solve_amplitudes": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _I, _I]),
+        "ftcc_grand_potential": (ctypes.c_int, [ctypes.c_void_p, _D, _D]),
+        "ftcc_get_amplitudes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D]),
+        "ftcc_lambda": (ctypes.c_int, [ctypes.c_void_p, _I, _I]),
+        "ftcc_get_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]),
+        "ftcc_response": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D), _D]),
+        "ftcc_eval_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                              _D, _D, _D, _D, _D]),
+        "ftcc_time_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D]),
+        "ftcc_stats": (ctypes.c_int, [ctypes.c_void_p, _L, _L, _D, _D]),
+        "ftcc_last_error": (ctypes.c_char_p, []),
+        "ftcc_abi_version": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the C header declares (used by the CPU-side load test)."""
+    return ["ftcc_default_options", "ftcc_create", "ftcc_destroy", "ftcc_set_stream", "ftcc_set_hamiltonian",
+            "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
+            "ftcc_get_lambda", "ftcc_response", "ftcc_eval_residual", "ftcc_time_residual", "ftcc_stats",
+            "ftcc_last_error", "ftcc_abi_version"]
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != tuple(shape):
+        a = a.reshape(shape)
+    return a
+
+
+def _check(rc, lib=None, allow=()):
+    if rc != OK and rc not in allow:
+        lib = lib or library()
+        raise FTCCError(rc, lib.ftcc_last_error().decode())
+    return rc
+
+
+def default_options(**kw):
+    o = Options()
+    library().ftcc_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One ftcc_ctx: n_instances problems solved together on one GPU."""
+
+    def __init__(self, n_instances=1, device=0, **options):
+        self.lib = library()
+        self.opt = default_options(**options)
+        self.B = int(n_instances)
+        self._h = ctypes.c_void_p()
+        _check(self.lib.ftcc_create(ctypes.byref(self._h), int(device), self.B, ctypes.byref(self.opt)))
+        self.n = None
+
+    def close(self):
+        if self._h:
+            self.lib.ftcc_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream_ptr):
+        _check(self.lib.ftcc_set_stream(self._h, ctypes.c_void_p(stream_ptr)))
+
+    def set_hamiltonian(self, inst, h, eri, eps):
+        h = _f64(h)
+        n = h.shape[0]
+        eri = _f64(eri, (n, n, n, n))
+        eps = _f64(eps, (n,))
+        _check(self.lib.ftcc_set_hamiltonian(self._h, int(inst), n, _ptr(h), _ptr(eri), _ptr(eps)))
+        self.n = n
+
+    def solve(self, mu, beta, raise_on_status=True):
+        mu = _f64(np.broadcast_to(np.asarray(mu, float), (self.B,)))
+        beta = _f64(np.broadcast_to(np.asarray(beta, float), (self.B,)))
+        its = np.zeros(self.B, dtype=np.int32)
+        st = np.zeros(self.B, dtype=np.int32)
+        rc = self.lib.ftcc_solve_amplitudes(self._h, _ptr(mu), _ptr(beta), its.ctypes.data_as(_I),
+                                           st.ctypes.data_as(_I))
+        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE))
+        return its, st
+
+    def grand_potential(self):
+        om = np.zeros(self.B)
+        parts = np.zeros((self.B, 3))
+        _check(self.lib.ftcc_grand_potential(self._h, _ptr(om), _ptr(parts)))
+        return om, parts
+
+    def amplitudes(self, inst, node):
+        n = self.n
+        t1 = np.zeros((n, n))
+        t2 = np.zeros((n, n, n, n))
+        _check(self.lib.ftcc_get_amplitudes(self._h, int(inst), int(node), _ptr(t1), _ptr(t2)))
+        return t1, t2
+
+    def lam(self, raise_on_status=True):
+        its = np.zeros(self.B, dtype=np.int32)
+        st = np.zeros(self.B, dtype=np.int32)
+        rc = self.lib.ftcc_lambda(self._h, its.ctypes.data_as(_I), st.ctypes.data_as(_I))
+        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE))
+        return its, st
+
+    def get_lambda(self, inst, node):
+        n = self.n
+        out = [np.zeros((n, n)), np.zeros((n,) * 4), np.zeros((n, n)), np.zeros((n,) * 4)]
+        _check(self.lib.ftcc_get_lambda(self._h, int(inst), int(node), *[_ptr(a) for a in out]))
+        return out
+
+    def response(self, want_mu=True, want_beta=True, want_h=True, deri_dtheta=None, dh_dtheta=None):
+        B, n = self.B, self.n
+        dmu = np.zeros(B) if want_mu else None
+        dbeta = np.zeros(B) if want_beta else None
+        dh = np.zeros((B, n, n)) if want_h else None
+        dth = None
+        keep = []
+        p_deri = p_dh = None
+        if deri_dtheta is not None or dh_dtheta is not None:
+            dth = np.zeros(B)
+            if deri_dtheta is not None:
+                arrs = [None if a is None else _f64(a, (n, n, n, n)) for a in deri_dtheta]
+                keep += arrs
+                p_deri = (_D * B)(*[ctypes.cast(None, _D) if a is None else _ptr(a) for a in arrs])
+            if dh_dtheta is not None:
+                arrs = [None if a is None else _f64(a, (n, n)) for a in dh_dtheta]
+                keep += arrs
+                p_dh = (_D * B)(*[ctypes.cast(None, _D) if a is None else _ptr(a) for a in arrs])
+        nul = ctypes.cast(None, _D)
+        _check(self.lib.ftcc_response(self._h, _ptr(dmu) if dmu is not None else nul,
+                                      _ptr(dbeta) if dbeta is not None else nul,
+                                      _ptr(dh) if dh is not None else nul,
+                                      p_deri, p_dh, _ptr(dth) if dth is not None else nul))
+        return dict(mu=dmu, beta=dbeta, h=dh, theta=dth)
+
+    def eval_residual(self, inst, mu, beta, t1, t2):
+        n = self.n
+        t1 = _f64(t1, (n, n))
+        t2 = _f64(t2, (n, n, n, n))
+        S1 = np.zeros((n, n))
+        S2 = np.zeros((n, n, n, n))
+        E = np.zeros(1)
+        _check(self.lib.ftcc_eval_residual(self._h, int(inst), float(mu), float(beta), _ptr(t1), _ptr(t2),
+                                           _ptr(S1), _ptr(S2), _ptr(E)))
+        return S1, S2, float(E[0])
+
+    def time_residual(self, reps):
+        sec = np.zeros(1)
+        fl = np.zeros(1)
+        _check(self.lib.ftcc_time_residual(self._h, int(reps), _ptr(sec), _ptr(fl)))
+        return float(sec[0]), float(fl[0])
+
+    def stats(self):
+        r = ctypes.c_long()
+        v = ctypes.c_long()
+        ts = ctypes.c_double()
+        tl = ctypes.c_double()
+        _check(self.lib.ftcc_stats(self._h, ctypes.byref(r), ctypes.byref(v), ctypes.byref(ts), ctypes.byref(tl)))
+        return dict(resid_evals=r.value, vjp_evals=v.value, solve_seconds=ts.value, lambda_seconds=tl.value)
