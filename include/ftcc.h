@@ -131,6 +131,13 @@ int ftcc_eval_residual(ftcc_ctx* ctx, int inst, double mu, double beta, const do
  * (all slots).  Either may be NULL. */
 int ftcc_time_residual(ftcc_ctx* ctx, int reps, double* seconds_out, double* flops_out);
 
+/* HIP-event timing of the dominant kernel (the 128x128 FP64-MFMA GEMM tile
+ * configuration, which carries the O(n^6) contractions) on the context's
+ * stream.  Returns the algorithmic flops (sum of 2*M*N*K), the summed launch
+ * durations and the launch count accumulated since the previous call, then
+ * resets the counters and enables (enable != 0) or disables recording. */
+int ftcc_kernel_profile(ftcc_ctx* ctx, int enable, double* flops, double* seconds, long* launches);
+
 /* Counters of the last solve / lambda: residual evaluations (instance x node),
  * backward evaluations, and device seconds spent in each phase. */
 int ftcc_stats(ftcc_ctx* ctx, long* resid_evals, long* vjp_evals, double* solve_seconds, double* lambda_seconds);

@@ -104,6 +104,23 @@ struct Scratch {
   double* dot_partial = nullptr;        // >= n_prob * 64 doubles
 };
 
+// HIP-event timing of the dominant kernel (the 128x128 FP64-MFMA GEMM tile
+// configuration): events are recorded around each such launch on the launch
+// stream and harvested at the next host synchronisation.
+struct KernelProfiler {
+  bool enabled = false;
+  std::vector<hipEvent_t> ev;   // pairs
+  std::vector<double> pending_flops;
+  int used = 0;
+  double flops = 0.0, seconds = 0.0;
+  long launches = 0;
+  void reset();
+  void record_begin(hipStream_t s);
+  void record_end(hipStream_t s, double flops);
+  void harvest();               // call after the stream has been synchronised
+  ~KernelProfiler();
+};
+
 class Executor {
  public:
   Executor() = default;
@@ -122,6 +139,7 @@ class Executor {
   void run_forward(hipStream_t s) const { run(fwd_, s); }
   void run_backward(hipStream_t s) const { run(bwd_, s); }
 
+  void set_profiler(KernelProfiler* p) { prof_ = p; }
   double gemm_flops_forward() const;
   double gemm_flops_backward() const;
   int n_launches_forward() const { return (int)fwd_.size(); }
@@ -146,6 +164,7 @@ class Executor {
   std::map<std::pair<int, std::string>, PerProb> const_cache_;
   std::vector<Launch> setup_, fwd_, bwd_;
   std::vector<void*> owned_;
+  KernelProfiler* prof_ = nullptr;
 };
 
 }  // namespace ftcc

@@ -514,8 +514,12 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
       case Launch::FILL:
         launch_permute((const PermProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
         break;
-      case Launch::GEMM:
+      case Launch::GEMM: {
+        const bool timed = prof_ && prof_->enabled && l.cfg == 0;
+        if (timed) prof_->record_begin(s);
         launch_gemm(l.cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
+        if (timed) prof_->record_end(s, l.flops);
+      }
         if (l.splitk_blocks > 0)
           launch_splitk_reduce((const GemmProblem*)l.d_desc, l.d_prefix2, l.n_prob, l.splitk_blocks, s);
         break;
@@ -524,6 +528,50 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
         break;
     }
   }
+}
+
+// ------------------------------------------------------------------ profiler
+void KernelProfiler::reset() {
+  used = 0;
+  pending_flops.clear();
+  flops = seconds = 0.0;
+  launches = 0;
+}
+
+void KernelProfiler::record_begin(hipStream_t s) {
+  if (used + 2 > (int)ev.size()) {
+    // pool full: wait for the stream and harvest before reusing events
+    FTCC_HIP(hipStreamSynchronize(s));
+    harvest();
+    if (ev.size() < 8192) {
+      const size_t old = ev.size();
+      ev.resize(old ? old * 2 : 512);
+      for (size_t k = old; k < ev.size(); ++k) FTCC_HIP(hipEventCreate(&ev[k]));
+    }
+  }
+  FTCC_HIP(hipEventRecord(ev[used], s));
+}
+
+void KernelProfiler::record_end(hipStream_t s, double f) {
+  FTCC_HIP(hipEventRecord(ev[used + 1], s));
+  pending_flops.push_back(f);
+  used += 2;
+}
+
+void KernelProfiler::harvest() {
+  for (size_t k = 0; k < pending_flops.size(); ++k) {
+    float ms = 0.f;
+    FTCC_HIP(hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]));
+    seconds += ms * 1e-3;
+    flops += pending_flops[k];
+    ++launches;
+  }
+  pending_flops.clear();
+  used = 0;
+}
+
+KernelProfiler::~KernelProfiler() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 
 double Executor::gemm_flops_forward() const {

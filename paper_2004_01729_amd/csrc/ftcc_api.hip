@@ -237,6 +237,7 @@ struct ftcc_ctx {
   std::map<int, std::pair<TauProblem*, int*>> tau_desc;
   std::map<int, int> tau_blocks;
   int* d_active = nullptr;                    // [B]
+  KernelProfiler prof;
   long resid_evals = 0, vjp_evals = 0;
   double t_solve = 0.0, t_lambda = 0.0;
   size_t bytes = 0;
@@ -279,7 +280,10 @@ int run_guarded(const std::function<void()>& f) {
   }
 }
 
-void sync(ftcc_ctx* c) { FTCC_HIP(hipStreamSynchronize(c->stream)); }
+void sync(ftcc_ctx* c) {
+  FTCC_HIP(hipStreamSynchronize(c->stream));
+  if (c->prof.enabled) c->prof.harvest();
+}
 
 // ------------------------------------------------------------------ thermal set-up
 void thermal_setup(ftcc_ctx* c, int i) {
@@ -524,8 +528,10 @@ void build(ftcc_ctx* c) {
   auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
   c->ex_main.reset(new Executor());
   c->ex_main->build(&prog, probs, bind_main, &c->scratch, calloc_, true, ugrads);
+  c->ex_main->set_profiler(&c->prof);
   c->ex_d.reset(new Executor());
   c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {});
+  c->ex_d->set_profiler(&c->prof);
 
   // propagator descriptors: one per (instance, segment) for each mode's buffer roles
   c->built = true;
@@ -1178,6 +1184,19 @@ int ftcc_time_residual(ftcc_ctx* c, int reps, double* seconds_out, double* flops
     FTCC_HIP(hipEventDestroy(e1));
     if (seconds_out) *seconds_out = ms * 1e-3;
     if (flops_out) *flops_out = c->ex_main->gemm_flops_forward();
+  });
+}
+
+int ftcc_kernel_profile(ftcc_ctx* c, int enable, double* flops, double* seconds, long* launches) {
+  return run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    FTCC_HIP(hipSetDevice(c->device));
+    sync(c);
+    if (flops) *flops = c->prof.flops;
+    if (seconds) *seconds = c->prof.seconds;
+    if (launches) *launches = c->prof.launches;
+    c->prof.reset();
+    c->prof.enabled = enable != 0;
   });
 }
 

@@ -64,6 +64,7 @@ def library():
                                               _D, _D, _D, _D, _D]),
         "ftcc_time_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D]),
         "ftcc_stats": (ctypes.c_int, [ctypes.c_void_p, _L, _L, _D, _D]),
+        "ftcc_kernel_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D, _L]),
         "ftcc_last_error": (ctypes.c_char_p, []),
         "ftcc_abi_version": (ctypes.c_int, []),
     }
@@ -80,6 +81,7 @@ def exported_symbols():
     return ["ftcc_default_options", "ftcc_create", "ftcc_destroy", "ftcc_set_stream", "ftcc_set_hamiltonian",
             "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
             "ftcc_get_lambda", "ftcc_response", "ftcc_eval_residual", "ftcc_time_residual", "ftcc_stats",
+            "ftcc_kernel_profile",
             "ftcc_last_error", "ftcc_abi_version"]
 
 
@@ -227,6 +229,15 @@ class Context:
         fl = np.zeros(1)
         _check(self.lib.ftcc_time_residual(self._h, int(reps), _ptr(sec), _ptr(fl)))
         return float(sec[0]), float(fl[0])
+
+    def kernel_profile(self, enable):
+        """Totals of the dominant GEMM kernel since the previous call; then enable/disable."""
+        fl = ctypes.c_double()
+        sec = ctypes.c_double()
+        nl = ctypes.c_long()
+        _check(self.lib.ftcc_kernel_profile(self._h, int(enable), ctypes.byref(fl), ctypes.byref(sec),
+                                            ctypes.byref(nl)))
+        return dict(flops=fl.value, seconds=sec.value, launches=nl.value)
 
     def stats(self):
         r = ctypes.c_long()
