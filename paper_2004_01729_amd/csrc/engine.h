@@ -87,6 +87,7 @@ struct Launch {
   int* d_prefix2 = nullptr;
   double* d_partial = nullptr;
   double flops = 0.0;
+  float tuned_ms = 0.f;
   std::string tag;
 };
 
@@ -104,8 +105,8 @@ struct Scratch {
   double* dot_partial = nullptr;        // >= n_prob * 64 doubles
 };
 
-// HIP-event timing of the dominant kernel (the 128x128 FP64-MFMA GEMM tile
-// configuration): events are recorded around each such launch on the launch
+// HIP-event timing of the dominant kernel (the FP64-MFMA GEMM with 128x128
+// tiles, BK 16 or 32): events are recorded around each such launch on the launch
 // stream and harvested at the next host synchronisation.
 struct KernelProfiler {
   bool enabled = false;
@@ -131,10 +132,15 @@ class Executor {
   // const_alloc(inst, count) returns a persistent per-instance buffer for a
   // permuted copy of a constant.  const_grads lists constants whose gradients
   // the backward list must produce.
+  // cache_alloc(count) (may be empty) provides buffers for reused permuted copies of
+  // value operands, up to cache_budget bytes in total.
   void build(const Program* prog, const std::vector<ProblemRef>& probs, Binder bind, Scratch* scratch,
              std::function<double*(int inst, size_t count)> const_alloc, bool want_backward,
-             const std::vector<int>& const_grads);
+             const std::vector<int>& const_grads, std::function<double*(size_t)> cache_alloc = nullptr,
+             size_t cache_budget = 0);
 
+  // time the candidate GEMM tile configurations of every large GEMM launch and keep the best
+  void autotune(hipStream_t s);
   void run_setup(hipStream_t s) const { run(setup_, s); }
   void run_forward(hipStream_t s) const { run(fwd_, s); }
   void run_backward(hipStream_t s) const { run(bwd_, s); }
@@ -149,19 +155,30 @@ class Executor {
   void run(const std::vector<Launch>& L, hipStream_t s) const;
   void contract(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
                 const PerProb& A, const std::string& ai, int a_const, const PerProb* B, const std::string& bi,
-                int b_const, bool acc, const std::string& tag);
+                int b_const, bool acc, const std::string& tag, int a_val = -1, int b_val = -1);
+  PerProb value_permuted(std::vector<Launch>& dst, int tensor, const PerProb& X, const std::string& xi,
+                         const std::string& yi, const PerProb& scratch, const std::string& tag);
   void perm(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
             const std::string& yi, double alpha, double beta, const std::vector<const double*>* scale,
             const std::string& tag);
   void fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag);
   PerProb const_permuted(int tensor, const PerProb& X, const std::string& xi, const std::string& yi);
   void* upload(const void* host, size_t bytes);
+  void dump_plan() const;
 
   const Program* prog_ = nullptr;
   std::vector<ProblemRef> probs_;
   Scratch* scratch_ = nullptr;
   std::function<double*(int, size_t)> const_alloc_;
   std::map<std::pair<int, std::string>, PerProb> const_cache_;
+  struct CacheEntry {
+    PerProb buf;
+    int version;
+  };
+  std::map<std::pair<int, std::string>, CacheEntry> value_cache_;
+  std::vector<int> version_;
+  std::function<double*(size_t)> cache_alloc_;
+  size_t cache_budget_ = 0, cache_bytes_ = 0;
   std::vector<Launch> setup_, fwd_, bwd_;
   std::vector<void*> owned_;
   KernelProfiler* prof_ = nullptr;

@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 
@@ -132,15 +134,19 @@ void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::strin
       for (int k = 0; k < 3; ++k)
         if (q.xs[k] == 1 && q.d[k] > 1) q.tb = k;
     }
+    for (int k = 0; k < 4; ++k) q.div[k] = make_fastdiv((unsigned)q.d[k]);
     prefix[p] = total;
     if (q.tb < 0) {
       const long el = (long)q.d[0] * q.d[1] * q.d[2] * q.d[3];
       total += (int)((el + 1023) / 1024);
     } else {
-      int oth[2], c = 0;
+      int c = 0;
       for (int k = 0; k < 3; ++k)
-        if (k != q.tb) oth[c++] = k;
-      total += ((q.d[3] + 31) / 32) * ((q.d[q.tb] + 31) / 32) * q.d[oth[0]] * q.d[oth[1]];
+        if (k != q.tb) q.oth[c++] = k;
+      const int nt3 = (q.d[3] + 31) / 32, ntb = (q.d[q.tb] + 31) / 32;
+      q.tdiv[0] = make_fastdiv((unsigned)nt3);
+      q.tdiv[1] = make_fastdiv((unsigned)ntb);
+      total += nt3 * ntb * q.d[q.oth[0]] * q.d[q.oth[1]];
     }
   }
   Launch L;
@@ -171,6 +177,7 @@ void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const 
     q.d[3] = (int)ipow(n, rank);
     q.xs[3] = 1;
     q.tb = -1;
+    for (int k = 0; k < 4; ++k) q.div[k] = make_fastdiv((unsigned)q.d[k]);
     q.alpha = 0.0;
     q.beta = 0.0;
     prefix[p] = total;
@@ -221,10 +228,45 @@ Executor::PerProb Executor::const_permuted(int tensor, const PerProb& X, const s
   return Y;
 }
 
+// Permuted copy of a non-constant value operand.  Copies are kept and reused by
+// later consumers until the tensor is written again (its version changes); the
+// operands of the backward program are forward values, fixed during backward.
+Executor::PerProb Executor::value_permuted(std::vector<Launch>& dst, int tensor, const PerProb& X,
+                                           const std::string& xi, const std::string& yi, const PerProb& scratch,
+                                           const std::string& tag) {
+  if (tensor < 0 || !cache_alloc_) {
+    perm(dst, X, xi, scratch, yi, 1.0, 0.0, nullptr, tag);
+    return scratch;
+  }
+  std::string key;
+  for (char c : yi) key.push_back((char)('0' + xi.find(c)));
+  auto k = std::make_pair(tensor, key);
+  auto it = value_cache_.find(k);
+  if (it != value_cache_.end() && it->second.version == version_[tensor]) return it->second.buf;
+  const int np = (int)probs_.size();
+  PerProb Y;
+  if (it != value_cache_.end()) {
+    Y = it->second.buf;
+  } else {
+    size_t bytes = 0;
+    for (int p = 0; p < np; ++p) bytes += sizeof(double) * (size_t)ipow(probs_[p].n, (int)xi.size());
+    if (cache_bytes_ + bytes > cache_budget_) {
+      perm(dst, X, xi, scratch, yi, 1.0, 0.0, nullptr, tag);
+      return scratch;
+    }
+    cache_bytes_ += bytes;
+    for (int p = 0; p < np; ++p) Y.push_back(cache_alloc_((size_t)ipow(probs_[p].n, (int)xi.size())));
+  }
+  perm(dst, X, xi, Y, yi, 1.0, 0.0, nullptr, tag + "(cached)");
+  value_cache_[k] = CacheEntry{Y, version_[tensor]};
+  return Y;
+}
+
 // ------------------------------------------------------------------ lowering: contraction
 void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
                         const PerProb& A, const std::string& ai, int a_const, const PerProb* B,
-                        const std::string& bi, int b_const, bool acc, const std::string& tag) {
+                        const std::string& bi, int b_const, bool acc, const std::string& tag, int a_val,
+                        int b_val) {
   const double beta = acc ? 1.0 : 0.0;
   const int np = (int)probs_.size();
   if (!B) {
@@ -254,10 +296,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     PerProb Bp = *B;
     if (bi != ai) {
       if (b_const >= 0) Bp = const_permuted(b_const, *B, bi, ai);
-      else {
-        perm(dst, *B, bi, scratch_->b, ai, 1.0, 0.0, nullptr, tag + ":permB");
-        Bp = scratch_->b;
-      }
+      else Bp = value_permuted(dst, b_val, *B, bi, ai, scratch_->b, tag + ":permB");
     }
     std::vector<DotProblem> ds(np);
     for (int p = 0; p < np; ++p) {
@@ -314,7 +353,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
       }
 
   // operands in GEMM layout
-  auto place = [&](const PerProb& X, const std::string& xi, int xconst, const std::string& first,
+  auto place = [&](const PerProb& X, const std::string& xi, int xconst, int xval, const std::string& first,
                    const std::string& second, PerProb& scratch, bool& trans, std::string& lay) -> PerProb {
     if (xi == first + second) {
       trans = false;
@@ -329,8 +368,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     trans = false;
     lay = first + second;
     if (xconst >= 0) return const_permuted(xconst, X, xi, lay);
-    perm(dst, X, xi, scratch, lay, 1.0, 0.0, nullptr, tag + ":perm");
-    return scratch;
+    return value_permuted(dst, xval, X, xi, lay, scratch, tag + ":perm");
   };
   // C[M][N] = A[M][K] B[K][N]; with swap, C^T[N][M] = B^T[N][K] A^T[K][M]
   std::string M = best.M, N = best.N, K = best.K;
@@ -338,12 +376,12 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
   bool ta = false, tb = false;
   std::string alay, blay;
   if (!best.swap) {
-    Ap = place(A, ai, a_const, M, K, scratch_->a, ta, alay);     // ta: stored [K][M]
-    Bp = place(*B, bi, b_const, K, N, scratch_->b, tb, blay);    // tb: stored [N][K]
+    Ap = place(A, ai, a_const, a_val, M, K, scratch_->a, ta, alay);     // ta: stored [K][M]
+    Bp = place(*B, bi, b_const, b_val, K, N, scratch_->b, tb, blay);    // tb: stored [N][K]
   } else {
     // rows of C = N letters (from B), cols = M letters (from A)
-    Ap = place(*B, bi, b_const, N, K, scratch_->b, ta, alay);
-    Bp = place(A, ai, a_const, K, M, scratch_->a, tb, blay);
+    Ap = place(*B, bi, b_const, b_val, N, K, scratch_->b, ta, alay);
+    Bp = place(A, ai, a_const, a_val, K, M, scratch_->a, tb, blay);
     std::swap(M, N);
   }
   const bool c_direct = (oi == M + N);
@@ -355,8 +393,8 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
   std::vector<int> prefix(np), prefix2(np);
   int cfg = 0;
   {
-    const long m = ipow(n0, (int)M.size()), nn = ipow(n0, (int)N.size());
-    cfg = (m >= 128 && nn >= 128) ? 0 : 1;
+    const long m = ipow(n0, (int)M.size()), nn = ipow(n0, (int)N.size()), kk = ipow(n0, (int)K.size());
+    cfg = (m >= 128 && nn >= 128) ? (kk >= 512 ? 2 : 0) : 1;
   }
   const int BM = gemm_bm(cfg), BN = gemm_bn(cfg);
   int total = 0, total2 = 0;
@@ -391,6 +429,8 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
       while (ks > 1 && (long)ks * g.M * g.N > ipow(n, 4)) --ks;
       ks = std::max(ks, 1);
     }
+    if ((long)g.M * g.K >= (1L << 31) || (long)g.K * g.N >= (1L << 31) || (long)g.M * g.N >= (1L << 31))
+      throw std::runtime_error("GEMM operand exceeds 2^31 elements: " + tag);
     g.ksplit = ks;
     g.kchunk = (g.K + ks - 1) / ks;
     g.kchunk = ((g.kchunk + 15) / 16) * 16;
@@ -426,7 +466,10 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
 // ------------------------------------------------------------------ build
 void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, Binder bind, Scratch* scratch,
                      std::function<double*(int, size_t)> const_alloc, bool want_backward,
-                     const std::vector<int>& const_grads) {
+                     const std::vector<int>& const_grads, std::function<double*(size_t)> cache_alloc,
+                     size_t cache_budget) {
+  cache_alloc_ = cache_alloc;
+  cache_budget_ = cache_budget;
   if (!prog->finalized()) throw std::runtime_error("Program::finalize() not called");
   prog_ = prog;
   probs_ = probs;
@@ -482,12 +525,18 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
     probs_ = probs;
     scratch_ = scratch;
   }
+  version_.assign(nt, 0);
+  auto vidx = [&](int k) { return (k >= 0 && cidx(k) < 0) ? k : -1; };
   for (const SymOp& o : prog->ops) {
     if (o.setup) continue;
     contract(fwd_, fwd[o.out], o.oi, o.alpha, fwd[o.a], o.ai, cidx(o.a), o.b >= 0 ? &fwd[o.b] : nullptr, o.bi,
-             cidx(o.b), o.accumulate, prog->t[o.out].name);
+             cidx(o.b), o.accumulate, prog->t[o.out].name, vidx(o.a), vidx(o.b));
+    version_[o.out]++;
   }
-  if (!want_backward) return;
+  if (!want_backward) {
+    dump_plan();
+    return;
+  }
   // zero every gradient buffer except the cotangents of the outputs
   for (int k = 0; k < nt; ++k)
     if (need_grad[k] && prog->t[k].kind != T_OUTPUT) fill(bwd_, grd[k], prog->t[k].rank, "zero:" + prog->t[k].name);
@@ -500,9 +549,73 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
       continue;
     }
     if (need_grad[o.a])
-      contract(bwd_, grd[o.a], o.ai, o.alpha, grd[o.out], o.oi, -1, &fwd[o.b], o.bi, cidx(o.b), true, tag + ":dA");
+      contract(bwd_, grd[o.a], o.ai, o.alpha, grd[o.out], o.oi, -1, &fwd[o.b], o.bi, cidx(o.b), true, tag + ":dA",
+               -1, vidx(o.b));
     if (need_grad[o.b])
-      contract(bwd_, grd[o.b], o.bi, o.alpha, fwd[o.a], o.ai, cidx(o.a), &grd[o.out], o.oi, -1, true, tag + ":dB");
+      contract(bwd_, grd[o.b], o.bi, o.alpha, fwd[o.a], o.ai, cidx(o.a), &grd[o.out], o.oi, -1, true, tag + ":dB",
+               vidx(o.a), -1);
+  }
+  dump_plan();
+}
+
+// Autotuner: every grouped GEMM launch with 128x128 tiles is timed on its own
+// descriptors (the real operand pointers and shapes of the program) with each
+// candidate tile configuration, and the fastest is kept.  Outputs written while
+// timing are overwritten by the first real sweep (every tensor's first op
+// overwrites it; gradient buffers are zero-filled before each backward).
+void Executor::autotune(hipStream_t s) {
+  const char* env = std::getenv("FTCC_AUTOTUNE");
+  if (env && env[0] == '0') return;
+  hipEvent_t e0, e1;
+  FTCC_HIP(hipEventCreate(&e0));
+  FTCC_HIP(hipEventCreate(&e1));
+  for (std::vector<Launch>* lst : {&fwd_, &bwd_}) {
+    for (Launch& l : *lst) {
+      if (l.kind != Launch::GEMM || gemm_bm(l.cfg) != 128) continue;
+      int best = l.cfg;
+      float best_ms = 1e30f;
+      for (int cfg : {0, 2}) {
+        launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
+        FTCC_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 2; ++r)
+          launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
+        FTCC_HIP(hipEventRecord(e1, s));
+        FTCC_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        FTCC_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = cfg;
+        }
+      }
+      l.cfg = best;
+      l.tuned_ms = best_ms * 0.5f;
+    }
+  }
+  FTCC_HIP(hipEventDestroy(e0));
+  FTCC_HIP(hipEventDestroy(e1));
+  dump_plan();
+}
+
+// FTCC_PLAN_DUMP=1 prints the lowered launch lists (diagnostics only)
+void Executor::dump_plan() const {
+  const char* env = std::getenv("FTCC_PLAN_DUMP");
+  if (!env || env[0] != '1') return;
+  const char* kinds[] = {"perm", "gemm", "dot", "fill"};
+  const std::pair<const char*, const std::vector<Launch>*> lists[] = {
+      {"setup", &setup_}, {"forward", &fwd_}, {"backward", &bwd_}};
+  for (const auto& pl : lists) {
+    int counts[4] = {0, 0, 0, 0};
+    double fl = 0.0;
+    for (const Launch& l : *pl.second) {
+      counts[l.kind]++;
+      fl += l.flops;
+      std::fprintf(stderr, "[plan] %-8s %-4s cfg=%d ta=%d tb=%d blocks=%d split=%d gflop=%.3f ms=%.3f %s\n",
+                   pl.first, kinds[l.kind], l.cfg, (int)l.ta, (int)l.tb, l.total, l.splitk_blocks > 0,
+                   l.flops * 1e-9, l.tuned_ms, l.tag.c_str());
+    }
+    std::fprintf(stderr, "[plan] %s: %d perm, %d gemm, %d dot, %d fill, %.3f GFLOP\n", pl.first, counts[0],
+                 counts[1], counts[2], counts[3], fl * 1e-9);
   }
 }
 
@@ -515,7 +628,7 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
         launch_permute((const PermProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
         break;
       case Launch::GEMM: {
-        const bool timed = prof_ && prof_->enabled && l.cfg == 0;
+        const bool timed = prof_ && prof_->enabled && gemm_bm(l.cfg) == 128;
         if (timed) prof_->record_begin(s);
         launch_gemm(l.cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
         if (timed) prof_->record_end(s, l.flops);

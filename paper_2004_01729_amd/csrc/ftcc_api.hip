@@ -526,12 +526,19 @@ void build(ftcc_ctx* c) {
     fail(FTCC_EINVAL, "unbound tensor " + d.name);
   };
   auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
+  auto vcache = [c](size_t count) { return c->dalloc(count); };
+  // reuse budget for permuted operand copies: a quarter of the free device memory
+  size_t free_b = 0, total_b = 0;
+  FTCC_HIP(hipMemGetInfo(&free_b, &total_b));
+  const size_t budget = free_b / 4;
   c->ex_main.reset(new Executor());
-  c->ex_main->build(&prog, probs, bind_main, &c->scratch, calloc_, true, ugrads);
+  c->ex_main->build(&prog, probs, bind_main, &c->scratch, calloc_, true, ugrads, vcache, budget);
   c->ex_main->set_profiler(&c->prof);
   c->ex_d.reset(new Executor());
-  c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {});
+  c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {}, vcache, budget / 2);
   c->ex_d->set_profiler(&c->prof);
+  c->ex_main->autotune(c->stream);
+  c->ex_d->autotune(c->stream);
 
   // propagator descriptors: one per (instance, segment) for each mode's buffer roles
   c->built = true;

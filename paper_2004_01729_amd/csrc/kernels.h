@@ -21,8 +21,16 @@ struct GemmProblem {
   double alpha, beta;
 };
 
+// Unsigned 32-bit division by a runtime constant: q = umulhi(x, mul) >> shr
+// (Granlund-Montgomery; exact for x < 2^31).
+struct FastDiv {
+  unsigned int d, mul, shr;
+};
+FastDiv make_fastdiv(unsigned int d);
+
 // Y (contiguous, dims d) = alpha * (*scale) * X[o . xs] + beta * Y ; tb = Y axis that is X's
-// fastest axis when it differs from Y's fastest axis, else -1.
+// fastest axis when it differs from Y's fastest axis, else -1.  div[k] divide by d[k];
+// for the tiled path tdiv[0..1] divide by the tile counts of axes 3 and tb.
 struct PermProblem {
   const double* X;
   double* Y;
@@ -30,6 +38,9 @@ struct PermProblem {
   long xs[4];
   int d[4];
   int tb;
+  int oth[2];            // the two Y axes other than 3 and tb (tiled path)
+  FastDiv div[4];
+  FastDiv tdiv[2];
   double alpha, beta;
 };
 
@@ -50,8 +61,9 @@ void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob,
                     hipStream_t s);
 void launch_dot(const DotProblem* d_probs, int n_prob, int blocks_per, double* d_partial, hipStream_t s);
 
-// tile sizes of the GEMM configurations
-inline int gemm_bm(int cfg) { return cfg == 0 ? 128 : 64; }
-inline int gemm_bn(int cfg) { return cfg == 0 ? 128 : 64; }
+// GEMM tile configurations: 0: 128x128 BK 16, 1: 64x64 BK 16, 2: 128x128 BK 32
+constexpr int kGemmConfigs = 3;
+inline int gemm_bm(int cfg) { return cfg == 1 ? 64 : 128; }
+inline int gemm_bn(int cfg) { return cfg == 1 ? 64 : 128; }
 
 }  // namespace ftcc

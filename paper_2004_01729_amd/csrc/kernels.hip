@@ -45,20 +45,29 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
 //   D (16x16): lane l holds D[4 * r + l / 16][l % 16], r = 0..3
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int BK, bool TA, bool TB>
-__global__ void __launch_bounds__(256)
+template <int BM, int BN, int BK, bool TA, bool TB, int WPE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 4)))
 gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ prefix,
                  int n_prob, int total_tiles) {
   constexpr int WM = BM / 2, WN = BN / 2;        // 2 x 2 waves
   constexpr int FM = WM / 16, FN = WN / 16;      // MFMA tiles per wave
-  constexpr int PA = BM + 1, PB = BN + 1;        // LDS row pitch (doubles)
+  // LDS tiles keep the global layout of each operand (no transposing stores):
+  //   TA: As[k][m] (pitch BM+1)   !TA: As[m][k] (pitch BK+1)
+  //   TB: Bs[n][k] (pitch BK+1)   !TB: Bs[k][n] (pitch BN+1)
+  constexpr int PA = TA ? BM + 1 : BK + 1;
+  constexpr int PB = TB ? BK + 1 : BN + 1;
+  constexpr int SA = TA ? BK * PA : BM * PA;
+  constexpr int SB = TB ? BN * PB : BK * PB;
   constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-  __shared__ double As[2][BK * PA];
-  __shared__ double Bs[2][BK * PB];
+  // thread -> element maps: e = tid + 256 j; rows of the stored layout
+  constexpr int RA = TA ? BM : BK;   // contiguous extent of A's stored rows
+  constexpr int RB = TB ? BK : BN;
+  __shared__ double As[2][SA];
+  __shared__ double Bs[2][SB];
 
   const int tile = xcd_remap(blockIdx.x, total_tiles);
   const int pi = find_problem(prefix, n_prob, tile);
-  const GemmProblem P = probs[pi];
+  const GemmProblem& P = probs[pi];
   int local = tile - prefix[pi];
   const int tiles_mn = P.tiles_m * P.tiles_n;
   const int ks = local / tiles_mn;
@@ -74,53 +83,45 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   const int m0 = tm * BM, n0 = tn * BN;
   const int kbeg = ks * P.kchunk;
   const int kend = min(P.K, kbeg + P.kchunk);
+  const int M = P.M, N = P.N;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
 
+  // Each thread loads LA elements of A: stored row r = (tid + 256 j) / RA, column c = tid % RA
+  // (256 is a multiple of RA), i.e. rows advance by 256 / RA per j.  Offsets are 32-bit:
+  // the host guarantees every operand holds fewer than 2^31 elements.
+  const int ca = tid % RA, r0a = tid / RA;
+  const int cb = tid % RB, r0b = tid / RB;
+  constexpr int DRA = 256 / RA, DRB = 256 / RB;
   const double* __restrict__ A = P.A;
   const double* __restrict__ B = P.B;
-  const long lda = P.lda, ldb = P.ldb;
+  const int lda = (int)P.lda, ldb = (int)P.ldb;
 
   double ra[LA], rb[LB];
+  // k0: first k of the tile
   auto load_tiles = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < LA; ++j) {
-      int e = tid + 256 * j;
-      int m, k;
-      if (TA) { k = e / BM; m = e % BM; } else { m = e / BK; k = e % BK; }
-      int gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      if (gm < P.M && gk < kend) v = TA ? A[(long)gk * lda + gm] : A[(long)gm * lda + gk];
-      ra[j] = v;
+      const int r = r0a + DRA * j;
+      int gm, gk;
+      if (TA) { gk = k0 + r; gm = m0 + ca; } else { gm = m0 + r; gk = k0 + ca; }
+      ra[j] = (gm < M && gk < kend) ? A[TA ? (unsigned)(gk * lda + gm) : (unsigned)(gm * lda + gk)] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < LB; ++j) {
-      int e = tid + 256 * j;
-      int n, k;
-      if (TB) { n = e / BK; k = e % BK; } else { k = e / BN; n = e % BN; }
-      int gn = n0 + n, gk = k0 + k;
-      double v = 0.0;
-      if (gn < P.N && gk < kend) v = TB ? B[(long)gn * ldb + gk] : B[(long)gk * ldb + gn];
-      rb[j] = v;
+      const int r = r0b + DRB * j;
+      int gn, gk;
+      if (TB) { gn = n0 + r; gk = k0 + cb; } else { gk = k0 + r; gn = n0 + cb; }
+      rb[j] = (gn < N && gk < kend) ? B[TB ? (unsigned)(gn * ldb + gk) : (unsigned)(gk * ldb + gn)] : 0.0;
     }
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < LA; ++j) {
-      int e = tid + 256 * j;
-      int m, k;
-      if (TA) { k = e / BM; m = e % BM; } else { m = e / BK; k = e % BK; }
-      As[buf][k * PA + m] = ra[j];
-    }
+    for (int j = 0; j < LA; ++j) As[buf][(r0a + DRA * j) * PA + ca] = ra[j];
 #pragma unroll
-    for (int j = 0; j < LB; ++j) {
-      int e = tid + 256 * j;
-      int n, k;
-      if (TB) { n = e / BK; k = e % BK; } else { k = e / BN; n = e % BN; }
-      Bs[buf][k * PB + n] = rb[j];
-    }
+    for (int j = 0; j < LB; ++j) Bs[buf][(r0b + DRB * j) * PB + cb] = rb[j];
   };
 
   double4_t acc[FM][FN];
@@ -135,25 +136,38 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     store_tiles(0);
     __syncthreads();
   }
+  const int fr = lane & 15, fk = lane >> 4;
+  const int abase = TA ? fk * PA + wm * WM + fr : (wm * WM + fr) * PA + fk;
+  const int bbase = TB ? (wn * WN + fr) * PB + fk : fk * PB + wn * WN + fr;
+  constexpr int ASTEP_I = TA ? 16 : 16 * PA;    // next MFMA tile in M
+  constexpr int ASTEP_K = TA ? 4 * PA : 4;      // next k group
+  constexpr int BSTEP_J = TB ? 16 * PB : 16;
+  constexpr int BSTEP_K = TB ? 4 : 4 * PB;
   for (int it = 0; it < nk; ++it) {
     const int cur = it & 1;
     const bool more = (it + 1) < nk;
     if (more) load_tiles(kbeg + (it + 1) * BK);
-    const double* as = As[cur];
-    const double* bs = Bs[cur];
+    const double* as = As[cur] + abase;
+    const double* bs = Bs[cur] + bbase;
+    double af[2][FM], bf[2][FN];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double af[FM], bf[FN];
+    for (int i = 0; i < FM; ++i) af[0][i] = as[i * ASTEP_I];
 #pragma unroll
-      for (int i = 0; i < FM; ++i) af[i] = as[kr * PA + wm * WM + i * 16 + (lane & 15)];
+    for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * BSTEP_J];
 #pragma unroll
-      for (int j = 0; j < FN; ++j) bf[j] = bs[kr * PB + wn * WN + j * 16 + (lane & 15)];
+    for (int kq = 0; kq < BK / 4; ++kq) {
+      const int c = kq & 1;
+      if (kq + 1 < BK / 4) {   // fetch the next k group while this one multiplies
+#pragma unroll
+        for (int i = 0; i < FM; ++i) af[c ^ 1][i] = as[(kq + 1) * ASTEP_K + i * ASTEP_I];
+#pragma unroll
+        for (int j = 0; j < FN; ++j) bf[c ^ 1][j] = bs[(kq + 1) * BSTEP_K + j * BSTEP_J];
+      }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[c][i], bf[c][j], acc[i][j], 0, 0, 0);
     }
     if (more) store_tiles(cur ^ 1);
     __syncthreads();
@@ -164,8 +178,8 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   long ldc;
   double alpha, beta;
   if (P.ksplit > 1) {
-    C = P.partial + (long)ks * P.M * P.N;
-    ldc = P.N;
+    C = P.partial + (long)ks * M * N;
+    ldc = N;
     alpha = 1.0;
     beta = 0.0;
   } else {
@@ -178,11 +192,11 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
-      const int gn = n0 + wn * WN + j * 16 + (lane & 15);
+      const int gn = n0 + wn * WN + j * 16 + fr;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * WM + i * 16 + 4 * r + (lane >> 4);
-        if (gm < P.M && gn < P.N) {
+        const int gm = m0 + wm * WM + i * 16 + 4 * r + fk;
+        if (gm < M && gn < N) {
           double* c = C + (long)gm * ldc + gn;
           double v = alpha * acc[i][j][r];
           if (beta != 0.0) v += beta * (*c);
@@ -214,66 +228,88 @@ __global__ void splitk_reduce_kernel(const GemmProblem* __restrict__ probs, cons
 }
 
 // ------------------------------------------------------------------ permute
+FastDiv make_fastdiv(unsigned int d) {
+  FastDiv f;
+  f.d = d;
+  unsigned int l = 0;
+  while ((1u << l) < d) ++l;     // l = ceil(log2 d)
+  // mul = floor(2^32 (2^l - d) / d) + 1, valid for numerators < 2^31
+  f.mul = (unsigned int)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  f.shr = l;
+  return f;
+}
+
+__device__ __forceinline__ unsigned int fdiv(unsigned int x, const FastDiv& f) {
+  const unsigned int t = __umulhi(x, f.mul);
+  return (t + ((x - t) >> 1)) >> (f.shr > 0 ? f.shr - 1 : 0);
+}
+
+__device__ __forceinline__ void fdivmod(unsigned int x, const FastDiv& f, unsigned int& q, unsigned int& r) {
+  q = (f.d == 1) ? x : fdiv(x, f);
+  r = x - q * f.d;
+}
+
 // Y[o0,o1,o2,o3] = alpha * X[sum_k o_k * xs[k]] + beta * Y   (Y contiguous, dims d)
-// Tiled path: axis `ta` of Y (its fastest, 3) against the Y axis `tb` that is
-// X's fastest; a 32x32 LDS tile keeps both the read and the write coalesced.
-__global__ void permute4_kernel(const PermProblem* __restrict__ probs, const int* __restrict__ prefix,
-                                int n_prob) {
+// Row path (X fastest = Y fastest): 1024 consecutive Y elements per block.
+// Tiled path: a 32x32 LDS tile over Y axes (tb, 3) keeps reads and writes coalesced.
+__global__ void __launch_bounds__(256) permute4_kernel(const PermProblem* __restrict__ probs,
+                                                       const int* __restrict__ prefix, int n_prob) {
   const int pi = find_problem(prefix, n_prob, blockIdx.x);
-  const PermProblem P = probs[pi];
-  const long local = blockIdx.x - prefix[pi];
+  const PermProblem& P = probs[pi];
+  const unsigned int local = blockIdx.x - prefix[pi];
   const double alpha = P.scale ? P.alpha * (*P.scale) : P.alpha;
+  const double beta = P.beta;
+  const double* __restrict__ X = P.X;
+  double* __restrict__ Y = P.Y;
   __shared__ double tileb[32][33];
   if (P.tb < 0) {
-    // contiguous-run path: Y's fastest axis is also X's fastest axis
-    const long total = (long)P.d[0] * P.d[1] * P.d[2] * P.d[3];
+    const unsigned int total = (unsigned int)P.d[0] * P.d[1] * P.d[2] * P.d[3];
+#pragma unroll
     for (int u = 0; u < 4; ++u) {
-      long e = local * 1024 + u * 256 + threadIdx.x;
-      if (e >= total) return;
-      long r = e;
-      int o3 = r % P.d[3]; r /= P.d[3];
-      int o2 = r % P.d[2]; r /= P.d[2];
-      int o1 = r % P.d[1]; r /= P.d[1];
-      int o0 = (int)r;
-      long xo = o0 * P.xs[0] + o1 * P.xs[1] + o2 * P.xs[2] + o3 * P.xs[3];
-      double v = (alpha != 0.0) ? alpha * P.X[xo] : 0.0;
-      if (P.beta != 0.0) v += P.beta * P.Y[e];
-      P.Y[e] = v;
+      const unsigned int e = local * 1024u + u * 256u + threadIdx.x;
+      if (e >= total) break;
+      unsigned int r = e, o3, o2, o1, o0;
+      fdivmod(r, P.div[3], r, o3);
+      fdivmod(r, P.div[2], r, o2);
+      fdivmod(r, P.div[1], o0, o1);
+      const long xo = o0 * P.xs[0] + o1 * P.xs[1] + o2 * P.xs[2] + (long)o3 * P.xs[3];
+      double v = (alpha != 0.0) ? alpha * X[xo] : 0.0;
+      if (beta != 0.0) v += beta * Y[e];
+      Y[e] = v;
     }
     return;
   }
-  // tiled path over Y axes (tb, 3); the other two Y axes (p, q) enumerate tiles
   const int tb = P.tb;
-  int oth[2], c = 0;
-  for (int k = 0; k < 3; ++k) if (k != tb) oth[c++] = k;
-  const int nt3 = (P.d[3] + 31) / 32, ntb = (P.d[tb] + 31) / 32;
-  long r = local;
-  const int t3 = r % nt3; r /= nt3;
-  const int tbb = r % ntb; r /= ntb;
-  const int iq = r % P.d[oth[1]]; r /= P.d[oth[1]];
-  const int ip = (int)r;
+  unsigned int r = local, t3, tbb, iq, ip;
+  fdivmod(r, P.tdiv[0], r, t3);
+  fdivmod(r, P.tdiv[1], r, tbb);
+  fdivmod(r, P.div[P.oth[1]], ip, iq);
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-  int o[4];
-  o[oth[0]] = ip;
-  o[oth[1]] = iq;
-  // read: X fastest is Y axis tb -> consecutive tx along tb
+  const long base = (long)ip * P.xs[P.oth[0]] + (long)iq * P.xs[P.oth[1]];
+  const int b0 = tbb * 32, c0 = t3 * 32;
+  const int db = P.d[tb], d3 = P.d[3];
+  const long xsb = P.xs[tb], xs3 = P.xs[3];
+#pragma unroll
   for (int y = ty; y < 32; y += 8) {
-    o[tb] = tbb * 32 + tx;
-    o[3] = t3 * 32 + y;
-    double v = 0.0;
-    if (o[tb] < P.d[tb] && o[3] < P.d[3])
-      v = P.X[o[0] * P.xs[0] + o[1] * P.xs[1] + o[2] * P.xs[2] + o[3] * P.xs[3]];
-    tileb[y][tx] = v;
+    const int ob = b0 + tx, o3 = c0 + y;
+    tileb[y][tx] = (ob < db && o3 < d3 && alpha != 0.0) ? X[base + ob * xsb + o3 * xs3] : 0.0;
   }
   __syncthreads();
+  // Y strides of the four axes
+  long ys[4];
+  ys[3] = 1;
+  ys[2] = d3;
+  ys[1] = ys[2] * P.d[2];
+  ys[0] = ys[1] * P.d[1];
+  const long ybase = (long)ip * ys[P.oth[0]] + (long)iq * ys[P.oth[1]];
+#pragma unroll
   for (int y = ty; y < 32; y += 8) {
-    o[tb] = tbb * 32 + y;
-    o[3] = t3 * 32 + tx;
-    if (o[tb] < P.d[tb] && o[3] < P.d[3]) {
-      long yo = (((long)o[0] * P.d[1] + o[1]) * P.d[2] + o[2]) * P.d[3] + o[3];
+    const int ob = b0 + y, o3 = c0 + tx;
+    if (ob < db && o3 < d3) {
+      const long yo = ybase + ob * ys[tb] + o3;
       double v = alpha * tileb[tx][y];
-      if (P.beta != 0.0) v += P.beta * P.Y[yo];
-      P.Y[yo] = v;
+      if (beta != 0.0) v += beta * Y[yo];
+      Y[yo] = v;
     }
   }
 }
@@ -308,25 +344,27 @@ __global__ void dot_final_kernel(const DotProblem* __restrict__ probs, int n_pro
 }
 
 // ------------------------------------------------------------------ launchers
-template <int BM, int BN, bool TA, bool TB>
+template <int BM, int BN, int BK, bool TA, bool TB>
 static void launch_gemm_t(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_tiles,
                           hipStream_t s) {
-  hipLaunchKernelGGL((gemm_mfma_kernel<BM, BN, 16, TA, TB>), dim3(total_tiles), dim3(256), 0, s,
+  constexpr int WPE = (BK == 16) ? 2 : 1;
+  hipLaunchKernelGGL((gemm_mfma_kernel<BM, BN, BK, TA, TB, WPE>), dim3(total_tiles), dim3(256), 0, s,
                      d_probs, d_prefix, n_prob, total_tiles);
 }
 
 void launch_gemm(int cfg, bool ta, bool tb, const GemmProblem* d_probs, const int* d_prefix, int n_prob,
                  int total_tiles, hipStream_t s) {
   if (total_tiles <= 0) return;
-#define FTCC_G(BM, BN)                                                                        \
-  do {                                                                                        \
-    if (ta && tb) launch_gemm_t<BM, BN, true, true>(d_probs, d_prefix, n_prob, total_tiles, s);    \
-    else if (ta) launch_gemm_t<BM, BN, true, false>(d_probs, d_prefix, n_prob, total_tiles, s);    \
-    else if (tb) launch_gemm_t<BM, BN, false, true>(d_probs, d_prefix, n_prob, total_tiles, s);    \
-    else launch_gemm_t<BM, BN, false, false>(d_probs, d_prefix, n_prob, total_tiles, s);           \
+#define FTCC_G(BM, BN, BK)                                                                        \
+  do {                                                                                            \
+    if (ta && tb) launch_gemm_t<BM, BN, BK, true, true>(d_probs, d_prefix, n_prob, total_tiles, s);    \
+    else if (ta) launch_gemm_t<BM, BN, BK, true, false>(d_probs, d_prefix, n_prob, total_tiles, s);    \
+    else if (tb) launch_gemm_t<BM, BN, BK, false, true>(d_probs, d_prefix, n_prob, total_tiles, s);    \
+    else launch_gemm_t<BM, BN, BK, false, false>(d_probs, d_prefix, n_prob, total_tiles, s);           \
   } while (0)
-  if (cfg == 0) FTCC_G(128, 128);
-  else FTCC_G(64, 64);
+  if (cfg == 0) FTCC_G(128, 128, 16);
+  else if (cfg == 1) FTCC_G(64, 64, 16);
+  else FTCC_G(128, 128, 32);
 #undef FTCC_G
 }
 
