@@ -62,9 +62,12 @@ typedef struct {
   int max_iter;         /* Picard sweeps per panel */
   int checkpoint;       /* 0: keep every node; 1: keep panel-start states only and
                            recompute each panel in the adjoint (HBM checkpointing) */
+  int diis_depth;       /* 0: plain fixed-point sweeps; 2..8: DIIS (Anderson) extrapolation over
+                           this many sweeps, forward and adjoint (needs 2 * depth * m * (n^2 + n^4)
+                           doubles per instance) */
 } ftcc_options;
 
-/* Defaults: n_tau 16, m 4, propagator 0, thr 0, tol 1e-12, max_iter 200, checkpoint 0. */
+/* Defaults: n_tau 16, m 4, propagator 0, thr 0, tol 1e-12, max_iter 200, checkpoint 0, diis_depth 0. */
 void ftcc_default_options(ftcc_options* opt);
 
 /* Create a context for n_instances independent (Hamiltonian, mu, beta) problems
@@ -83,7 +86,7 @@ int ftcc_set_stream(ftcc_ctx* ctx, void* hip_stream);
  *        real, with <pq|rs> = <qp|sr> (plane waves and Bloch waves need not
  *        satisfy the real-orbital symmetry <pq|rs> = <rq|ps>)
  *   eps  n reference orbital energies (H_0 = sum_p eps_p a_p^+ a_p, Section II.B)
- * All instances of one context must have the same n in this version. */
+ * Instances may have different n; every step is one grouped launch over all of them. */
 int ftcc_set_hamiltonian(ftcc_ctx* ctx, int inst, int n, const double* h, const double* eri, const double* eps);
 
 /* Thermal integrals for (mu[i], beta[i]) and the forward imaginary-time march
@@ -110,7 +113,8 @@ int ftcc_get_lambda(ftcc_ctx* ctx, int inst, int node, double* lam1, double* lam
 /* Derivatives of Omega at a frozen reference (orbitals, eps and the dropped
  * slots fixed; Section II.D types 1, 2, 4, 5, 6 for this discretisation):
  *   dO_dmu[i], dO_dbeta[i]   (either may be NULL)
- *   dO_dh                    [n_instances][n*n] dOmega/dh_pq, or NULL
+ *   dO_dh                    dOmega/dh_pq of every instance, n_i*n_i row-major blocks one after
+ *                            the other in instance order (sum_i n_i^2 doubles), or NULL
  *   deri_dtheta, dh_dtheta   optional direction of a scalar parameter theta per
  *                            instance (arrays of n_instances host pointers to n^4
  *                            and n*n arrays; an entry may be NULL), e.g.

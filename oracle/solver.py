@@ -66,8 +66,37 @@ def _panel_weights(model, grid, deriv=False):
     return w1, w2
 
 
-def solve(model, grid, tol=1e-13, max_iter=400, mix=1.0):
-    """Forward march.  `mix` < 1 applies linear damping to the Picard update."""
+def _diis_next(hist_s, hist_r):
+    """Anderson/DIIS extrapolation: minimise |sum c_j r_j| with sum c_j = 1."""
+    k = len(hist_r)
+    G = np.array([[float(np.dot(a, b)) for b in hist_r] for a in hist_r])
+    A = np.zeros((k + 1, k + 1))
+    A[:k, :k] = G / max(np.max(np.abs(np.diag(G))), 1e-300)
+    A[:k, k] = A[k, :k] = -1.0
+    rhs = np.zeros(k + 1)
+    rhs[k] = -1.0
+    c = np.linalg.lstsq(A, rhs, rcond=None)[0][:k]
+    return sum(cj * (sj + rj) for cj, sj, rj in zip(c, hist_s, hist_r))
+
+
+def _flat(vs):
+    return np.concatenate([np.concatenate([v[0].ravel(), v[1].ravel()]) for v in vs])
+
+
+def _unflat(vec, like):
+    out, off = [], 0
+    for v in like:
+        a = vec[off:off + v[0].size].reshape(v[0].shape)
+        off += v[0].size
+        b = vec[off:off + v[1].size].reshape(v[1].shape)
+        off += v[1].size
+        out.append((a, b))
+    return out
+
+
+def solve(model, grid, tol=1e-13, max_iter=400, mix=1.0, diis=0):
+    """Forward march.  `mix` < 1 applies linear damping to the Picard update;
+    diis > 1 extrapolates over that many sweeps (the fixed point is unchanged)."""
     (E1, Ee1, W1, We1), (E2, Ee2, W2, We2) = _panel_weights(model, grid)
     m = grid.m
     sb = model.zeros()
@@ -75,6 +104,7 @@ def solve(model, grid, tol=1e-13, max_iter=400, mix=1.0):
     for p in range(grid.P):
         starts.append(sb)
         s = [(E1[x] * sb[0], E2[x] * sb[1]) for x in range(m)]
+        hist_s, hist_r = [], []
         for it in range(1, max_iter + 1):
             S = [model.residual(s[x]) for x in range(m)]
             new = []
@@ -87,11 +117,17 @@ def solve(model, grid, tol=1e-13, max_iter=400, mix=1.0):
                 new.append((n1, n2))
             change = max(_maxabs((new[x][0] - s[x][0], new[x][1] - s[x][1])) for x in range(m))
             scale = max(1.0, max(_maxabs(v) for v in new))
-            s = new
             if not np.isfinite(change):
                 raise FloatingPointError(f"panel {p}: non-finite amplitudes")
             if change <= tol * scale:
+                s = new
                 break
+            if diis > 1:
+                hist_s.append(_flat(s))
+                hist_r.append(_flat(new) - hist_s[-1])
+                hist_s, hist_r = hist_s[-diis:], hist_r[-diis:]
+                new = _unflat(_diis_next(hist_s, hist_r), new) if len(hist_r) > 1 else new
+            s = new
         else:
             raise RuntimeError(f"panel {p}: Picard iteration did not converge (last change {change:.3e})")
         iters.append(it)

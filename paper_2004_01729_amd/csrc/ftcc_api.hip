@@ -9,6 +9,7 @@
 #include <functional>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -233,11 +234,20 @@ struct ftcc_ctx {
   unsigned long long* d_maxbits = nullptr;    // [B][2]
   double* d_partial = nullptr;                // TAU_BETA partial sums
   std::vector<int> tau_prefix_host;
-  // descriptor sets for the propagator (uploaded once)
-  std::map<int, std::pair<TauProblem*, int*>> tau_desc;
-  std::map<int, int> tau_blocks;
   int* d_active = nullptr;                    // [B]
   KernelProfiler prof;
+  hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
+  std::vector<int> beta_part_off;             // first TAU_BETA partial of each instance
+  std::vector<int> active_host;               // per-instance "still iterating" flags
+  std::map<std::pair<int, int>, std::pair<TauProblem*, int*>> tau_cache;
+  std::map<std::pair<int, int>, std::pair<int, int>> tau_shape;   // (n_prob, blocks)
+  // DIIS state: per instance `depth` stored iterates X and residuals R (m * len each)
+  std::vector<std::vector<double*>> diis_X, diis_R;
+  std::vector<int> diis_count, diis_next;
+  double* d_gram = nullptr;     // [B][D][D]
+  double* d_coef = nullptr;     // [B][D]
+  int* d_dcount = nullptr;      // [B]
+  int* d_dnewest = nullptr;     // [B]
   long resid_evals = 0, vjp_evals = 0;
   double t_solve = 0.0, t_lambda = 0.0;
   size_t bytes = 0;
@@ -383,16 +393,14 @@ void build(ftcc_ctx* c) {
   if (c->built) return;
   for (int i = 0; i < c->B; ++i)
     if (!c->inst[i].has_ham) fail(FTCC_ESTATE, "instance " + std::to_string(i) + " has no Hamiltonian");
-  const int n = c->inst[0].n;
-  for (int i = 0; i < c->B; ++i)
-    if (c->inst[i].n != n) fail(FTCC_EINVAL, "all instances of a context must have the same n");
   const int m = c->m, P = c->P, B = c->B;
-  const long n2 = (long)n * n, n4 = n2 * n2, len = n2 + n4;
   c->prog = build_residual_program();
   const Program& prog = c->prog;
 
   for (int i = 0; i < B; ++i) {
     Instance& I = c->inst[i];
+    const int n = I.n;
+    const long n2 = (long)n * n, n4 = n2 * n2, len = n2 + n4;
     I.occ = c->dalloc(n);
     I.wo = c->dalloc(n);
     I.wv = c->dalloc(n);
@@ -443,6 +451,8 @@ void build(ftcc_ctx* c) {
   for (int i = 0; i < B; ++i)
     for (int x = 0; x < m; ++x) {
       const int p = i * m + x;
+      const int n = c->inst[i].n;
+      const long n2 = (long)n * n, n4 = n2 * n2, len = n2 + n4;
       probs.push_back({i, x, n});
       c->amp[p] = c->dalloc(len);
       c->S[p] = c->dalloc(len);
@@ -467,9 +477,36 @@ void build(ftcc_ctx* c) {
     std::vector<int> ones(2 * B, 1);
     FTCC_HIP(hipMemcpy(c->d_active, ones.data(), sizeof(int) * B, hipMemcpyHostToDevice));
   }
+  const int D = c->opt.diis_depth;
+  if (D > 0) {
+    c->diis_X.assign(B, {});
+    c->diis_R.assign(B, {});
+    for (int i = 0; i < B; ++i) {
+      const long n = c->inst[i].n, len = n * n + n * n * n * n;
+      for (int d = 0; d < D; ++d) {
+        c->diis_X[i].push_back(c->dalloc((size_t)m * len));
+        c->diis_R[i].push_back(c->dalloc((size_t)m * len));
+      }
+    }
+    c->d_gram = c->dalloc((size_t)B * D * D);
+    c->d_coef = c->dalloc((size_t)B * D);
+    c->d_dcount = (int*)c->dalloc(B);
+    c->d_dnewest = (int*)c->dalloc(B);
+    c->diis_count.assign(B, 0);
+    c->diis_next.assign(B, 0);
+  }
   c->d_rule = (PanelRule*)c->dalloc(sizeof(PanelRule) / sizeof(double) + 1);
   FTCC_HIP(hipMemcpy(c->d_rule, &c->rule, sizeof(PanelRule), hipMemcpyHostToDevice));
-  c->d_partial = c->dalloc((size_t)B * 2 * ((len + 1023) / 1024) + 16);
+  {
+    size_t blocks = 16;
+    c->beta_part_off.assign(B, 0);
+    for (int i = 0; i < B; ++i) {
+      const long n2 = (long)c->inst[i].n * c->inst[i].n;
+      c->beta_part_off[i] = (int)blocks - 16;
+      blocks += (n2 + 1023) / 1024 + (n2 * n2 + 1023) / 1024;
+    }
+    c->d_partial = c->dalloc(blocks);
+  }
 
   std::vector<int> ugrads;
   for (int k = 0; k < 4; ++k) ugrads.push_back(prog.id(kU[k]));
@@ -486,6 +523,7 @@ void build(ftcc_ctx* c) {
   };
   auto bind_common = [&, c](int t, int p, bool grad) -> double* {
     const TensorDecl& d = prog.t[t];
+    const long n = probs[p].n, n2 = n * n;
     const long cnt = ipow(n, d.rank);
     if (t == id_t1) return grad ? c->gr[p] : c->amp[p];
     if (t == id_t2) return grad ? c->gr[p] + n2 : c->amp[p] + n2;
@@ -507,6 +545,7 @@ void build(ftcc_ctx* c) {
     const TensorDecl& d = prog.t[t];
     if (double* q = bind_common(t, p, grad)) return q;
     const int i = probs[p].inst;
+    const long n = probs[p].n, n2 = n * n;
     if (d.kind == T_CONST) return c->inst[i].blk[d.name];
     if (d.derived) return tensor_buf(c->derived, t, i, ipow(n, d.rank));
     if (t == id_S1) return c->S[p];
@@ -518,6 +557,7 @@ void build(ftcc_ctx* c) {
     const TensorDecl& d = prog.t[t];
     if (double* q = bind_common(t, p, grad)) return q;
     const int i = probs[p].inst;
+    const long n = probs[p].n, n2 = n * n;
     if (d.kind == T_CONST) return c->inst[i].dblk[d.name];
     if (d.derived) return tensor_buf(c->dderived, t, i, ipow(n, d.rank));
     if (t == id_S1) return c->dS[p];
@@ -539,86 +579,131 @@ void build(ftcc_ctx* c) {
   c->ex_d->set_profiler(&c->prof);
   c->ex_main->autotune(c->stream);
   c->ex_d->autotune(c->stream);
+  FTCC_HIP(hipStreamSynchronize(c->stream));
+  const char* genv = std::getenv("FTCC_GRAPH");
+  if (!(genv && genv[0] == '0')) {
+    // the forward and backward launch lists are static: capture each once as a graph
+    hipGraph_t g;
+    FTCC_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->ex_main->run_forward(c->stream);
+    FTCC_HIP(hipStreamEndCapture(c->stream, &g));
+    FTCC_HIP(hipGraphInstantiate(&c->g_fwd, g, nullptr, nullptr, 0));
+    FTCC_HIP(hipGraphDestroy(g));
+    FTCC_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->ex_main->run_backward(c->stream);
+    FTCC_HIP(hipStreamEndCapture(c->stream, &g));
+    FTCC_HIP(hipGraphInstantiate(&c->g_bwd, g, nullptr, nullptr, 0));
+    FTCC_HIP(hipGraphDestroy(g));
+  }
 
   // propagator descriptors: one per (instance, segment) for each mode's buffer roles
   c->built = true;
 }
 
-enum Roles { R_FWD = 0, R_END, R_INIT, R_LAMT, R_LSTEP, R_APREV, R_BETA };
+// the forward / backward programs: graph replay unless the kernel profiler records events
+void forward(ftcc_ctx* c) {
+  if (c->g_fwd && !c->prof.enabled) FTCC_HIP(hipGraphLaunch(c->g_fwd, c->stream));
+  else c->ex_main->run_forward(c->stream);
+}
+
+void backward(ftcc_ctx* c) {
+  if (c->g_bwd && !c->prof.enabled) FTCC_HIP(hipGraphLaunch(c->g_bwd, c->stream));
+  else c->ex_main->run_backward(c->stream);
+}
+
+void clear_tau_cache(ftcc_ctx* c) {
+  for (auto& kv : c->tau_cache) {
+    (void)hipFree(kv.second.first);
+    (void)hipFree(kv.second.second);
+  }
+  c->tau_cache.clear();
+  c->tau_shape.clear();
+}
 
 // Descriptor set for the propagator: per instance two segments (t1, t2).
-// `panel` selects per-panel buffers (sb, lam, a, ...).
-void tau_run(ftcc_ctx* c, int mode, int panel, bool use_active) {
+// `panel` selects per-panel buffers (sb, lambda, a, ...).  Descriptors are built
+// once per (mode, panel) and kept until the next solve (beta may change).
+void tau_run(ftcc_ctx* c, int mode, int panel) {
   const int B = c->B, m = c->m;
-  const int n = c->inst[0].n;
-  const long n2 = (long)n * n, n4 = n2 * n2;
-  std::vector<TauProblem> ps;
-  std::vector<int> prefix;
-  int total = 0;
-  for (int i = 0; i < B; ++i) {
-    Instance& I = c->inst[i];
-    for (int seg = 0; seg < 2; ++seg) {
-      TauProblem t;
-      std::memset(&t, 0, sizeof(t));
-      const long off = seg ? n2 : 0;
-      t.eps = I.eps;
-      t.n = n;
-      t.rank = seg ? 4 : 2;
-      t.len = seg ? n4 : n2;
-      t.h = I.beta / c->P;
-      t.maxbits = c->d_maxbits + 2 * i;
-      for (int x = 0; x < m; ++x) {
-        const int p = i * m + x;
-        switch (mode) {
-          case TAU_INIT:
-          case TAU_STEP:
-            t.S[x] = c->S[p] + off;
-            t.s[x] = c->amp[p] + off;
-            break;
-          case TAU_END:
-            t.S[x] = c->S[p] + off;
-            break;
-          case TAU_LAMT:      // S = lambda (node storage), s = lambda-tilde (cotangent slots)
-            t.S[x] = I.lam[panel * m + x] + off;
-            t.s[x] = c->cot[p] + off;
-            break;
-          case TAU_LSTEP:     // s = lambda (node storage), R = gradient
-            t.s[x] = I.lam[panel * m + x] + off;
-            t.R[x] = c->gr[p] + off;
-            break;
-          case TAU_APREV:
-            t.S[x] = I.lam[panel * m + x] + off;
-            break;
-          case TAU_BETA:      // S = lambda, R = converged residuals
-            t.S[x] = I.lam[panel * m + x] + off;
-            t.R[x] = c->S[p] + off;
-            break;
+  const auto key = std::make_pair(mode, panel);
+  auto it = c->tau_cache.find(key);
+  if (it == c->tau_cache.end()) {
+    std::vector<TauProblem> ps;
+    std::vector<int> prefix;
+    int total = 0;
+    for (int i = 0; i < B; ++i) {
+      Instance& I = c->inst[i];
+      const long n = I.n, n2 = n * n, n4 = n2 * n2;
+      for (int seg = 0; seg < 2; ++seg) {
+        TauProblem t;
+        std::memset(&t, 0, sizeof(t));
+        const long off = seg ? n2 : 0;
+        t.eps = I.eps;
+        t.n = (int)n;
+        t.rank = seg ? 4 : 2;
+        t.len = seg ? n4 : n2;
+        t.h = I.beta / c->P;
+        t.maxbits = c->d_maxbits + 2 * i;
+        t.active = (mode == TAU_STEP || mode == TAU_LSTEP) ? c->d_active + i : nullptr;
+        for (int x = 0; x < m; ++x) {
+          const int p = i * m + x;
+          switch (mode) {
+            case TAU_INIT:
+            case TAU_STEP:
+              t.S[x] = c->S[p] + off;
+              t.s[x] = c->amp[p] + off;
+              break;
+            case TAU_END:
+              t.S[x] = c->S[p] + off;
+              break;
+            case TAU_LAMT:      // S = lambda (node storage), s = lambda-tilde (cotangent slots)
+              t.S[x] = I.lam[panel * m + x] + off;
+              t.s[x] = c->cot[p] + off;
+              break;
+            case TAU_LSTEP:     // s = lambda (node storage), R = gradient
+              t.s[x] = I.lam[panel * m + x] + off;
+              t.R[x] = c->gr[p] + off;
+              break;
+            case TAU_APREV:
+              t.S[x] = I.lam[panel * m + x] + off;
+              break;
+            case TAU_BETA:      // S = lambda, R = converged residuals
+              t.S[x] = I.lam[panel * m + x] + off;
+              t.R[x] = c->S[p] + off;
+              break;
+          }
         }
+        if (mode == TAU_INIT || mode == TAU_STEP || mode == TAU_END || mode == TAU_BETA) t.sb = I.sb[panel] + off;
+        if (mode == TAU_END) t.out = I.sb[panel + 1] + off;
+        if (mode == TAU_LAMT || mode == TAU_APREV) t.sb = I.abuf[panel + 1] + off;
+        if (mode == TAU_APREV) t.out = I.abuf[panel] + off;
+        if (mode == TAU_BETA) t.lam_a = I.abuf[panel + 1] + off;
+        const int nb = (int)((t.len + 1023) / 1024);
+        t.partial = c->d_partial + (long)total;
+        prefix.push_back(total);
+        total += nb;
+        ps.push_back(t);
       }
-      if (mode == TAU_INIT || mode == TAU_STEP || mode == TAU_END || mode == TAU_BETA) t.sb = I.sb[panel] + off;
-      if (mode == TAU_END) t.out = I.sb[panel + 1] + off;
-      if (mode == TAU_LAMT || mode == TAU_APREV) t.sb = I.abuf[panel + 1] + off;
-      if (mode == TAU_APREV) t.out = I.abuf[panel] + off;
-      if (mode == TAU_BETA) t.lam_a = I.abuf[panel + 1] + off;
-      const int nb = (int)((t.len + 1023) / 1024);
-      t.partial = c->d_partial + (long)total;
-      prefix.push_back(total);
-      total += nb;
-      ps.push_back(t);
-      (void)use_active;
     }
+    TauProblem* d_ps = nullptr;
+    int* d_pre = nullptr;
+    FTCC_HIP(hipMalloc((void**)&d_ps, sizeof(TauProblem) * ps.size()));
+    FTCC_HIP(hipMalloc((void**)&d_pre, sizeof(int) * prefix.size()));
+    FTCC_HIP(hipMemcpy(d_ps, ps.data(), sizeof(TauProblem) * ps.size(), hipMemcpyHostToDevice));
+    FTCC_HIP(hipMemcpy(d_pre, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice));
+    it = c->tau_cache.emplace(key, std::make_pair(d_ps, d_pre)).first;
+    c->tau_shape[key] = std::make_pair((int)ps.size(), total);
   }
-  // upload descriptors (small) and launch
-  TauProblem* d_ps = nullptr;
-  int* d_pre = nullptr;
-  FTCC_HIP(hipMallocAsync((void**)&d_ps, sizeof(TauProblem) * ps.size(), c->stream));
-  FTCC_HIP(hipMallocAsync((void**)&d_pre, sizeof(int) * prefix.size(), c->stream));
-  FTCC_HIP(hipMemcpyAsync(d_ps, ps.data(), sizeof(TauProblem) * ps.size(), hipMemcpyHostToDevice, c->stream));
-  FTCC_HIP(hipMemcpyAsync(d_pre, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice, c->stream));
-  launch_tau(c->d_rule, mode, d_ps, d_pre, (int)ps.size(), total, c->stream);
+  const auto shp = c->tau_shape[key];
+  launch_tau(c->d_rule, mode, it->second.first, it->second.second, shp.first, shp.second, c->stream);
   FTCC_HIP(hipGetLastError());
-  FTCC_HIP(hipFreeAsync(d_ps, c->stream));
-  FTCC_HIP(hipFreeAsync(d_pre, c->stream));
+}
+
+void set_active(ftcc_ctx* c, const std::vector<bool>& active) {
+  c->active_host.assign(c->B, 0);
+  for (int i = 0; i < c->B; ++i) c->active_host[i] = active[i] ? 1 : 0;
+  FTCC_HIP(hipMemcpyAsync(c->d_active, c->active_host.data(), sizeof(int) * c->B, hipMemcpyHostToDevice,
+                          c->stream));
 }
 
 void reset_maxbits(ftcc_ctx* c) {
@@ -641,6 +726,89 @@ void copy_d(ftcc_ctx* c, double* dst, const double* src, long count) {
 
 void zero_d(ftcc_ctx* c, double* dst, long count) { launch_axpby(count, 0.0, dst, 0.0, dst, c->stream); }
 
+// ------------------------------------------------------------------ DIIS (Anderson) acceleration
+// The fixed-point map G is one sweep (forward residual + propagator, or one
+// adjoint sweep).  Before the sweep the iterate s_k is saved as X_k; after it
+// R_k = G(s_k) - s_k, the Gram matrix row <R_k, R_j> is updated by dot
+// kernels, the bordered least-squares system is solved on the device and the
+// iterate is replaced by sum_j c_j (X_j + R_j).
+void diis_reset(ftcc_ctx* c) {
+  for (int i = 0; i < c->B; ++i) c->diis_count[i] = c->diis_next[i] = 0;
+}
+
+using NodeBufs = std::function<double*(int inst, int x)>;
+
+void diis_before(ftcc_ctx* c, const NodeBufs& it, const std::vector<bool>& active) {
+  for (int i = 0; i < c->B; ++i) {
+    if (!active[i]) continue;
+    const long n = c->inst[i].n, len = n * n + n * n * n * n;
+    double* X = c->diis_X[i][c->diis_next[i]];
+    for (int x = 0; x < c->m; ++x) copy_d(c, X + x * len, it(i, x), len);
+  }
+}
+
+void diis_after(ftcc_ctx* c, const NodeBufs& it, const std::vector<bool>& active) {
+  const int D = c->opt.diis_depth, m = c->m;
+  std::vector<int> newest(c->B, 0);
+  bool any = false;
+  for (int i = 0; i < c->B; ++i) {
+    newest[i] = c->diis_next[i];
+    if (!active[i]) continue;
+    any = true;
+    const long n = c->inst[i].n, len = n * n + n * n * n * n;
+    const int slot = c->diis_next[i];
+    double* X = c->diis_X[i][slot];
+    double* R = c->diis_R[i][slot];
+    for (int x = 0; x < m; ++x) {
+      copy_d(c, R + x * len, it(i, x), len);
+      launch_axpby(len, -1.0, X + x * len, 1.0, R + x * len, c->stream);
+    }
+    c->diis_count[i] = std::min(D, c->diis_count[i] + 1);
+    c->diis_next[i] = (slot + 1) % D;
+    // Gram entries of the new residual against every stored one
+    std::vector<DotProblem> ds;
+    for (int t = 0; t < c->diis_count[i]; ++t) {
+      for (int tw = 0; tw < 2; ++tw) {
+        DotProblem d;
+        d.X = R;
+        d.Y = c->diis_R[i][t];
+        d.out = c->d_gram + (long)i * D * D + (tw ? t * D + slot : slot * D + t);
+        d.len = m * len;
+        d.alpha = 1.0;
+        d.beta = 0.0;
+        ds.push_back(d);
+      }
+    }
+    DotProblem* dd = nullptr;
+    FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem) * ds.size(), c->stream));
+    FTCC_HIP(hipMemcpyAsync(dd, ds.data(), sizeof(DotProblem) * ds.size(), hipMemcpyHostToDevice, c->stream));
+    launch_dot(dd, (int)ds.size(), 64, c->scratch.dot_partial, c->stream);
+    FTCC_HIP(hipFreeAsync(dd, c->stream));
+  }
+  if (!any) return;
+  FTCC_HIP(hipMemcpyAsync(c->d_dcount, c->diis_count.data(), sizeof(int) * c->B, hipMemcpyHostToDevice, c->stream));
+  std::vector<int>* keep = new std::vector<int>(newest);
+  FTCC_HIP(hipMemcpyAsync(c->d_dnewest, keep->data(), sizeof(int) * c->B, hipMemcpyHostToDevice, c->stream));
+  launch_diis_solve(c->B, c->d_dcount, c->d_dnewest, c->d_gram, D, c->d_coef, c->stream);
+  for (int i = 0; i < c->B; ++i) {
+    if (!active[i] || c->diis_count[i] < 2) continue;
+    const long n = c->inst[i].n, len = n * n + n * n * n * n;
+    for (int x = 0; x < m; ++x) {
+      DiisTerms t;
+      t.k = c->diis_count[i];
+      t.coef = c->d_coef + (long)i * D;
+      for (int j = 0; j < t.k; ++j) {
+        t.X[j] = c->diis_X[i][j] + x * len;
+        t.R[j] = c->diis_R[i][j] + x * len;
+      }
+      launch_diis_combine(len, t, it(i, x), c->stream);
+    }
+  }
+  FTCC_HIP(hipStreamSynchronize(c->stream));
+  delete keep;
+}
+
+
 // Converge the Picard iteration of one panel for all instances (amplitudes in
 // the slots, residuals at the final amplitudes in S).  Returns per-instance sweeps.
 std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
@@ -649,12 +817,17 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
   std::vector<bool> active(B, true);
   for (int i = 0; i < B; ++i)
     if (status[i] != 0) active[i] = false;
-  tau_run(c, TAU_INIT, panel, false);
+  tau_run(c, TAU_INIT, panel);
+  const bool diis = c->opt.diis_depth > 0;
+  NodeBufs amp_of = [c](int i, int x) { return c->amp[i * c->m + x]; };
+  if (diis) diis_reset(c);
   for (int it = 1; it <= c->opt.max_iter; ++it) {
-    c->ex_main->run_forward(c->stream);
+    forward(c);
     c->resid_evals += (long)B * c->m;
     reset_maxbits(c);
-    tau_run(c, TAU_STEP, panel, true);
+    set_active(c, active);
+    if (diis) diis_before(c, amp_of, active);
+    tau_run(c, TAU_STEP, panel);
     std::vector<double> mb = read_maxbits(c);
     bool any = false;
     for (int i = 0; i < B; ++i) {
@@ -673,11 +846,12 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
       any = true;
     }
     if (!any) break;
+    if (diis) diis_after(c, amp_of, active);
     if (it == c->opt.max_iter)
       for (int i = 0; i < B; ++i)
         if (active[i]) status[i] = FTCC_ENOCONV;
   }
-  c->ex_main->run_forward(c->stream);
+  forward(c);
   c->resid_evals += (long)B * c->m;
   return its;
 }
@@ -696,6 +870,7 @@ void ftcc_default_options(ftcc_options* opt) {
   opt->tol = 1e-12;
   opt->max_iter = 200;
   opt->checkpoint = 0;
+  opt->diis_depth = 0;
 }
 
 int ftcc_abi_version(void) { return FTCC_ABI_VERSION; }
@@ -714,6 +889,8 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
     if (o.propagator < 0 || o.propagator > 1) fail(FTCC_EINVAL, "propagator must be 0 or 1");
     if (!(o.tol > 0.0) || o.max_iter < 1) fail(FTCC_EINVAL, "tol must be > 0 and max_iter >= 1");
     if (!(o.occ_thresh >= 0.0)) fail(FTCC_EINVAL, "occ_thresh must be >= 0");
+    if (o.diis_depth < 0 || o.diis_depth == 1 || o.diis_depth > kMaxDiis)
+      fail(FTCC_EINVAL, "diis_depth must be 0 (plain fixed-point sweeps) or 2..8");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) fail(FTCC_EDEVICE, "no HIP device");
     if (device < 0 || device >= ndev) fail(FTCC_EINVAL, "device index out of range");
@@ -742,6 +919,9 @@ int ftcc_destroy(ftcc_ctx* c) {
   return run_guarded([&] {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    clear_tau_cache(c);
+    if (c->g_fwd) (void)hipGraphExecDestroy(c->g_fwd);
+    if (c->g_bwd) (void)hipGraphExecDestroy(c->g_bwd);
     c->ex_main.reset();
     c->ex_d.reset();
     for (void* p : c->allocs) (void)hipFree(p);
@@ -796,9 +976,9 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
       if (!std::isfinite(mu[i]) || !(beta[i] > 0.0) || !std::isfinite(beta[i]))
         fail(FTCC_EINVAL, "mu must be finite and beta positive");
     build(c);
+    clear_tau_cache(c);
     const int B = c->B, m = c->m, P = c->P;
-    const int n = c->inst[0].n;
-    const long n2 = (long)n * n, len = n2 + n2 * n2;
+    auto lenof = [c](int i) { const long n = c->inst[i].n; return n * n + n * n * n * n; };
     hipEvent_t e0, e1;
     FTCC_HIP(hipEventCreate(&e0));
     FTCC_HIP(hipEventCreate(&e1));
@@ -809,7 +989,7 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
       I.mu = mu[i];
       I.beta = beta[i];
       thermal_setup(c, i);
-      zero_d(c, I.sb[0], len);
+      zero_d(c, I.sb[0], lenof(i));
       I.iters = 0;
       I.status = 0;
     }
@@ -825,12 +1005,12 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
           FTCC_HIP(hipMemcpyAsync(&ebuf[i * m + x], c->e[i * m + x], sizeof(double), hipMemcpyDeviceToHost,
                                   c->stream));
           if (!c->opt.checkpoint) {
-            copy_d(c, I.grid[p * m + x], c->amp[i * m + x], len);
-            copy_d(c, I.resid[p * m + x], c->S[i * m + x], len);
+            copy_d(c, I.grid[p * m + x], c->amp[i * m + x], lenof(i));
+            copy_d(c, I.resid[p * m + x], c->S[i * m + x], lenof(i));
           }
         }
       }
-      tau_run(c, TAU_END, p, false);
+      tau_run(c, TAU_END, p);
       sync(c);
       for (int i = 0; i < B; ++i)
         for (int x = 0; x < m; ++x) c->inst[i].energies[p * m + x] = ebuf[i * m + x];
@@ -906,11 +1086,12 @@ namespace {
 // forward program there (tape for the backward, residuals in S).
 void load_panel(ftcc_ctx* c, int p) {
   const int B = c->B, m = c->m;
-  const long n = c->inst[0].n, len = n * n + n * n * n * n;
   if (!c->opt.checkpoint) {
-    for (int i = 0; i < B; ++i)
+    for (int i = 0; i < B; ++i) {
+      const long n = c->inst[i].n, len = n * n + n * n * n * n;
       for (int x = 0; x < m; ++x) copy_d(c, c->amp[i * m + x], c->inst[i].grid[p * m + x], len);
-    c->ex_main->run_forward(c->stream);
+    }
+    forward(c);
   } else {
     std::vector<int> st(B, 0);
     panel_solve(c, p, st);   // deterministic: reproduces the forward sweep
@@ -928,9 +1109,9 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
     if (!c->solved) fail(FTCC_ESTATE, "call ftcc_solve_amplitudes first");
     FTCC_HIP(hipSetDevice(c->device));
     const int B = c->B, m = c->m, P = c->P;
-    const long n = c->inst[0].n, n2 = n * n, len = n2 + n2 * n2;
     for (int i = 0; i < B; ++i) {
       Instance& I = c->inst[i];
+      const long n = I.n, len = n * n + n * n * n * n;
       if (I.lam.empty()) {
         I.lam.resize(P * m);
         I.lamt.resize(P * m);
@@ -952,18 +1133,27 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
     for (int p = P - 1; p >= 0; --p) {
       load_panel(c, p);
       // lambda_x = -(g_x/beta) dE/ds : backward with zero S-cotangent
-      for (int q = 0; q < B * m; ++q) zero_d(c, c->cot[q], len);
-      c->ex_main->run_backward(c->stream);
+      for (int q = 0; q < B * m; ++q) {
+        const long n = c->inst[q / m].n;
+        zero_d(c, c->cot[q], n * n + n * n * n * n);
+      }
+      backward(c);
       c->vjp_evals += (long)B * m;
       reset_maxbits(c);
-      tau_run(c, TAU_LSTEP, p, false);
       std::vector<bool> active(B, true);
+      set_active(c, active);
+      tau_run(c, TAU_LSTEP, p);
+      const bool diis = c->opt.diis_depth > 0;
+      NodeBufs lam_of = [c, p](int i, int x) { return c->inst[i].lam[p * c->m + x]; };
+      if (diis) diis_reset(c);
       for (int it = 1; it <= c->opt.max_iter; ++it) {
-        tau_run(c, TAU_LAMT, p, false);
-        c->ex_main->run_backward(c->stream);
+        tau_run(c, TAU_LAMT, p);
+        backward(c);
         c->vjp_evals += (long)B * m;
         reset_maxbits(c);
-        tau_run(c, TAU_LSTEP, p, false);
+        set_active(c, active);
+        if (diis) diis_before(c, lam_of, active);
+        tau_run(c, TAU_LSTEP, p);
         std::vector<double> mb = read_maxbits(c);
         bool any = false;
         for (int i = 0; i < B; ++i) {
@@ -982,14 +1172,17 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
           any = true;
         }
         if (!any) break;
+        if (diis) diis_after(c, lam_of, active);
         if (it == c->opt.max_iter)
           for (int i = 0; i < B; ++i)
             if (active[i]) status[i] = FTCC_ENOCONV;
       }
-      tau_run(c, TAU_LAMT, p, false);   // lambda-tilde of the converged lambda
-      for (int i = 0; i < B; ++i)
+      tau_run(c, TAU_LAMT, p);   // lambda-tilde of the converged lambda
+      for (int i = 0; i < B; ++i) {
+        const long n = c->inst[i].n, len = n * n + n * n * n * n;
         for (int x = 0; x < m; ++x) copy_d(c, c->inst[i].lamt[p * m + x], c->cot[i * m + x], len);
-      tau_run(c, TAU_APREV, p, false);
+      }
+      tau_run(c, TAU_APREV, p);
     }
     FTCC_HIP(hipEventRecord(e1, c->stream));
     sync(c);
@@ -1035,13 +1228,13 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
     if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
     FTCC_HIP(hipSetDevice(c->device));
     const int B = c->B, m = c->m, P = c->P;
-    const long n = c->inst[0].n, n2 = n * n, n4 = n2 * n2, len = n2 + n4;
     const bool want_theta = dO_dtheta && (deri_dtheta || dh_dtheta);
     // device copies of the theta directions
     std::vector<double*> d_deri(B, nullptr), d_dh(B, nullptr);
     std::vector<void*> tmp;
     if (want_theta) {
       for (int i = 0; i < B; ++i) {
+        const long n = c->inst[i].n, n2 = n * n, n4 = n2 * n2;
         if (deri_dtheta && deri_dtheta[i]) {
           FTCC_HIP(hipMalloc((void**)&d_deri[i], sizeof(double) * n4));
           tmp.push_back(d_deri[i]);
@@ -1055,8 +1248,9 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
       }
     }
     for (int i = 0; i < B; ++i) {
+      const long n = c->inst[i].n;
       zero_d(c, c->inst[i].acc, 8);
-      for (int k = 0; k < 4; ++k) zero_d(c, c->inst[i].ugrad_acc[k], n2);
+      for (int k = 0; k < 4; ++k) zero_d(c, c->inst[i].ugrad_acc[k], n * n);
     }
     // dot launches: <lamt_x, dS_x> and (g_x/beta) dE_x accumulated into acc[slot]
     auto accumulate = [&](int slot) {
@@ -1065,10 +1259,11 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         for (int x = 0; x < m; ++x) {
           const int q = i * m + x;
           DotProblem d;
+          const long n = c->inst[i].n;
           d.X = c->cot[q];
           d.Y = c->dS[q];
           d.out = c->inst[i].acc + slot;
-          d.len = len;
+          d.len = n * n + n * n * n * n;
           d.alpha = 1.0;
           d.beta = 1.0;
           ds.push_back(d);
@@ -1087,23 +1282,27 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
     };
     for (int p = 0; p < P; ++p) {
       load_panel(c, p);
-      for (int i = 0; i < B; ++i)
+      for (int i = 0; i < B; ++i) {
+        const long n = c->inst[i].n, len = n * n + n * n * n * n;
         for (int x = 0; x < m; ++x) copy_d(c, c->cot[i * m + x], c->inst[i].lamt[p * m + x], len);
+      }
       if (dO_dh) {
-        c->ex_main->run_backward(c->stream);
-        for (int i = 0; i < B; ++i)
+        backward(c);
+        for (int i = 0; i < B; ++i) {
+          const long n = c->inst[i].n;
           for (int x = 0; x < m; ++x)
             for (int k = 0; k < 4; ++k)
-              launch_axpby(n2, 1.0, c->ugrad[i * m + x][k], 1.0, c->inst[i].ugrad_acc[k], c->stream);
+              launch_axpby(n * n, 1.0, c->ugrad[i * m + x][k], 1.0, c->inst[i].ugrad_acc[k], c->stream);
+        }
       }
       // beta: explicit dependence of the propagator weights (needs S at converged s)
       if (dO_dbeta) {
-        tau_run(c, TAU_BETA, p, false);
+        tau_run(c, TAU_BETA, p);
         // partial sums per (instance, segment) -> acc[3]
-        const int nb1 = (int)((n2 + 1023) / 1024), nb2 = (int)((n4 + 1023) / 1024);
         for (int i = 0; i < B; ++i) {
-          const long base = (long)i * (nb1 + nb2);
-          launch_sum(c->d_partial + base, nb1 + nb2, c->inst[i].acc + 4, c->stream);
+          const long n2 = (long)c->inst[i].n * c->inst[i].n;
+          const int nb1 = (int)((n2 + 1023) / 1024), nb2 = (int)((n2 * n2 + 1023) / 1024);
+          launch_sum(c->d_partial + c->beta_part_off[i], nb1 + nb2, c->inst[i].acc + 4, c->stream);
           launch_axpby(1, 1.0 / P, c->inst[i].acc + 4, 1.0, c->inst[i].acc + 3, c->stream);
         }
       }
@@ -1121,6 +1320,7 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
     std::vector<double> accs(8 * B), mfv(5 * B);
     for (int i = 0; i < B; ++i) {
       Instance& I = c->inst[i];
+      const long n = I.n, n2 = n * n;
       hipLaunchKernelGGL(meanfield_kernel, dim3(1), dim3(256), 0, c->stream, (int)n, I.eps, I.h, I.eri, I.occ,
                          I.fock, I.mu, I.beta, d_dh[i], d_deri[i], I.mf);
       FTCC_HIP(hipMemcpyAsync(&mfv[5 * i], I.mf, sizeof(double) * 5, hipMemcpyDeviceToHost, c->stream));
@@ -1130,7 +1330,9 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(double) * n2, c->stream));
         hipLaunchKernelGGL(dh_assemble_kernel, dim3((n2 + 255) / 256), dim3(256), 0, c->stream, (int)n, I.occ, I.wo,
                            I.wv, I.ugrad_acc[0], I.ugrad_acc[1], I.ugrad_acc[2], I.ugrad_acc[3], dd);
-        FTCC_HIP(hipMemcpyAsync(dO_dh + (long)i * n2, dd, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
+        long off = 0;
+        for (int k = 0; k < i; ++k) off += (long)c->inst[k].n * c->inst[k].n;
+        FTCC_HIP(hipMemcpyAsync(dO_dh + off, dd, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
         FTCC_HIP(hipFreeAsync(dd, c->stream));
       }
     }
@@ -1162,7 +1364,7 @@ int ftcc_eval_residual(ftcc_ctx* c, int i, double mu, double beta, const double*
       FTCC_HIP(
           hipMemcpyAsync(c->amp[i * c->m + x] + n2, t2, sizeof(double) * n4, hipMemcpyHostToDevice, c->stream));
     }
-    c->ex_main->run_forward(c->stream);
+    forward(c);
     const int q = i * c->m;
     if (S1) FTCC_HIP(hipMemcpyAsync(S1, c->S[q], sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
     if (S2) FTCC_HIP(hipMemcpyAsync(S2, c->S[q] + n2, sizeof(double) * n4, hipMemcpyDeviceToHost, c->stream));
@@ -1182,7 +1384,7 @@ int ftcc_time_residual(ftcc_ctx* c, int reps, double* seconds_out, double* flops
     FTCC_HIP(hipEventCreate(&e0));
     FTCC_HIP(hipEventCreate(&e1));
     FTCC_HIP(hipEventRecord(e0, c->stream));
-    for (int r = 0; r < reps; ++r) c->ex_main->run_forward(c->stream);
+    for (int r = 0; r < reps; ++r) forward(c);
     FTCC_HIP(hipEventRecord(e1, c->stream));
     sync(c);
     float ms = 0.f;

@@ -42,6 +42,7 @@ struct TauProblem {
   double* out;                  // end state / previous adjoint state
   const double* lam_a;          // a_{p+1} for TAU_BETA
   unsigned long long* maxbits;  // [0] max |change|, [1] max |value| (bit patterns of doubles >= 0)
+  const int* active;            // STEP / LSTEP: instance still iterating (nullptr: always)
   double* partial;              // TAU_BETA: one partial sum per block
 };
 
@@ -85,6 +86,19 @@ void launch_block(const BlockSpec& b, hipStream_t s);
 void launch_fock_deriv(int n, const double* eri, const double* deri, const double* dh, const double* occ,
                        const double* docc, double* du, hipStream_t s);
 void launch_u_from_fock(int n, const double* fock, const double* eps, double* u, hipStream_t s);
+
+// DIIS: coefficients for every instance from its Gram matrix (ld x ld, count entries
+// valid), then the extrapolated iterate sum_j c_j (X_j + R_j) of one buffer.
+constexpr int kMaxDiis = 8;
+struct DiisTerms {
+  int k;
+  const double* coef;
+  const double* X[kMaxDiis];
+  const double* R[kMaxDiis];
+};
+void launch_diis_solve(int n_inst, const int* counts, const int* newest, const double* G, int ld, double* coef,
+                       hipStream_t s);
+void launch_diis_combine(long len, const DiisTerms& t, double* out, hipStream_t s);
 
 // sum of `count` doubles into *out (single block, deterministic)
 void launch_sum(const double* x, int count, double* out, hipStream_t s);

@@ -106,6 +106,12 @@ __device__ __forceinline__ double delta_of(const TauProblem& P, long e) {
   return P.eps[a] + P.eps[b] - P.eps[i] - P.eps[j];
 }
 
+// max that propagates NaN as +infinity (fmax would drop it)
+__device__ __forceinline__ double nan_max(double a, double b) {
+  if (b != b) return INFINITY;
+  return fmax(a, b);
+}
+
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) {
   // non-negative doubles order like their bit patterns
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
@@ -121,6 +127,7 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
     if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
   }
   const TauProblem& P = probs[lo];
+  if (P.active && *P.active == 0) return;   // converged instance of a batch: left unchanged
   const PanelRule R = *rule;
   const int m = R.m;
   const long base = (long)(b - prefix[lo]) * 1024;
@@ -138,8 +145,8 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
     if (mode == TAU_LSTEP) {
       for (int x = 0; x < m; ++x) {
         const double nv = -P.R[x][e];
-        mchg = fmax(mchg, fabs(nv - P.s[x][e]));
-        mval = fmax(mval, fabs(nv));
+        mchg = nan_max(mchg, fabs(nv - P.s[x][e]));
+        mval = nan_max(mval, fabs(nv));
         P.s[x][e] = nv;
       }
       continue;
@@ -174,7 +181,7 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
         for (int x = 0; x < m; ++x) P.s[x][e] = 0.0;
       } else if (mode == TAU_STEP) {
         for (int x = 0; x < m; ++x) {
-          mchg = fmax(mchg, fabs(P.s[x][e]));
+          mchg = nan_max(mchg, fabs(P.s[x][e]));
           P.s[x][e] = 0.0;
         }
       } else {
@@ -191,8 +198,8 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
         double v = (sb != 0.0) ? w.E[x] * sb : 0.0;
         for (int y = 0; y < m; ++y)
           if (Sv[y] != 0.0) v -= w.W[x][y] * Sv[y];
-        mchg = fmax(mchg, fabs(v - P.s[x][e]));
-        mval = fmax(mval, fabs(v));
+        mchg = nan_max(mchg, fabs(v - P.s[x][e]));
+        mval = nan_max(mval, fabs(v));
         P.s[x][e] = v;
       }
     } else if (mode == TAU_END) {
@@ -222,8 +229,8 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
       if (threadIdx.x < s) {
-        r0[threadIdx.x] = fmax(r0[threadIdx.x], r0[threadIdx.x + s]);
-        r1[threadIdx.x] = fmax(r1[threadIdx.x], r1[threadIdx.x + s]);
+        r0[threadIdx.x] = nan_max(r0[threadIdx.x], r0[threadIdx.x + s]);
+        r1[threadIdx.x] = nan_max(r1[threadIdx.x], r1[threadIdx.x + s]);
       }
       __syncthreads();
     }
@@ -358,6 +365,85 @@ __global__ void block_kernel(BlockSpec B) {
 void launch_block(const BlockSpec& b, hipStream_t s) {
   const long len = (b.rank == 4) ? (long)b.n * b.n * b.n * b.n : (long)b.n * b.n;
   hipLaunchKernelGGL(block_kernel, dim3((len + 255) / 256), dim3(256), 0, s, b);
+}
+
+// ------------------------------------------------------------------ DIIS (Anderson) extrapolation
+// One thread per instance: minimise |sum_j c_j r_j|^2 subject to sum_j c_j = 1 over
+// the `count` stored residuals (Gram matrix G, row-major with leading dimension
+// ld), by Gaussian elimination with partial pivoting on the bordered system.
+// A singular or non-finite system falls back to the newest iterate (plain Picard).
+__global__ void diis_solve_kernel(int n_inst, const int* counts, const int* newest, const double* G, int ld,
+                                  double* coef) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_inst) return;
+  const int k = counts[i];
+  const double* g = G + (long)i * ld * ld;
+  double* c = coef + (long)i * ld;
+  double A[9][10];
+  double scale = 0.0;
+  for (int a = 0; a < k; ++a) scale = fmax(scale, fabs(g[a * ld + a]));
+  bool ok = (k > 1) && scale > 0.0 && isfinite(scale);
+  if (ok) {
+    for (int a = 0; a < k; ++a) {
+      for (int b = 0; b < k; ++b) A[a][b] = g[a * ld + b] / scale;
+      A[a][k] = -1.0;
+      A[a][k + 1] = 0.0;
+    }
+    for (int b = 0; b < k; ++b) A[k][b] = -1.0;
+    A[k][k] = 0.0;
+    A[k][k + 1] = -1.0;
+    const int nn = k + 1;
+    for (int col = 0; col < nn && ok; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < nn; ++r)
+        if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+      if (!(fabs(A[piv][col]) > 1e-14)) {
+        ok = false;
+        break;
+      }
+      if (piv != col)
+        for (int q = 0; q <= nn; ++q) {
+          const double t = A[col][q];
+          A[col][q] = A[piv][q];
+          A[piv][q] = t;
+        }
+      for (int r = 0; r < nn; ++r) {
+        if (r == col) continue;
+        const double f = A[r][col] / A[col][col];
+        for (int q = col; q <= nn; ++q) A[r][q] -= f * A[col][q];
+      }
+    }
+    if (ok)
+      for (int a = 0; a < k; ++a) {
+        c[a] = A[a][nn] / A[a][a];
+        if (!isfinite(c[a])) ok = false;
+      }
+  }
+  if (!ok)
+    for (int a = 0; a < ld; ++a) c[a] = (a == newest[i]) ? 1.0 : 0.0;
+}
+
+void launch_diis_solve(int n_inst, const int* counts, const int* newest, const double* G, int ld, double* coef,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(diis_solve_kernel, dim3((n_inst + 63) / 64), dim3(64), 0, s, n_inst, counts, newest, G, ld,
+                     coef);
+}
+
+// out[e] = sum_j coef[j] * (X_j[e] + R_j[e])
+__global__ void diis_combine_kernel(long len, DiisTerms t, double* out) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double v = 0.0;
+  for (int j = 0; j < t.k; ++j) {
+    const double cj = t.coef[j];
+    if (cj != 0.0) v += cj * (t.X[j][e] + t.R[j][e]);
+  }
+  out[e] = v;
+}
+
+void launch_diis_combine(long len, const DiisTerms& t, double* out, hipStream_t s) {
+  if (len <= 0) return;
+  hipLaunchKernelGGL(diis_combine_kernel, dim3((len + 255) / 256), dim3(256), 0, s, len, t, out);
 }
 
 // ------------------------------------------------------------------ small utilities

@@ -31,7 +31,7 @@ class FTCCError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("n_tau", ctypes.c_int), ("nodes_per_panel", ctypes.c_int), ("propagator", ctypes.c_int),
                 ("occ_thresh", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("checkpoint", ctypes.c_int)]
+                ("checkpoint", ctypes.c_int), ("diis_depth", ctypes.c_int)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -151,6 +151,8 @@ class Context:
         eps = _f64(eps, (n,))
         _check(self.lib.ftcc_set_hamiltonian(self._h, int(inst), n, _ptr(h), _ptr(eri), _ptr(eps)))
         self.n = n
+        self.sizes = getattr(self, "sizes", {})
+        self.sizes[int(inst)] = n
 
     def solve(self, mu, beta, raise_on_status=True):
         mu = _f64(np.broadcast_to(np.asarray(mu, float), (self.B,)))
@@ -189,28 +191,37 @@ class Context:
         return out
 
     def response(self, want_mu=True, want_beta=True, want_h=True, deri_dtheta=None, dh_dtheta=None):
-        B, n = self.B, self.n
+        """dOmega/dmu, dbeta, dh (list of n_i x n_i arrays) and the optional theta direction."""
+        B = self.B
+        sizes = [self.sizes[i] for i in range(B)]
+        n = max(sizes)
         dmu = np.zeros(B) if want_mu else None
         dbeta = np.zeros(B) if want_beta else None
-        dh = np.zeros((B, n, n)) if want_h else None
+        dh_flat = np.zeros(sum(k * k for k in sizes)) if want_h else None
         dth = None
         keep = []
         p_deri = p_dh = None
         if deri_dtheta is not None or dh_dtheta is not None:
             dth = np.zeros(B)
             if deri_dtheta is not None:
-                arrs = [None if a is None else _f64(a, (n, n, n, n)) for a in deri_dtheta]
+                arrs = [None if a is None else _f64(a, (sizes[i],) * 4) for i, a in enumerate(deri_dtheta)]
                 keep += arrs
                 p_deri = (_D * B)(*[ctypes.cast(None, _D) if a is None else _ptr(a) for a in arrs])
             if dh_dtheta is not None:
-                arrs = [None if a is None else _f64(a, (n, n)) for a in dh_dtheta]
+                arrs = [None if a is None else _f64(a, (sizes[i],) * 2) for i, a in enumerate(dh_dtheta)]
                 keep += arrs
                 p_dh = (_D * B)(*[ctypes.cast(None, _D) if a is None else _ptr(a) for a in arrs])
         nul = ctypes.cast(None, _D)
         _check(self.lib.ftcc_response(self._h, _ptr(dmu) if dmu is not None else nul,
                                       _ptr(dbeta) if dbeta is not None else nul,
-                                      _ptr(dh) if dh is not None else nul,
+                                      _ptr(dh_flat) if dh_flat is not None else nul,
                                       p_deri, p_dh, _ptr(dth) if dth is not None else nul))
+        dh = None
+        if dh_flat is not None:
+            dh, off = [], 0
+            for k in sizes:
+                dh.append(dh_flat[off:off + k * k].reshape(k, k))
+                off += k * k
         return dict(mu=dmu, beta=dbeta, h=dh, theta=dth)
 
     def eval_residual(self, inst, mu, beta, t1, t2):

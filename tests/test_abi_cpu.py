@@ -51,5 +51,5 @@ def test_abi_version_and_error_string(lib):
 def test_default_options(lib):
     from paper_2004_01729_amd import ftcc
     o = ftcc.default_options()
-    assert (o.n_tau, o.nodes_per_panel, o.propagator, o.max_iter, o.checkpoint) == (16, 4, 0, 200, 0)
+    assert (o.n_tau, o.nodes_per_panel, o.propagator, o.max_iter, o.checkpoint, o.diis_depth) == (16, 4, 0, 200, 0, 0)
     assert o.tol == 1e-12 and o.occ_thresh == 0.0

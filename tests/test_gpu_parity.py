@@ -110,3 +110,24 @@ def test_adjoint_and_response_small(ftcc):
         assert abs(res[key][0] - ref) < 1e-8 * max(1.0, abs(ref)), key
     ref_h = S.d_omega_dh(model, gr, sol, adj)
     assert _rel(res["h"][0], ref_h) < 1e-8
+
+
+def test_forward_and_adjoint_with_diis(ftcc):
+    """DIIS changes the iteration, not the fixed point: Omega and dOmega/dmu as the
+    plain oracle march."""
+    s = fi.hubbard_config(L=4, U=4.0, T=1.0)
+    _say("[diis] hubbard L=4 U=4 T=1 n_tau=8 diis_depth=6")
+    ctx = ftcc.Context(1, n_tau=8, nodes_per_panel=4, tol=1e-13, diis_depth=6)
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    ctx.solve(s.mu, s.beta)
+    om, _ = ctx.grand_potential()
+    ctx.lam()
+    r = ctx.response(want_mu=True, want_beta=False, want_h=False)
+    ctx.close()
+    model = _oracle(s.h, s.eri, s.eps, s.mu, s.beta)
+    gr = G.Grid(s.beta, 2, 4)
+    sol = S.solve(model, gr, tol=1e-13)
+    adj = S.adjoint(model, gr, sol, tol=1e-13)
+    assert abs(om[0] - sol.omega) < 1e-10 * abs(sol.omega)
+    ref = S.d_omega(model, gr, sol, adj, "mu")
+    assert abs(r["mu"][0] - ref) < 1e-8 * max(1.0, abs(ref))
