@@ -53,13 +53,19 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def step(ctx, s):
+def step(ctx, s, times=None):
+    t0 = time.perf_counter()
     ctx.solve(s.mu, s.beta)
     ctx.grand_potential()
     st0 = ctx.stats()
+    t1 = time.perf_counter()
     ctx.lam()
     st1 = ctx.stats()
     ctx.response(want_mu=True, want_beta=True, want_h=True)
+    t2 = time.perf_counter()
+    if times is not None:
+        times["forward"] += t1 - t0
+        times["gradient"] += t2 - t1
     return st0, st1
 
 
@@ -134,9 +140,10 @@ def main():
     ctx.kernel_profile(1)            # start recording the dominant GEMM kernel
     evals = 0
     vjps = 0
+    times = dict(forward=0.0, gradient=0.0)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st0, st1 = step(ctx, s)
+        st0, st1 = step(ctx, s, times)
         evals += st0["resid_evals"]
         vjps += st1["vjp_evals"]
     torch.cuda.synchronize()
@@ -148,6 +155,25 @@ def main():
 
     om, parts = ctx.grand_potential()
     resp = ctx.response(want_mu=True, want_beta=True, want_h=False)
+    # gradient of Omega: adjoint (Lambda + response, all of dOmega/dmu, dbeta, dh_pq)
+    # against central finite differences, which cost two forward solves per parameter
+    t_fwd = times["forward"] / args.steps
+    t_grad = times["gradient"] / args.steps
+    d = 1e-4
+    tf0 = time.perf_counter()
+    ctx.solve(s.mu + d, s.beta)
+    op = ctx.grand_potential()[0][0]
+    ctx.solve(s.mu - d, s.beta)
+    om_ = ctx.grand_potential()[0][0]
+    t_fd_mu = time.perf_counter() - tf0
+    fd_mu = (op - om_) / (2 * d)
+    n_h = s.n * (s.n + 1) // 2
+    gradient = dict(adjoint_s=t_grad, forward_s=t_fwd, fd_mu_measured_s=t_fd_mu,
+                    fd_mu_beta_s=2 * t_fd_mu, fd_all_params_s_extrapolated=(2 + n_h) * t_fd_mu,
+                    n_params=2 + n_h, adjoint_vs_fd_speedup_mu_beta=2 * t_fd_mu / t_grad,
+                    adjoint_vs_fd_speedup_all=(2 + n_h) * t_fd_mu / t_grad,
+                    dOmega_dmu_adjoint=float(resp["mu"][0]), dOmega_dmu_fd=float(fd_mu),
+                    fd_rel_diff=abs(fd_mu - resp["mu"][0]) / max(1.0, abs(resp["mu"][0])))
     value = evals / el
     achieved = prof["flops"] / prof["seconds"] if prof["seconds"] > 0 else 0.0
     line = {
@@ -165,7 +191,7 @@ def main():
         "data": "synthetic",
         "config": dict(cfg, residual_evals_per_step=evals / args.steps, vjp_evals_per_step=vjps / args.steps,
                        omega=float(om[0]), omega_cc=float(parts[0, 2]), dOmega_dmu=float(resp["mu"][0]),
-                       dOmega_dbeta=float(resp["beta"][0])),
+                       dOmega_dbeta=float(resp["beta"][0]), gradient_vs_fd=gradient),
         "roofline": {
             "bound": "mfma",
             "achieved": achieved / 1e12,
