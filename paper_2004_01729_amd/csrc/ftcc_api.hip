@@ -203,7 +203,7 @@ struct Instance {
   double *occ = nullptr, *wo = nullptr, *wv = nullptr, *fock = nullptr;
   double *dn = nullptr, *dwo = nullptr, *dwv = nullptr, *du_raw = nullptr, *u_raw = nullptr;
   std::map<std::string, double*> blk, dblk;
-  std::vector<double*> grid, resid, sb, lam, lamt, abuf;
+  std::vector<double*> grid, resid, sb, lam, abuf;
   double* mf = nullptr;          // meanfield outputs (5)
   double* acc = nullptr;         // response accumulators: [0] mu, [1] beta, [2] theta, [3] beta grid
   std::vector<double> energies;  // per node
@@ -225,8 +225,13 @@ struct ftcc_ctx {
   Program prog;
   std::unique_ptr<Executor> ex_main, ex_d;
   bool built = false, solved = false, have_lambda = false;
-  // per problem (instance * m + slot)
+  // per node (instance * m + x): amplitudes, residuals, energies, gradients, cotangents
   std::vector<double*> amp, S, e, gr, cot, ebar, dS, de;
+  // per executor slot (instance * slots + slot); the same pointers as the node
+  // buffers when every node of a panel has its own slot (slots == m)
+  int slots = 0;
+  std::vector<double*> s_amp, s_S, s_e, s_gr, s_cot, s_ebar, s_dS, s_de;
+  std::vector<std::array<double*, 4>> s_ugrad;
   std::map<std::pair<int, int>, double*> inter, inter_grad, dderived;   // (tensor, problem) / (tensor, inst)
   std::map<std::pair<int, int>, double*> derived;
   std::vector<std::array<double*, 4>> ugrad;
@@ -433,44 +438,98 @@ void build(ftcc_ctx* c) {
     }
     I.energies.assign(P * m, 0.0);
   }
-  const int np = B * m;
-  c->amp.resize(np);
-  c->S.resize(np);
-  c->e.resize(np);
-  c->gr.resize(np);
-  c->cot.resize(np);
-  c->ebar.resize(np);
-  c->dS.resize(np);
-  c->de.resize(np);
-  c->ugrad.resize(np);
-  c->scratch.a.resize(np);
-  c->scratch.b.resize(np);
-  c->scratch.c.resize(np);
-  c->scratch.part.resize(np);
-  std::vector<ProblemRef> probs;
+  // Executor slots per instance: every node of a panel evaluated in one grouped
+  // launch (slots = m) unless the per-slot working set (about 40 n^4 doubles:
+  // intermediates, their gradients, scratch) would take more than half of the
+  // free device memory; then the nodes go through one slot in turn.
+  {
+    size_t free_b = 0, total_b = 0;
+    FTCC_HIP(hipMemGetInfo(&free_b, &total_b));
+    double need = 0.0;
+    for (int i = 0; i < B; ++i) need += 40.0 * m * std::pow((double)c->inst[i].n, 4) * sizeof(double);
+    c->slots = (need > 0.5 * (double)free_b) ? 1 : m;
+    const char* senv = std::getenv("FTCC_NODE_SLOTS");
+    if (senv && senv[0] == '1') c->slots = 1;
+  }
+  const int SL = c->slots;
+  const int nn = B * m;
+  c->amp.resize(nn);
+  c->S.resize(nn);
+  c->e.resize(nn);
+  c->gr.resize(nn);
+  c->cot.resize(nn);
+  c->ebar.resize(nn);
+  c->dS.resize(nn);
+  c->de.resize(nn);
+  c->ugrad.resize(nn);
   for (int i = 0; i < B; ++i)
     for (int x = 0; x < m; ++x) {
       const int p = i * m + x;
       const int n = c->inst[i].n;
       const long n2 = (long)n * n, n4 = n2 * n2, len = n2 + n4;
-      probs.push_back({i, x, n});
       c->amp[p] = c->dalloc(len);
       c->S[p] = c->dalloc(len);
       c->e[p] = c->dalloc(1);
       c->gr[p] = c->dalloc(len);
       c->cot[p] = c->dalloc(len);
       c->ebar[p] = c->dalloc(1);
-      c->dS[p] = c->dalloc(len);
+      // with one slot the derivative residuals reuse the gradient buffers (never live together)
+      c->dS[p] = (SL == m) ? c->dalloc(len) : c->gr[p];
       c->de[p] = c->dalloc(1);
       for (int k = 0; k < 4; ++k) c->ugrad[p][k] = c->dalloc(n2);
-      c->scratch.a[p] = c->dalloc(n4);
-      c->scratch.b[p] = c->dalloc(n4);
-      c->scratch.c[p] = c->dalloc(n4);
-      c->scratch.part[p] = c->dalloc(n4);
       const double eb = c->rule.b[x] / P;   // (1/beta) g_x
       FTCC_HIP(hipMemcpy(c->ebar[p], &eb, sizeof(double), hipMemcpyHostToDevice));
+      (void)n4;
     }
-  c->scratch.dot_partial = c->dalloc((size_t)np * 64 + 64);
+  const int np = B * SL;
+  c->scratch.a.resize(np);
+  c->scratch.b.resize(np);
+  c->scratch.c.resize(np);
+  c->scratch.part.resize(np);
+  c->s_amp.resize(np);
+  c->s_S.resize(np);
+  c->s_e.resize(np);
+  c->s_gr.resize(np);
+  c->s_cot.resize(np);
+  c->s_ebar.resize(np);
+  c->s_dS.resize(np);
+  c->s_de.resize(np);
+  c->s_ugrad.resize(np);
+  std::vector<ProblemRef> probs;
+  for (int i = 0; i < B; ++i)
+    for (int x = 0; x < SL; ++x) {
+      const int q = i * SL + x;
+      const int n = c->inst[i].n;
+      const long n2 = (long)n * n, n4 = n2 * n2, len = n2 + n4;
+      probs.push_back({i, x, n});
+      if (SL == m) {
+        const int p = i * m + x;
+        c->s_amp[q] = c->amp[p];
+        c->s_S[q] = c->S[p];
+        c->s_e[q] = c->e[p];
+        c->s_gr[q] = c->gr[p];
+        c->s_cot[q] = c->cot[p];
+        c->s_ebar[q] = c->ebar[p];
+        c->s_dS[q] = c->dS[p];
+        c->s_de[q] = c->de[p];
+        c->s_ugrad[q] = c->ugrad[p];
+      } else {
+        c->s_amp[q] = c->dalloc(len);
+        c->s_S[q] = c->dalloc(len);
+        c->s_e[q] = c->dalloc(1);
+        c->s_gr[q] = c->dalloc(len);
+        c->s_cot[q] = c->dalloc(len);
+        c->s_ebar[q] = c->dalloc(1);
+        c->s_dS[q] = c->s_S[q];       // the derivative executor runs apart from the main one
+        c->s_de[q] = c->dalloc(1);
+        for (int k = 0; k < 4; ++k) c->s_ugrad[q][k] = c->dalloc(n2);
+      }
+      c->scratch.a[q] = c->dalloc(n4);
+      c->scratch.b[q] = c->dalloc(n4);
+      c->scratch.c[q] = c->dalloc(n4);
+      c->scratch.part[q] = c->dalloc(n4);
+    }
+  c->scratch.dot_partial = c->dalloc((size_t)nn * 64 + 64);
   c->d_maxbits = (unsigned long long*)c->dalloc(2 * B);
   c->d_active = (int*)c->dalloc(B);
   {
@@ -525,15 +584,15 @@ void build(ftcc_ctx* c) {
     const TensorDecl& d = prog.t[t];
     const long n = probs[p].n, n2 = n * n;
     const long cnt = ipow(n, d.rank);
-    if (t == id_t1) return grad ? c->gr[p] : c->amp[p];
-    if (t == id_t2) return grad ? c->gr[p] + n2 : c->amp[p] + n2;
+    if (t == id_t1) return grad ? c->s_gr[p] : c->s_amp[p];
+    if (t == id_t2) return grad ? c->s_gr[p] + n2 : c->s_amp[p] + n2;
     if (grad) {
-      if (t == id_S1) return c->cot[p];
-      if (t == id_S2) return c->cot[p] + n2;
-      if (t == id_E) return c->ebar[p];
+      if (t == id_S1) return c->s_cot[p];
+      if (t == id_S2) return c->s_cot[p] + n2;
+      if (t == id_E) return c->s_ebar[p];
       if (d.kind == T_CONST) {
         for (int k = 0; k < 4; ++k)
-          if (d.name == kU[k]) return c->ugrad[p][k];
+          if (d.name == kU[k]) return c->s_ugrad[p][k];
         fail(FTCC_EINVAL, "no gradient buffer for " + d.name);
       }
       return tensor_buf(c->inter_grad, t, p, cnt);
@@ -548,9 +607,9 @@ void build(ftcc_ctx* c) {
     const long n = probs[p].n, n2 = n * n;
     if (d.kind == T_CONST) return c->inst[i].blk[d.name];
     if (d.derived) return tensor_buf(c->derived, t, i, ipow(n, d.rank));
-    if (t == id_S1) return c->S[p];
-    if (t == id_S2) return c->S[p] + n2;
-    if (t == id_E) return c->e[p];
+    if (t == id_S1) return c->s_S[p];
+    if (t == id_S2) return c->s_S[p] + n2;
+    if (t == id_E) return c->s_e[p];
     fail(FTCC_EINVAL, "unbound tensor " + d.name);
   };
   Binder bind_d = [&, c](int t, int p, bool grad) -> double* {
@@ -560,9 +619,9 @@ void build(ftcc_ctx* c) {
     const long n = probs[p].n, n2 = n * n;
     if (d.kind == T_CONST) return c->inst[i].dblk[d.name];
     if (d.derived) return tensor_buf(c->dderived, t, i, ipow(n, d.rank));
-    if (t == id_S1) return c->dS[p];
-    if (t == id_S2) return c->dS[p] + n2;
-    if (t == id_E) return c->de[p];
+    if (t == id_S1) return c->s_dS[p];
+    if (t == id_S2) return c->s_dS[p] + n2;
+    if (t == id_E) return c->s_de[p];
     fail(FTCC_EINVAL, "unbound tensor " + d.name);
   };
   auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
@@ -601,14 +660,81 @@ void build(ftcc_ctx* c) {
 }
 
 // the forward / backward programs: graph replay unless the kernel profiler records events
-void forward(ftcc_ctx* c) {
+void run_fwd_slots(ftcc_ctx* c) {
   if (c->g_fwd && !c->prof.enabled) FTCC_HIP(hipGraphLaunch(c->g_fwd, c->stream));
   else c->ex_main->run_forward(c->stream);
 }
 
-void backward(ftcc_ctx* c) {
+void run_bwd_slots(ftcc_ctx* c) {
   if (c->g_bwd && !c->prof.enabled) FTCC_HIP(hipGraphLaunch(c->g_bwd, c->stream));
   else c->ex_main->run_backward(c->stream);
+}
+
+long node_len(ftcc_ctx* c, int i) {
+  const long n = c->inst[i].n;
+  return n * n + n * n * n * n;
+}
+
+void dcopy(ftcc_ctx* c, double* dst, const double* src, long count) {
+  FTCC_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToDevice, c->stream));
+}
+
+// forward residuals of every node of the panel slots (node amplitudes -> S, E)
+void forward(ftcc_ctx* c) {
+  if (c->slots == c->m) {
+    run_fwd_slots(c);
+    return;
+  }
+  for (int x = 0; x < c->m; ++x) {
+    for (int i = 0; i < c->B; ++i) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    run_fwd_slots(c);
+    for (int i = 0; i < c->B; ++i) {
+      dcopy(c, c->S[i * c->m + x], c->s_S[i], node_len(c, i));
+      dcopy(c, c->e[i * c->m + x], c->s_e[i], 1);
+    }
+  }
+}
+
+// reverse pass of every node (cotangents cot, E weights ebar -> gradients gr, ugrad).
+// With one slot each node's forward tape is recomputed first.
+void backward(ftcc_ctx* c) {
+  if (c->slots == c->m) {
+    run_bwd_slots(c);
+    return;
+  }
+  for (int x = 0; x < c->m; ++x) {
+    for (int i = 0; i < c->B; ++i) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    run_fwd_slots(c);
+    c->resid_evals += c->B;
+    for (int i = 0; i < c->B; ++i) {
+      const int p = i * c->m + x;
+      dcopy(c, c->s_cot[i], c->cot[p], node_len(c, i));
+      dcopy(c, c->s_ebar[i], c->ebar[p], 1);
+    }
+    run_bwd_slots(c);
+    for (int i = 0; i < c->B; ++i) {
+      const int p = i * c->m + x;
+      const long n = c->inst[i].n;
+      dcopy(c, c->gr[p], c->s_gr[i], node_len(c, i));
+      for (int k = 0; k < 4; ++k) dcopy(c, c->ugrad[p][k], c->s_ugrad[i][k], n * n);
+    }
+  }
+}
+
+// derivative-integral residuals of every node (-> dS, dE)
+void d_forward(ftcc_ctx* c) {
+  if (c->slots == c->m) {
+    c->ex_d->run_forward(c->stream);
+    return;
+  }
+  for (int x = 0; x < c->m; ++x) {
+    for (int i = 0; i < c->B; ++i) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    c->ex_d->run_forward(c->stream);
+    for (int i = 0; i < c->B; ++i) {
+      dcopy(c, c->dS[i * c->m + x], c->s_dS[i], node_len(c, i));
+      dcopy(c, c->de[i * c->m + x], c->s_de[i], 1);
+    }
+  }
 }
 
 void clear_tau_cache(ftcc_ctx* c) {
@@ -1113,12 +1239,9 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
       Instance& I = c->inst[i];
       const long n = I.n, len = n * n + n * n * n * n;
       if (I.lam.empty()) {
+        // lambda-tilde is not stored: it is recomputed from lambda and a_{p+1} when needed
         I.lam.resize(P * m);
-        I.lamt.resize(P * m);
-        for (int k = 0; k < P * m; ++k) {
-          I.lam[k] = c->dalloc(len);
-          I.lamt[k] = c->dalloc(len);
-        }
+        for (int k = 0; k < P * m; ++k) I.lam[k] = c->dalloc(len);
         I.abuf.resize(P + 1);
         for (int p = 0; p <= P; ++p) I.abuf[p] = c->dalloc(len);
       }
@@ -1177,11 +1300,6 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
           for (int i = 0; i < B; ++i)
             if (active[i]) status[i] = FTCC_ENOCONV;
       }
-      tau_run(c, TAU_LAMT, p);   // lambda-tilde of the converged lambda
-      for (int i = 0; i < B; ++i) {
-        const long n = c->inst[i].n, len = n * n + n * n * n * n;
-        for (int x = 0; x < m; ++x) copy_d(c, c->inst[i].lamt[p * m + x], c->cot[i * m + x], len);
-      }
       tau_run(c, TAU_APREV, p);
     }
     FTCC_HIP(hipEventRecord(e1, c->stream));
@@ -1213,11 +1331,17 @@ int ftcc_get_lambda(ftcc_ctx* c, int i, int k, double* l1, double* l2, double* l
     if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
     if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
     const long n = c->inst[i].n, n2 = n * n;
+    FTCC_HIP(hipSetDevice(c->device));
     sync(c);
     if (l1) FTCC_HIP(hipMemcpy(l1, c->inst[i].lam[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
     if (l2) FTCC_HIP(hipMemcpy(l2, c->inst[i].lam[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
-    if (lt1) FTCC_HIP(hipMemcpy(lt1, c->inst[i].lamt[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
-    if (lt2) FTCC_HIP(hipMemcpy(lt2, c->inst[i].lamt[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+    if (lt1 || lt2) {
+      tau_run(c, TAU_LAMT, k / c->m);
+      sync(c);
+      const double* src = c->cot[i * c->m + k % c->m];
+      if (lt1) FTCC_HIP(hipMemcpy(lt1, src, sizeof(double) * n2, hipMemcpyDeviceToHost));
+      if (lt2) FTCC_HIP(hipMemcpy(lt2, src + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+    }
   });
 }
 
@@ -1282,10 +1406,7 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
     };
     for (int p = 0; p < P; ++p) {
       load_panel(c, p);
-      for (int i = 0; i < B; ++i) {
-        const long n = c->inst[i].n, len = n * n + n * n * n * n;
-        for (int x = 0; x < m; ++x) copy_d(c, c->cot[i * m + x], c->inst[i].lamt[p * m + x], len);
-      }
+      tau_run(c, TAU_LAMT, p);   // lambda-tilde of the panel into the cotangent buffers
       if (dO_dh) {
         backward(c);
         for (int i = 0; i < B; ++i) {
@@ -1312,7 +1433,7 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         if (which == 2 && !want_theta) continue;
         for (int i = 0; i < B; ++i) deriv_setup(c, i, which, d_dh[i], d_deri[i]);
         c->ex_d->run_setup(c->stream);
-        c->ex_d->run_forward(c->stream);
+        d_forward(c);
         accumulate(which);
       }
     }

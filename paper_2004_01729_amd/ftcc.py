@@ -122,7 +122,7 @@ class Context:
         self.B = int(n_instances)
         self._h = ctypes.c_void_p()
         _check(self.lib.ftcc_create(ctypes.byref(self._h), int(device), self.B, ctypes.byref(self.opt)))
-        self.n = None
+        self.sizes = {}
 
     def close(self):
         if self._h:
@@ -150,8 +150,6 @@ class Context:
         eri = _f64(eri, (n, n, n, n))
         eps = _f64(eps, (n,))
         _check(self.lib.ftcc_set_hamiltonian(self._h, int(inst), n, _ptr(h), _ptr(eri), _ptr(eps)))
-        self.n = n
-        self.sizes = getattr(self, "sizes", {})
         self.sizes[int(inst)] = n
 
     def solve(self, mu, beta, raise_on_status=True):
@@ -170,8 +168,13 @@ class Context:
         _check(self.lib.ftcc_grand_potential(self._h, _ptr(om), _ptr(parts)))
         return om, parts
 
+    def _size(self, inst):
+        if int(inst) not in self.sizes:
+            raise FTCCError(EINVAL, f"instance {inst} has no Hamiltonian")
+        return self.sizes[int(inst)]
+
     def amplitudes(self, inst, node):
-        n = self.n
+        n = self._size(inst)
         t1 = np.zeros((n, n))
         t2 = np.zeros((n, n, n, n))
         _check(self.lib.ftcc_get_amplitudes(self._h, int(inst), int(node), _ptr(t1), _ptr(t2)))
@@ -184,10 +187,15 @@ class Context:
         _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE))
         return its, st
 
-    def get_lambda(self, inst, node):
-        n = self.n
-        out = [np.zeros((n, n)), np.zeros((n,) * 4), np.zeros((n, n)), np.zeros((n,) * 4)]
-        _check(self.lib.ftcc_get_lambda(self._h, int(inst), int(node), *[_ptr(a) for a in out]))
+    def get_lambda(self, inst, node, tilde=True):
+        """[lambda1, lambda2, lambda-tilde1, lambda-tilde2] of one node (the last two None
+        unless `tilde`)."""
+        n = self._size(inst)
+        out = [np.zeros((n, n)), np.zeros((n,) * 4)]
+        out += [np.zeros((n, n)), np.zeros((n,) * 4)] if tilde else [None, None]
+        nul = ctypes.cast(None, _D)
+        _check(self.lib.ftcc_get_lambda(self._h, int(inst), int(node),
+                                        *[nul if a is None else _ptr(a) for a in out]))
         return out
 
     def response(self, want_mu=True, want_beta=True, want_h=True, deri_dtheta=None, dh_dtheta=None):
@@ -225,7 +233,7 @@ class Context:
         return dict(mu=dmu, beta=dbeta, h=dh, theta=dth)
 
     def eval_residual(self, inst, mu, beta, t1, t2):
-        n = self.n
+        n = self._size(inst)
         t1 = _f64(t1, (n, n))
         t2 = _f64(t2, (n, n, n, n))
         S1 = np.zeros((n, n))

@@ -68,3 +68,19 @@ def test_checkpoint_reproduces_adjoint(F):
     assert np.array_equal(om0, om1)
     assert np.allclose(r0["mu"], r1["mu"], rtol=1e-13, atol=1e-14)
     assert np.allclose(r0["beta"], r1["beta"], rtol=1e-13, atol=1e-14)
+
+
+def test_one_slot_mode_matches(F, monkeypatch):
+    """The memory-lean schedule (one executor slot per instance, nodes evaluated one
+    after another) chosen automatically for large n gives the same Omega, gradients
+    and Lambda as the all-nodes-at-once schedule."""
+    systems = _systems()[:3]
+    print("[slots] one executor slot vs m slots, checkpoint=1", flush=True)
+    om0, r0 = _run(F, systems, checkpoint=1)
+    monkeypatch.setenv("FTCC_NODE_SLOTS", "1")
+    om1, r1 = _run(F, systems, checkpoint=1)
+    assert np.allclose(om0, om1, rtol=1e-13, atol=0)
+    for key in ("mu", "beta"):
+        assert np.allclose(r0[key], r1[key], rtol=1e-12, atol=1e-13), key
+    for a, b in zip(r0["h"], r1["h"]):
+        assert np.abs(a - b).max() < 1e-12
