@@ -16,7 +16,12 @@ metric: tau-point T2 residual evaluations per second of whole-step wall time
 re-evaluations inside the adjoint and response phases).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|hubbard6|hubbard10]
-                       [--no-cpu-baseline]
+                       [--no-cpu-baseline] [--mode step|residual|copy] [--reps R]
+
+--mode residual times R back-to-back residual evaluations of every node of the
+last panel at the converged amplitudes (kernel throughput alone); --mode copy
+runs R device-to-device copies of 1 GiB (the byte-counter calibration for the
+traffic figures).  Both print one JSON line of their own.
 """
 from __future__ import annotations
 
@@ -69,6 +74,32 @@ def step(ctx, s, times=None):
     return st0, st1
 
 
+def residual_throughput(ctx, reps, n_tau):
+    """Back-to-back residual evaluations of every node of the last panel (the
+    converged amplitudes the solve left there), between HIP events."""
+    sec, fl = ctx.time_residual(reps)
+    m = ctx.opt.nodes_per_panel
+    return dict(evals_per_s=reps * m / sec, ms_per_eval=1e3 * sec / (reps * m),
+                gemm_tflops=fl * reps / sec / 1e12, frac_fp64_mfma=fl * reps / sec / PEAK_FP64_MFMA,
+                gemm_flop_per_eval=fl / m)
+
+
+def copy_calibration(reps, nbytes=1 << 30):
+    """Plain device-to-device copies of known size: what FETCH_SIZE / WRITE_SIZE
+    read for exactly nbytes read and nbytes written per launch."""
+    import torch
+    x = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").uniform_()
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return dict(mode="copy", bytes_read_per_launch=nbytes, bytes_written_per_launch=nbytes, launches=reps,
+                gbps=2 * nbytes * reps / el / 1e9)
+
+
 def cpu_baseline(s, budget_s=20.0):
     """The oracle as it stands (spin-summed restricted kernels, numpy/BLAS on
     the host) on a bounded sample: the einsum items of one residual evaluation
@@ -119,6 +150,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ueg57")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy"))
+    ap.add_argument("--reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -130,9 +163,18 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.mode == "copy":
+        print(json.dumps(copy_calibration(args.reps)), flush=True)
+        return
     s, opts, cfg = workload(args.workload)
     ctx = F.Context(1, **opts)
     ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    if args.mode == "residual":
+        ctx.solve(s.mu, s.beta)
+        r = residual_throughput(ctx, args.reps, opts["n_tau"])
+        ctx.close()
+        print(json.dumps(dict(mode="residual", workload=cfg["workload"], reps=args.reps, **r)), flush=True)
+        return
     for _ in range(args.warmup):
         step(ctx, s)
     torch.cuda.synchronize()
@@ -155,6 +197,7 @@ def main():
 
     om, parts = ctx.grand_potential()
     resp = ctx.response(want_mu=True, want_beta=True, want_h=False)
+    m1 = residual_throughput(ctx, 3, n_tau)
     # gradient of Omega: adjoint (Lambda + response, all of dOmega/dmu, dbeta, dh_pq)
     # against central finite differences, which cost two forward solves per parameter
     t_fwd = times["forward"] / args.steps
@@ -191,7 +234,8 @@ def main():
         "data": "synthetic",
         "config": dict(cfg, residual_evals_per_step=evals / args.steps, vjp_evals_per_step=vjps / args.steps,
                        omega=float(om[0]), omega_cc=float(parts[0, 2]), dOmega_dmu=float(resp["mu"][0]),
-                       dOmega_dbeta=float(resp["beta"][0]), gradient_vs_fd=gradient),
+                       dOmega_dbeta=float(resp["beta"][0]), gradient_vs_fd=gradient,
+                       residual_throughput=m1),
         "roofline": {
             "bound": "mfma",
             "achieved": achieved / 1e12,

@@ -26,7 +26,8 @@
  *     the last failure on the calling thread is ftcc_last_error();
  *   - pointer arguments are HOST memory owned by the caller, read or written
  *     only during the call; the library keeps its own device copies;
- *   - a context owns all device memory it allocates and frees it in ftcc_destroy;
+ *   - a context owns all device memory it allocates and frees it in ftcc_destroy
+ *     (through the caller's allocator when ftcc_set_allocator installed one);
  *   - one context must not be used by two threads at once;
  *   - required order: create -> set_hamiltonian (every instance) ->
  *     solve_amplitudes -> grand_potential -> lambda -> response.
@@ -37,11 +38,13 @@
 #ifndef FTCC_H
 #define FTCC_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
 
-#define FTCC_ABI_VERSION 1
+#define FTCC_ABI_VERSION 2
 
 #define FTCC_OK 0
 #define FTCC_EINVAL -1      /* bad argument */
@@ -65,9 +68,15 @@ typedef struct {
   int diis_depth;       /* 0: plain fixed-point sweeps; 2..8: DIIS (Anderson) extrapolation over
                            this many sweeps, forward and adjoint (needs 2 * depth * m * (n^2 + n^4)
                            doubles per instance) */
+  size_t mem_cap_bytes; /* 0: no cap.  Otherwise an upper bound on the device memory the context
+                           allocates; the schedule is chosen to fit it: checkpointing is switched
+                           on when the stored tau grid would take more than half the cap, and the
+                           nodes of a panel share one executor slot when the per-node working set
+                           would not fit.  An allocation beyond the cap fails with FTCC_ENOMEM. */
 } ftcc_options;
 
-/* Defaults: n_tau 16, m 4, propagator 0, thr 0, tol 1e-12, max_iter 200, checkpoint 0, diis_depth 0. */
+/* Defaults: n_tau 16, m 4, propagator 0, thr 0, tol 1e-12, max_iter 200, checkpoint 0, diis_depth 0,
+ * mem_cap_bytes 0. */
 void ftcc_default_options(ftcc_options* opt);
 
 /* Create a context for n_instances independent (Hamiltonian, mu, beta) problems
@@ -79,6 +88,19 @@ int ftcc_destroy(ftcc_ctx* ctx);
 /* Run all device work on this hipStream_t (NULL: the context's own stream).
  * The stream must stay valid until it is replaced or the context destroyed. */
 int ftcc_set_stream(ftcc_ctx* ctx, void* hip_stream);
+
+/* Device memory supplier for the context's bulk buffers (integrals, amplitudes,
+ * residuals, intermediates, Lambda), e.g. a framework's caching allocator.
+ *   alloc(bytes, user) returns device memory on the context's device, usable
+ *   from its stream, or NULL (reported as FTCC_ENOMEM);
+ *   free(ptr, user) is called once for every pointer alloc returned, in
+ *   ftcc_destroy (free may be NULL when the caller reclaims the memory itself).
+ * Must be called before the first ftcc_set_hamiltonian (FTCC_ESTATE otherwise).
+ * NULL alloc restores hipMalloc / hipFree.  Launch descriptors (a few KB) are
+ * always the library's own hipMalloc. */
+typedef void* (*ftcc_alloc_fn)(size_t bytes, void* user);
+typedef void (*ftcc_free_fn)(void* ptr, void* user);
+int ftcc_set_allocator(ftcc_ctx* ctx, ftcc_alloc_fn alloc, ftcc_free_fn free_fn, void* user);
 
 /* Instance `inst` (0 <= inst < n_instances) with n spatial orbitals:
  *   h    n*n row-major one-body matrix (reference orbital basis)

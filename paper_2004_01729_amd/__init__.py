@@ -5,4 +5,4 @@ The native library libftcc.so (C ABI in include/ftcc.h) holds every kernel;
 `paper_2004_01729_amd.autograd` wraps it as a torch.autograd.Function.
 Importing this package loads nothing; the library is loaded on first use.
 """
-__all__ = ["ftcc", "build"]
+__all__ = ["ftcc", "build", "autograd"]

@@ -81,12 +81,15 @@ struct Launch {
   int cfg = 0;
   bool ta = false, tb = false;
   int splitk_blocks = 0;
+  int min_k = 0;                    // smallest K of the launch's GEMM problems
   int dot_blocks = 0;
   void* d_desc = nullptr;
   int* d_prefix = nullptr;
   int* d_prefix2 = nullptr;
   double* d_partial = nullptr;
   double flops = 0.0;
+  std::vector<double> prob_flops;   // per problem (GEMM), for gated accounting
+  std::vector<int> prob_inst;
   float tuned_ms = 0.f;
   std::string tag;
 };
@@ -103,6 +106,7 @@ using Binder = std::function<double*(int tensor, int prob, bool grad)>;
 struct Scratch {
   std::vector<double*> a, b, c, part;   // per problem: n^4 doubles each
   double* dot_partial = nullptr;        // >= n_prob * 64 doubles
+  double* tail_ws = nullptr;            // kTailWorkspaceDoubles: GEMM tail-split partial tiles
 };
 
 // HIP-event timing of the dominant kernel (the FP64-MFMA GEMM with 128x128
@@ -146,6 +150,14 @@ class Executor {
   void run_backward(hipStream_t s) const { run(bwd_, s); }
 
   void set_profiler(KernelProfiler* p) { prof_ = p; }
+  // Per-instance run flags (device int array indexed by instance, read when the
+  // kernels run): forward and backward launches of an instance whose flag is 0
+  // return at once.  Set before build(); set-up launches are never gated.
+  // h_flags mirrors the device flags on the host (flop accounting of the profiler).
+  void set_gate(const int* d_flags, const int* h_flags) {
+    gate_ = d_flags;
+    gate_host_ = h_flags;
+  }
   double gemm_flops_forward() const;
   double gemm_flops_backward() const;
   int n_launches_forward() const { return (int)fwd_.size(); }
@@ -182,6 +194,16 @@ class Executor {
   std::vector<Launch> setup_, fwd_, bwd_;
   std::vector<void*> owned_;
   KernelProfiler* prof_ = nullptr;
+  const int* gate_ = nullptr;
+  const int* gate_host_ = nullptr;
+  double run_flops(const Launch& l) const;
+  GemmTail tail_of(const Launch& l, int cfg) const {
+    return plan_gemm_tail(cfg, l.total, l.min_k, l.splitk_blocks > 0, scratch_ ? scratch_->tail_ws : nullptr,
+                          kTailWorkspaceDoubles);
+  }
+  const int* gate_for(const std::vector<Launch>& dst, int p) const {
+    return (gate_ && &dst != &setup_) ? gate_ + probs_[p].inst : nullptr;
+  }
 };
 
 }  // namespace ftcc

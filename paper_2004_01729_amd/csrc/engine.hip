@@ -117,6 +117,7 @@ void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::strin
     q.scale = scale ? (*scale)[p] : nullptr;
     q.alpha = alpha;
     q.beta = beta;
+    q.active = gate_for(dst, p);
     // Y axes padded on the left to 4; X strides of each Y axis
     for (int k = 0; k < 4; ++k) {
       q.d[k] = 1;
@@ -180,6 +181,7 @@ void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const 
     for (int k = 0; k < 4; ++k) q.div[k] = make_fastdiv((unsigned)q.d[k]);
     q.alpha = 0.0;
     q.beta = 0.0;
+    q.active = gate_for(dst, p);
     prefix[p] = total;
     total += (int)((q.d[3] + 1023) / 1024);
   }
@@ -306,6 +308,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
       ds[p].len = ipow(probs_[p].n, (int)ai.size());
       ds[p].alpha = alpha;
       ds[p].beta = beta;
+      ds[p].active = gate_for(dst, p);
     }
     Launch L;
     L.kind = Launch::DOT;
@@ -420,6 +423,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     g.ldc = g.N;
     g.alpha = galpha;
     g.beta = gbeta;
+    g.active = gate_for(dst, p);
     g.tiles_m = (g.M + BM - 1) / BM;
     g.tiles_n = (g.N + BN - 1) / BN;
     int ks = 1;
@@ -443,10 +447,22 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     total2 += (int)(((long)g.M * g.N + 1023) / 1024);
     flops += 2.0 * g.M * (double)g.N * g.K;
   }
+  std::vector<double> pf(np);
+  std::vector<int> pinst(np);
+  for (int p = 0; p < np; ++p) {
+    pf[p] = 2.0 * gs[p].M * (double)gs[p].N * gs[p].K;
+    pinst[p] = probs_[p].inst;
+  }
   Launch L;
   L.kind = Launch::GEMM;
   L.n_prob = np;
   L.total = total;
+  L.min_k = np > 0 ? gs[0].K : 0;
+  for (int p = 1; p < np; ++p) L.min_k = std::min(L.min_k, gs[p].K);
+  if (&dst != &setup_) {
+    L.prob_flops = pf;
+    L.prob_inst = pinst;
+  }
   L.cfg = cfg;
   L.ta = ta;
   L.tb = tb;
@@ -575,10 +591,11 @@ void Executor::autotune(hipStream_t s) {
       int best = l.cfg;
       float best_ms = 1e30f;
       for (int cfg : {0, 2}) {
-        launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
+        const GemmTail tail = tail_of(l, cfg);
+        launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, tail, s);
         FTCC_HIP(hipEventRecord(e0, s));
         for (int r = 0; r < 2; ++r)
-          launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
+          launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, tail, s);
         FTCC_HIP(hipEventRecord(e1, s));
         FTCC_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -620,6 +637,15 @@ void Executor::dump_plan() const {
 }
 
 // ------------------------------------------------------------------ run
+// algorithmic flops of a GEMM launch over the problems whose instance runs
+double Executor::run_flops(const Launch& l) const {
+  if (!gate_host_ || l.prob_flops.empty()) return l.flops;
+  double f = 0.0;
+  for (size_t p = 0; p < l.prob_flops.size(); ++p)
+    if (gate_host_[l.prob_inst[p]]) f += l.prob_flops[p];
+  return f;
+}
+
 void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
   for (const Launch& l : L) {
     switch (l.kind) {
@@ -630,8 +656,9 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
       case Launch::GEMM: {
         const bool timed = prof_ && prof_->enabled && gemm_bm(l.cfg) == 128;
         if (timed) prof_->record_begin(s);
-        launch_gemm(l.cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, s);
-        if (timed) prof_->record_end(s, l.flops);
+        launch_gemm(l.cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, tail_of(l, l.cfg),
+                    s);
+        if (timed) prof_->record_end(s, run_flops(l));
       }
         if (l.splitk_blocks > 0)
           launch_splitk_reduce((const GemmProblem*)l.d_desc, l.d_prefix2, l.n_prob, l.splitk_blocks, s);

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <functional>
 #include <cmath>
 #include <cstdio>
@@ -239,7 +240,9 @@ struct ftcc_ctx {
   unsigned long long* d_maxbits = nullptr;    // [B][2]
   double* d_partial = nullptr;                // TAU_BETA partial sums
   std::vector<int> tau_prefix_host;
-  int* d_active = nullptr;                    // [B]
+  int* d_active = nullptr;                    // [B] propagator step flags
+  int* d_run = nullptr;                       // [B] residual-program run flags (executor gate)
+  std::vector<int> run_host;                  // host copy of d_run
   KernelProfiler prof;
   hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
   std::vector<int> beta_part_off;             // first TAU_BETA partial of each instance
@@ -256,11 +259,21 @@ struct ftcc_ctx {
   long resid_evals = 0, vjp_evals = 0;
   double t_solve = 0.0, t_lambda = 0.0;
   size_t bytes = 0;
+  ftcc_alloc_fn ualloc = nullptr;   // caller's device memory supplier (or hipMalloc)
+  ftcc_free_fn ufree = nullptr;
+  void* uuser = nullptr;
 
   double* dalloc(size_t count) {
     void* p = nullptr;
-    const size_t nb = std::max<size_t>(count, 1) * sizeof(double);
-    if (hipMalloc(&p, nb) != hipSuccess) {
+    // 256-byte granules keep every buffer aligned for 16-byte vector loads
+    const size_t nb = (std::max<size_t>(count, 1) * sizeof(double) + 255) / 256 * 256;
+    if (opt.mem_cap_bytes && bytes + nb > opt.mem_cap_bytes)
+      fail(FTCC_ENOMEM, "allocation of " + std::to_string(nb) + " bytes would exceed mem_cap_bytes (" +
+                            std::to_string(bytes) + " bytes already held)");
+    if (ualloc) {
+      p = ualloc(nb, uuser);
+      if (!p) fail(FTCC_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(nb) + " bytes");
+    } else if (hipMalloc(&p, nb) != hipSuccess) {
       (void)hipGetLastError();
       fail(FTCC_ENOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed (" + std::to_string(bytes) +
                             " bytes already held)");
@@ -268,6 +281,15 @@ struct ftcc_ctx {
     bytes += nb;
     allocs.push_back(p);
     return (double*)p;
+  }
+
+  // device memory this context may still take: free memory, bounded by the cap
+  double available() {
+    size_t free_b = 0, total_b = 0;
+    FTCC_HIP(hipMemGetInfo(&free_b, &total_b));
+    double a = (double)free_b;
+    if (opt.mem_cap_bytes) a = std::min(a, (double)opt.mem_cap_bytes - (double)bytes);
+    return std::max(a, 0.0);
   }
 };
 
@@ -293,6 +315,33 @@ int run_guarded(const std::function<void()>& f) {
     g_err = e.what();
     return FTCC_EINVAL;
   }
+}
+
+// Progress lines on stderr (one per panel of each phase) when FTCC_TRACE is set:
+// large instances spend minutes per phase.
+bool trace_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("FTCC_TRACE");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
+}
+
+void trace(ftcc_ctx* c, const char* phase, int panel, int n_panels, const std::vector<int>& sweeps,
+           std::chrono::steady_clock::time_point t0) {
+  if (!trace_on()) return;
+  const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int mx = 0;
+  for (int v : sweeps) mx = std::max(mx, v);
+  std::fprintf(stderr, "[ftcc] %s panel %d/%d: max sweeps %d, %.2f s since phase start, %.2f GiB held\n",
+               phase, panel, n_panels, mx, s, c->bytes / 1073741824.0);
+  std::fflush(stderr);
+}
+
+void trace_mem(ftcc_ctx* c, const char* stage) {
+  if (!trace_on()) return;
+  std::fprintf(stderr, "[ftcc] device memory held after %s: %.2f GiB\n", stage, c->bytes / 1073741824.0);
+  std::fflush(stderr);
 }
 
 void sync(ftcc_ctx* c) {
@@ -393,6 +442,8 @@ void deriv_setup(ftcc_ctx* c, int i, int which, const double* d_dh, const double
   FTCC_HIP(hipGetLastError());
 }
 
+long node_len_of(long n) { return n * n + n * n * n * n; }
+
 // ------------------------------------------------------------------ build
 void build(ftcc_ctx* c) {
   if (c->built) return;
@@ -428,6 +479,24 @@ void build(ftcc_ctx* c) {
     for (int k = 0; k < 4; ++k) I.ugrad_acc[k] = c->dalloc(n2);
     I.sb.resize(P + 1);
     for (int p = 0; p <= P; ++p) I.sb[p] = c->dalloc(len);
+  }
+  // Checkpointing when the stored grid (amplitudes and residuals of every node)
+  // would take more than half of the capped memory.
+  if (!c->opt.checkpoint && c->opt.mem_cap_bytes) {
+    double grid = 0.0;
+    for (int i = 0; i < B; ++i) grid += 2.0 * P * m * (double)node_len_of(c->inst[i].n) * sizeof(double);
+    if (grid > 0.5 * (double)c->opt.mem_cap_bytes) c->opt.checkpoint = 1;
+  }
+  for (int i = 0; i < B; ++i) {
+    Instance& I = c->inst[i];
+    const long len = node_len_of(I.n);
+    // Lambda of every node and the panel-boundary adjoint states a_p, allocated up
+    // front so that the optional caches below are sized to what is left;
+    // lambda-tilde is not stored (recomputed from lambda and a_{p+1} when needed)
+    I.lam.resize(P * m);
+    for (int k = 0; k < P * m; ++k) I.lam[k] = c->dalloc(len);
+    I.abuf.resize(P + 1);
+    for (int p = 0; p <= P; ++p) I.abuf[p] = c->dalloc(len);
     if (!c->opt.checkpoint) {
       I.grid.resize(P * m);
       I.resid.resize(P * m);
@@ -438,16 +507,15 @@ void build(ftcc_ctx* c) {
     }
     I.energies.assign(P * m, 0.0);
   }
+  trace_mem(c, "integrals, panel states and Lambda storage");
   // Executor slots per instance: every node of a panel evaluated in one grouped
   // launch (slots = m) unless the per-slot working set (about 40 n^4 doubles:
   // intermediates, their gradients, scratch) would take more than half of the
   // free device memory; then the nodes go through one slot in turn.
   {
-    size_t free_b = 0, total_b = 0;
-    FTCC_HIP(hipMemGetInfo(&free_b, &total_b));
     double need = 0.0;
     for (int i = 0; i < B; ++i) need += 40.0 * m * std::pow((double)c->inst[i].n, 4) * sizeof(double);
-    c->slots = (need > 0.5 * (double)free_b) ? 1 : m;
+    c->slots = (need > 0.5 * c->available()) ? 1 : m;
     const char* senv = std::getenv("FTCC_NODE_SLOTS");
     if (senv && senv[0] == '1') c->slots = 1;
   }
@@ -530,8 +598,12 @@ void build(ftcc_ctx* c) {
       c->scratch.part[q] = c->dalloc(n4);
     }
   c->scratch.dot_partial = c->dalloc((size_t)nn * 64 + 64);
+  c->scratch.tail_ws = c->dalloc(kTailWorkspaceDoubles);
   c->d_maxbits = (unsigned long long*)c->dalloc(2 * B);
   c->d_active = (int*)c->dalloc(B);
+  c->d_run = (int*)c->dalloc(B);
+  c->run_host.assign(B, 1);
+  FTCC_HIP(hipMemcpy(c->d_run, c->run_host.data(), sizeof(int) * B, hipMemcpyHostToDevice));
   {
     std::vector<int> ones(2 * B, 1);
     FTCC_HIP(hipMemcpy(c->d_active, ones.data(), sizeof(int) * B, hipMemcpyHostToDevice));
@@ -567,6 +639,7 @@ void build(ftcc_ctx* c) {
     c->d_partial = c->dalloc(blocks);
   }
 
+  trace_mem(c, "node and slot buffers");
   std::vector<int> ugrads;
   for (int k = 0; k < 4; ++k) ugrads.push_back(prog.id(kU[k]));
   const int id_t1 = prog.id("t1"), id_t2 = prog.id("t2"), id_S1 = prog.id("S1"), id_S2 = prog.id("S2"),
@@ -626,16 +699,16 @@ void build(ftcc_ctx* c) {
   };
   auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
   auto vcache = [c](size_t count) { return c->dalloc(count); };
-  // reuse budget for permuted operand copies: a quarter of the free device memory
-  size_t free_b = 0, total_b = 0;
-  FTCC_HIP(hipMemGetInfo(&free_b, &total_b));
-  const size_t budget = free_b / 4;
+  // reuse budget for permuted operand copies: a quarter of the memory still available
+  const size_t budget = (size_t)(c->available() / 4);
   c->ex_main.reset(new Executor());
+  c->ex_main->set_gate(c->d_run, c->run_host.data());
   c->ex_main->build(&prog, probs, bind_main, &c->scratch, calloc_, true, ugrads, vcache, budget);
   c->ex_main->set_profiler(&c->prof);
   c->ex_d.reset(new Executor());
   c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {}, vcache, budget / 2);
   c->ex_d->set_profiler(&c->prof);
+  trace_mem(c, "executors");
   c->ex_main->autotune(c->stream);
   c->ex_d->autotune(c->stream);
   FTCC_HIP(hipStreamSynchronize(c->stream));
@@ -657,6 +730,13 @@ void build(ftcc_ctx* c) {
 
   // propagator descriptors: one per (instance, segment) for each mode's buffer roles
   c->built = true;
+}
+
+// number of instances whose residual programs currently run
+long n_running(ftcc_ctx* c) {
+  long k = 0;
+  for (int v : c->run_host) k += v ? 1 : 0;
+  return k;
 }
 
 // the forward / backward programs: graph replay unless the kernel profiler records events
@@ -686,9 +766,11 @@ void forward(ftcc_ctx* c) {
     return;
   }
   for (int x = 0; x < c->m; ++x) {
-    for (int i = 0; i < c->B; ++i) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    for (int i = 0; i < c->B; ++i)
+      if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
     run_fwd_slots(c);
     for (int i = 0; i < c->B; ++i) {
+      if (!c->run_host[i]) continue;
       dcopy(c, c->S[i * c->m + x], c->s_S[i], node_len(c, i));
       dcopy(c, c->e[i * c->m + x], c->s_e[i], 1);
     }
@@ -703,16 +785,19 @@ void backward(ftcc_ctx* c) {
     return;
   }
   for (int x = 0; x < c->m; ++x) {
-    for (int i = 0; i < c->B; ++i) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    for (int i = 0; i < c->B; ++i)
+      if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
     run_fwd_slots(c);
-    c->resid_evals += c->B;
+    c->resid_evals += n_running(c);
     for (int i = 0; i < c->B; ++i) {
+      if (!c->run_host[i]) continue;
       const int p = i * c->m + x;
       dcopy(c, c->s_cot[i], c->cot[p], node_len(c, i));
       dcopy(c, c->s_ebar[i], c->ebar[p], 1);
     }
     run_bwd_slots(c);
     for (int i = 0; i < c->B; ++i) {
+      if (!c->run_host[i]) continue;
       const int p = i * c->m + x;
       const long n = c->inst[i].n;
       dcopy(c, c->gr[p], c->s_gr[i], node_len(c, i));
@@ -832,6 +917,21 @@ void set_active(ftcc_ctx* c, const std::vector<bool>& active) {
                           c->stream));
 }
 
+// Which instances the forward / backward residual programs evaluate (the
+// others' launches return at once).  Outside the fixed-point loops every
+// instance runs.
+void set_run(ftcc_ctx* c, const std::vector<bool>& run) {
+  bool same = true;
+  for (int i = 0; i < c->B; ++i) same = same && ((c->run_host[i] != 0) == run[i]);
+  if (same) return;
+  for (int i = 0; i < c->B; ++i) c->run_host[i] = run[i] ? 1 : 0;
+  FTCC_HIP(hipMemcpyAsync(c->d_run, c->run_host.data(), sizeof(int) * c->B, hipMemcpyHostToDevice, c->stream));
+  // the host array is reused by the next call: finish this copy first
+  FTCC_HIP(hipStreamSynchronize(c->stream));
+}
+
+void run_all(ftcc_ctx* c) { set_run(c, std::vector<bool>(c->B, true)); }
+
 void reset_maxbits(ftcc_ctx* c) {
   hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, c->stream, c->d_maxbits, 2 * c->B);
 }
@@ -895,7 +995,7 @@ void diis_after(ftcc_ctx* c, const NodeBufs& it, const std::vector<bool>& active
     std::vector<DotProblem> ds;
     for (int t = 0; t < c->diis_count[i]; ++t) {
       for (int tw = 0; tw < 2; ++tw) {
-        DotProblem d;
+        DotProblem d{};
         d.X = R;
         d.Y = c->diis_R[i][t];
         d.out = c->d_gram + (long)i * D * D + (tw ? t * D + slot : slot * D + t);
@@ -947,9 +1047,10 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
   const bool diis = c->opt.diis_depth > 0;
   NodeBufs amp_of = [c](int i, int x) { return c->amp[i * c->m + x]; };
   if (diis) diis_reset(c);
+  set_run(c, active);   // converged or failed instances stop costing residual evaluations
   for (int it = 1; it <= c->opt.max_iter; ++it) {
     forward(c);
-    c->resid_evals += (long)B * c->m;
+    c->resid_evals += n_running(c) * c->m;
     reset_maxbits(c);
     set_active(c, active);
     if (diis) diis_before(c, amp_of, active);
@@ -972,13 +1073,19 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
       any = true;
     }
     if (!any) break;
+    set_run(c, active);
     if (diis) diis_after(c, amp_of, active);
     if (it == c->opt.max_iter)
       for (int i = 0; i < B; ++i)
         if (active[i]) status[i] = FTCC_ENOCONV;
   }
+  // residuals at the final amplitudes of every instance still in good standing
+  std::vector<bool> ok(B);
+  for (int i = 0; i < B; ++i) ok[i] = status[i] == 0;
+  set_run(c, ok);
   forward(c);
-  c->resid_evals += (long)B * c->m;
+  c->resid_evals += n_running(c) * c->m;
+  run_all(c);
   return its;
 }
 
@@ -997,6 +1104,7 @@ void ftcc_default_options(ftcc_options* opt) {
   opt->max_iter = 200;
   opt->checkpoint = 0;
   opt->diis_depth = 0;
+  opt->mem_cap_bytes = 0;
 }
 
 int ftcc_abi_version(void) { return FTCC_ABI_VERSION; }
@@ -1050,7 +1158,10 @@ int ftcc_destroy(ftcc_ctx* c) {
     if (c->g_bwd) (void)hipGraphExecDestroy(c->g_bwd);
     c->ex_main.reset();
     c->ex_d.reset();
-    for (void* p : c->allocs) (void)hipFree(p);
+    for (void* p : c->allocs) {
+      if (c->ufree) c->ufree(p, c->uuser);
+      else if (!c->ualloc) (void)hipFree(p);
+    }
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
   });
@@ -1060,6 +1171,16 @@ int ftcc_set_stream(ftcc_ctx* c, void* s) {
   return run_guarded([&] {
     if (!c) fail(FTCC_EINVAL, "null context");
     c->stream = s ? (hipStream_t)s : c->own_stream;
+  });
+}
+
+int ftcc_set_allocator(ftcc_ctx* c, ftcc_alloc_fn alloc, ftcc_free_fn free_fn, void* user) {
+  return run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    if (!c->allocs.empty()) fail(FTCC_ESTATE, "set the allocator before the first ftcc_set_hamiltonian");
+    c->ualloc = alloc;
+    c->ufree = alloc ? free_fn : nullptr;
+    c->uuser = alloc ? user : nullptr;
   });
 }
 
@@ -1122,6 +1243,7 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
     c->ex_main->run_setup(c->stream);
     std::vector<int> status(B, 0), total(B, 0);
     std::vector<double> ebuf(B * m);
+    const auto wall0 = std::chrono::steady_clock::now();
     for (int p = 0; p < P; ++p) {
       std::vector<int> its = panel_solve(c, p, status);
       for (int i = 0; i < B; ++i) total[i] += its[i];
@@ -1140,6 +1262,7 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
       sync(c);
       for (int i = 0; i < B; ++i)
         for (int x = 0; x < m; ++x) c->inst[i].energies[p * m + x] = ebuf[i * m + x];
+      trace(c, "forward", p + 1, P, its, wall0);
     }
     FTCC_HIP(hipEventRecord(e1, c->stream));
     sync(c);
@@ -1157,7 +1280,8 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
       double occ_cc = 0.0;
       for (int p = 0; p < P; ++p)
         for (int x = 0; x < m; ++x) occ_cc += c->rule.b[x] / P * I.energies[p * m + x];
-      I.omega_cc = occ_cc;
+      // an instance whose march failed has no grand potential
+      I.omega_cc = status[i] == 0 ? occ_cc : std::nan("");
       I.iters = total[i];
       I.status = status[i];
       if (iters_out) iters_out[i] = total[i];
@@ -1210,17 +1334,25 @@ namespace {
 
 // Bring the converged amplitudes of panel p into the slots and evaluate the
 // forward program there (tape for the backward, residuals in S).
+// Leaves the run flags on the instances whose forward march succeeded.
 void load_panel(ftcc_ctx* c, int p) {
   const int B = c->B, m = c->m;
+  std::vector<int> st(B);
+  std::vector<bool> ok(B);
+  for (int i = 0; i < B; ++i) {
+    st[i] = c->inst[i].status;
+    ok[i] = st[i] == 0;
+  }
   if (!c->opt.checkpoint) {
     for (int i = 0; i < B; ++i) {
       const long n = c->inst[i].n, len = n * n + n * n * n * n;
       for (int x = 0; x < m; ++x) copy_d(c, c->amp[i * m + x], c->inst[i].grid[p * m + x], len);
     }
+    set_run(c, ok);
     forward(c);
   } else {
-    std::vector<int> st(B, 0);
     panel_solve(c, p, st);   // deterministic: reproduces the forward sweep
+    set_run(c, ok);
   }
 }
 
@@ -1238,13 +1370,6 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
     for (int i = 0; i < B; ++i) {
       Instance& I = c->inst[i];
       const long n = I.n, len = n * n + n * n * n * n;
-      if (I.lam.empty()) {
-        // lambda-tilde is not stored: it is recomputed from lambda and a_{p+1} when needed
-        I.lam.resize(P * m);
-        for (int k = 0; k < P * m; ++k) I.lam[k] = c->dalloc(len);
-        I.abuf.resize(P + 1);
-        for (int p = 0; p <= P; ++p) I.abuf[p] = c->dalloc(len);
-      }
       zero_d(c, I.abuf[P], len);
     }
     hipEvent_t e0, e1;
@@ -1253,7 +1378,10 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
     FTCC_HIP(hipEventRecord(e0, c->stream));
     c->vjp_evals = 0;
     std::vector<int> total(B, 0), status(B, 0);
+    for (int i = 0; i < B; ++i) status[i] = c->inst[i].status;   // a failed forward march has no adjoint
+    const auto wall0 = std::chrono::steady_clock::now();
     for (int p = P - 1; p >= 0; --p) {
+      const std::vector<int> before = total;
       load_panel(c, p);
       // lambda_x = -(g_x/beta) dE/ds : backward with zero S-cotangent
       for (int q = 0; q < B * m; ++q) {
@@ -1261,9 +1389,10 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
         zero_d(c, c->cot[q], n * n + n * n * n * n);
       }
       backward(c);
-      c->vjp_evals += (long)B * m;
+      c->vjp_evals += n_running(c) * m;
       reset_maxbits(c);
-      std::vector<bool> active(B, true);
+      std::vector<bool> active(B);
+      for (int i = 0; i < B; ++i) active[i] = c->inst[i].status == 0;
       set_active(c, active);
       tau_run(c, TAU_LSTEP, p);
       const bool diis = c->opt.diis_depth > 0;
@@ -1272,7 +1401,7 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
       for (int it = 1; it <= c->opt.max_iter; ++it) {
         tau_run(c, TAU_LAMT, p);
         backward(c);
-        c->vjp_evals += (long)B * m;
+        c->vjp_evals += n_running(c) * m;
         reset_maxbits(c);
         set_active(c, active);
         if (diis) diis_before(c, lam_of, active);
@@ -1295,12 +1424,20 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
           any = true;
         }
         if (!any) break;
+        set_run(c, active);
         if (diis) diis_after(c, lam_of, active);
         if (it == c->opt.max_iter)
           for (int i = 0; i < B; ++i)
             if (active[i]) status[i] = FTCC_ENOCONV;
       }
+      run_all(c);
       tau_run(c, TAU_APREV, p);
+      if (trace_on()) {
+        sync(c);
+        std::vector<int> sw(B);
+        for (int i = 0; i < B; ++i) sw[i] = total[i] - before[i];
+        trace(c, "lambda", P - p, P, sw, wall0);
+      }
     }
     FTCC_HIP(hipEventRecord(e1, c->stream));
     sync(c);
@@ -1382,7 +1519,7 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
       for (int i = 0; i < B; ++i)
         for (int x = 0; x < m; ++x) {
           const int q = i * m + x;
-          DotProblem d;
+          DotProblem d{};
           const long n = c->inst[i].n;
           d.X = c->cot[q];
           d.Y = c->dS[q];
@@ -1404,7 +1541,12 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         for (int x = 0; x < m; ++x)
           launch_axpby(1, c->rule.b[x] / P, c->de[i * m + x], 1.0, c->inst[i].acc + slot, c->stream);
     };
+    const auto wall0 = std::chrono::steady_clock::now();
     for (int p = 0; p < P; ++p) {
+      if (trace_on() && p > 0) {
+        sync(c);
+        trace(c, "response", p, P, std::vector<int>(1, 0), wall0);
+      }
       load_panel(c, p);
       tau_run(c, TAU_LAMT, p);   // lambda-tilde of the panel into the cotangent buffers
       if (dO_dh) {
@@ -1437,6 +1579,7 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         accumulate(which);
       }
     }
+    run_all(c);
     // mean-field parts and assembly
     std::vector<double> accs(8 * B), mfv(5 * B);
     for (int i = 0; i < B; ++i) {
@@ -1513,7 +1656,8 @@ int ftcc_time_residual(ftcc_ctx* c, int reps, double* seconds_out, double* flops
     FTCC_HIP(hipEventDestroy(e0));
     FTCC_HIP(hipEventDestroy(e1));
     if (seconds_out) *seconds_out = ms * 1e-3;
-    if (flops_out) *flops_out = c->ex_main->gemm_flops_forward();
+    // one forward() evaluates every node: m / slots passes of the slot program
+    if (flops_out) *flops_out = c->ex_main->gemm_flops_forward() * (c->m / c->slots);
   });
 }
 

@@ -19,6 +19,7 @@ struct GemmProblem {
   int M, N, K;
   int tiles_m, tiles_n, ksplit, kchunk;
   double alpha, beta;
+  const int* active;     // optional run flag of the problem's instance (0: skip the problem)
 };
 
 // Unsigned 32-bit division by a runtime constant: q = umulhi(x, mul) >> shr
@@ -42,6 +43,7 @@ struct PermProblem {
   FastDiv div[4];
   FastDiv tdiv[2];
   double alpha, beta;
+  const int* active;     // optional run flag (0: skip)
 };
 
 // *out = alpha * sum_e X[e] Y[e] + beta * *out
@@ -51,10 +53,26 @@ struct DotProblem {
   double* out;
   long len;
   double alpha, beta;
+  const int* active;     // optional run flag (0: skip, *out keeps its value)
 };
 
+// Tail split of a grouped GEMM launch.  The tiles of a launch run in waves of
+// gemm_slots(cfg) resident blocks; when the last wave would be mostly idle, the
+// last total - dp_tiles tiles are cut into `splits` K-segments each.  Their
+// partial tiles (BM x BN, row-major) go to ws and gemm_tail_reduce adds them in
+// segment order (deterministic) and applies alpha / beta.
+struct GemmTail {
+  int dp_tiles = 0;     // tiles computed whole: blocks [0, dp_tiles)
+  int splits = 1;       // 1: no tail split
+  double* ws = nullptr;
+};
+int gemm_slots(int cfg);
+// min_k: smallest K of the launch's problems; any_ksplit: a problem already uses split-K
+GemmTail plan_gemm_tail(int cfg, int total_tiles, int min_k, bool any_ksplit, double* ws, size_t ws_doubles);
+constexpr size_t kTailWorkspaceDoubles = (size_t)1024 * 128 * 128;   // 128 MiB
+
 void launch_gemm(int cfg, bool ta, bool tb, const GemmProblem* d_probs, const int* d_prefix, int n_prob,
-                 int total_tiles, hipStream_t s);
+                 int total_tiles, const GemmTail& tail, hipStream_t s);
 void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,
                           hipStream_t s);
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

@@ -38,6 +38,17 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
   return x * q + (x < r ? x : r) + i;
 }
 
+// Tile (tm, tn) of the local tile index inside a problem: bands of 8 tile-rows,
+// column-major inside a band, so that consecutive blocks share B columns and A rows.
+__device__ __forceinline__ void tile_coords(int local, int tiles_m, int tiles_n, int& tm, int& tn) {
+  const int GM = 8;
+  const int band = local / (GM * tiles_n);
+  const int first_m = band * GM;
+  const int band_rows = min(GM, tiles_m - first_m);
+  tm = first_m + (local % (GM * tiles_n)) % band_rows;
+  tn = (local % (GM * tiles_n)) / band_rows;
+}
+
 // ------------------------------------------------------------------ GEMM
 // Fragment layouts of v_mfma_f64_16x16x4f64 (wave64):
 //   A (16x4):  lane l holds A[l % 16][l / 16]
@@ -48,7 +59,7 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 template <int BM, int BN, int BK, bool TA, bool TB, int WPE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE, 4)))
 gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ prefix,
-                 int n_prob, int total_tiles) {
+                 int n_prob, int dp_tiles, int splits, double* __restrict__ ws) {
   constexpr int WM = BM / 2, WN = BN / 2;        // 2 x 2 waves
   constexpr int FM = WM / 16, FN = WN / 16;      // MFMA tiles per wave
   // LDS tiles keep the global layout of each operand (no transposing stores):
@@ -65,24 +76,37 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   __shared__ double As[2][SA];
   __shared__ double Bs[2][SB];
 
-  const int tile = xcd_remap(blockIdx.x, total_tiles);
+  // blocks [0, dp_tiles): whole tiles in XCD-aware order; the rest: K-segments of
+  // the tail tiles (unit u = segment u % splits of tile dp_tiles + u / splits)
+  const int b = blockIdx.x;
+  int tile, kseg = -1;
+  if (b < dp_tiles) {
+    tile = xcd_remap(b, dp_tiles);
+  } else {
+    const int u = b - dp_tiles;
+    tile = dp_tiles + u / splits;
+    kseg = u % splits;
+  }
   const int pi = find_problem(prefix, n_prob, tile);
   const GemmProblem& P = probs[pi];
+  if (P.active && *P.active == 0) return;   // the whole block leaves before any barrier
   int local = tile - prefix[pi];
   const int tiles_mn = P.tiles_m * P.tiles_n;
   const int ks = local / tiles_mn;
   local -= ks * tiles_mn;
-  // grouped ordering inside the problem: bands of 8 tile-rows
-  const int GM = 8;
-  const int band = local / (GM * P.tiles_n);
-  const int first_m = band * GM;
-  const int band_rows = min(GM, P.tiles_m - first_m);
-  const int tm = first_m + (local % (GM * P.tiles_n)) % band_rows;
-  const int tn = (local % (GM * P.tiles_n)) / band_rows;
+  int tm, tn;
+  tile_coords(local, P.tiles_m, P.tiles_n, tm, tn);
 
   const int m0 = tm * BM, n0 = tn * BN;
-  const int kbeg = ks * P.kchunk;
-  const int kend = min(P.K, kbeg + P.kchunk);
+  int kbeg, kend;
+  if (kseg < 0) {
+    kbeg = ks * P.kchunk;
+    kend = min(P.K, kbeg + P.kchunk);
+  } else {
+    const int kc = ((P.K + splits - 1) / splits + BK - 1) / BK * BK;
+    kbeg = kseg * kc;
+    kend = min(P.K, kbeg + kc);
+  }
   const int M = P.M, N = P.N;
 
   const int tid = threadIdx.x;
@@ -174,6 +198,17 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   }
 
   // epilogue
+  if (kseg >= 0) {   // partial tile of a tail segment, summed by gemm_tail_reduce
+    double* W = ws + (long)(b - dp_tiles) * (BM * BN);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          W[(wm * WM + i * 16 + 4 * r + fk) * BN + wn * WN + j * 16 + fr] = acc[i][j][r];
+    return;
+  }
   double* C;
   long ldc;
   double alpha, beta;
@@ -206,12 +241,41 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     }
 }
 
+// C = alpha * (sum of the K-segment partials, in segment order) + beta * C for the
+// tail tiles of a launch; blockIdx.y = tail tile, 1024 elements per block in x.
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) gemm_tail_reduce_kernel(const GemmProblem* __restrict__ probs,
+                                                               const int* __restrict__ prefix, int n_prob,
+                                                               int dp_tiles, int splits,
+                                                               const double* __restrict__ ws) {
+  const int t = dp_tiles + blockIdx.y;
+  const int pi = find_problem(prefix, n_prob, t);
+  const GemmProblem& P = probs[pi];
+  if (P.active && *P.active == 0) return;
+  int tm, tn;
+  tile_coords(t - prefix[pi], P.tiles_m, P.tiles_n, tm, tn);   // tail launches have no split-K problems
+  const double* W = ws + (long)blockIdx.y * splits * (BM * BN);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = blockIdx.x * 1024 + u * 256 + threadIdx.x;
+    if (e >= BM * BN) break;
+    const int gm = tm * BM + e / BN, gn = tn * BN + e % BN;
+    if (gm >= P.M || gn >= P.N) continue;
+    double s = 0.0;
+    for (int k = 0; k < splits; ++k) s += W[(long)k * (BM * BN) + e];
+    double* c = P.C + (long)gm * P.ldc + gn;
+    double v = P.alpha * s;
+    if (P.beta != 0.0) v += P.beta * (*c);
+    *c = v;
+  }
+}
+
 // C = alpha * sum_s partial[s] + beta * C for split-K problems
 __global__ void splitk_reduce_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ prefix,
                                      int n_prob, int total) {
   const int pi = find_problem(prefix, n_prob, blockIdx.x);
   const GemmProblem P = probs[pi];
-  if (P.ksplit <= 1) return;
+  if (P.ksplit <= 1 || (P.active && *P.active == 0)) return;
   const long mn = (long)P.M * P.N;
   const long chunk = (long)(blockIdx.x - prefix[pi]) * 256 * 4;
   for (int u = 0; u < 4; ++u) {
@@ -256,6 +320,7 @@ __global__ void __launch_bounds__(256) permute4_kernel(const PermProblem* __rest
                                                        const int* __restrict__ prefix, int n_prob) {
   const int pi = find_problem(prefix, n_prob, blockIdx.x);
   const PermProblem& P = probs[pi];
+  if (P.active && *P.active == 0) return;   // uniform per block, before the barrier
   const unsigned int local = blockIdx.x - prefix[pi];
   const double alpha = P.scale ? P.alpha * (*P.scale) : P.alpha;
   const double beta = P.beta;
@@ -319,6 +384,7 @@ __global__ void dot_partial_kernel(const DotProblem* __restrict__ probs, int blo
   const int pi = blockIdx.x / blocks_per;
   const int bi = blockIdx.x % blocks_per;
   const DotProblem P = probs[pi];
+  if (P.active && *P.active == 0) return;
   double s = 0.0;
   for (long e = (long)bi * 256 + threadIdx.x; e < P.len; e += (long)blocks_per * 256) s += P.X[e] * P.Y[e];
   __shared__ double red[256];
@@ -336,6 +402,7 @@ __global__ void dot_final_kernel(const DotProblem* __restrict__ probs, int n_pro
   const int pi = blockIdx.x * blockDim.x + threadIdx.x;
   if (pi >= n_prob) return;
   const DotProblem P = probs[pi];
+  if (P.active && *P.active == 0) return;
   double s = 0.0;
   for (int b = 0; b < blocks_per; ++b) s += partial[pi * blocks_per + b];
   double v = P.alpha * s;
@@ -346,26 +413,82 @@ __global__ void dot_final_kernel(const DotProblem* __restrict__ probs, int n_pro
 // ------------------------------------------------------------------ launchers
 template <int BM, int BN, int BK, bool TA, bool TB>
 static void launch_gemm_t(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_tiles,
-                          hipStream_t s) {
+                          const GemmTail& tail, hipStream_t s) {
   constexpr int WPE = (BK == 16) ? 2 : 1;
-  hipLaunchKernelGGL((gemm_mfma_kernel<BM, BN, BK, TA, TB, WPE>), dim3(total_tiles), dim3(256), 0, s,
-                     d_probs, d_prefix, n_prob, total_tiles);
+  const bool split = tail.splits > 1 && tail.dp_tiles < total_tiles;
+  const int dp = split ? tail.dp_tiles : total_tiles;
+  const int blocks = dp + (split ? (total_tiles - dp) * tail.splits : 0);
+  hipLaunchKernelGGL((gemm_mfma_kernel<BM, BN, BK, TA, TB, WPE>), dim3(blocks), dim3(256), 0, s, d_probs, d_prefix,
+                     n_prob, dp, split ? tail.splits : 1, tail.ws);
+  if (split)
+    hipLaunchKernelGGL((gemm_tail_reduce_kernel<BM, BN>), dim3((BM * BN + 1023) / 1024, total_tiles - dp),
+                       dim3(256), 0, s, d_probs, d_prefix, n_prob, dp, tail.splits, (const double*)tail.ws);
 }
 
 void launch_gemm(int cfg, bool ta, bool tb, const GemmProblem* d_probs, const int* d_prefix, int n_prob,
-                 int total_tiles, hipStream_t s) {
+                 int total_tiles, const GemmTail& tail, hipStream_t s) {
   if (total_tiles <= 0) return;
-#define FTCC_G(BM, BN, BK)                                                                        \
-  do {                                                                                            \
-    if (ta && tb) launch_gemm_t<BM, BN, BK, true, true>(d_probs, d_prefix, n_prob, total_tiles, s);    \
-    else if (ta) launch_gemm_t<BM, BN, BK, true, false>(d_probs, d_prefix, n_prob, total_tiles, s);    \
-    else if (tb) launch_gemm_t<BM, BN, BK, false, true>(d_probs, d_prefix, n_prob, total_tiles, s);    \
-    else launch_gemm_t<BM, BN, BK, false, false>(d_probs, d_prefix, n_prob, total_tiles, s);           \
+#define FTCC_G(BM, BN, BK)                                                                              \
+  do {                                                                                                  \
+    if (ta && tb) launch_gemm_t<BM, BN, BK, true, true>(d_probs, d_prefix, n_prob, total_tiles, tail, s);    \
+    else if (ta) launch_gemm_t<BM, BN, BK, true, false>(d_probs, d_prefix, n_prob, total_tiles, tail, s);    \
+    else if (tb) launch_gemm_t<BM, BN, BK, false, true>(d_probs, d_prefix, n_prob, total_tiles, tail, s);    \
+    else launch_gemm_t<BM, BN, BK, false, false>(d_probs, d_prefix, n_prob, total_tiles, tail, s);           \
   } while (0)
   if (cfg == 0) FTCC_G(128, 128, 16);
   else if (cfg == 1) FTCC_G(64, 64, 16);
   else FTCC_G(128, 128, 32);
 #undef FTCC_G
+}
+
+// Resident blocks of one configuration on the current device (occupancy x CUs).
+int gemm_slots(int cfg) {
+  static int cache[kGemmConfigs] = {0, 0, 0};
+  if (cfg < 0 || cfg >= kGemmConfigs) return 0;
+  if (cache[cfg] > 0) return cache[cfg];
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  hipError_t e;
+  if (cfg == 0)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_mfma_kernel<128, 128, 16, false, false, 2>, 256, 0);
+  else if (cfg == 1)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_mfma_kernel<64, 64, 16, false, false, 2>, 256, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gemm_mfma_kernel<128, 128, 32, false, false, 1>, 256, 0);
+  if (e != hipSuccess || per_cu <= 0) return 0;
+  cache[cfg] = per_cu * prop.multiProcessorCount;
+  return cache[cfg];
+}
+
+// Choose the tail split: waves of `slots` blocks; the r = total mod slots tiles of
+// the last wave are cut into s segments when ceil(r s / slots) / s waves of
+// segment work beat the one wave they would otherwise take.
+GemmTail plan_gemm_tail(int cfg, int total_tiles, int min_k, bool any_ksplit, double* ws, size_t ws_doubles) {
+  GemmTail t;
+  t.dp_tiles = total_tiles;
+  const int slots = gemm_slots(cfg);
+  if (!ws || any_ksplit || slots <= 0 || total_tiles < slots) return t;
+  const int r = total_tiles % slots;
+  if (r == 0) return t;
+  const int bm = gemm_bm(cfg), bn = gemm_bn(cfg), bk = (cfg == 2) ? 32 : 16;
+  double best = 1.0;
+  int best_s = 1;
+  for (int s = 2; s <= 8; ++s) {
+    if (min_k / s < 4 * bk) break;
+    if ((size_t)r * s * bm * bn > ws_doubles) break;
+    const double waves = (double)((r * s + slots - 1) / slots) / s + 0.02 * s;   // + segment reduce
+    if (waves < best) {
+      best = waves;
+      best_s = s;
+    }
+  }
+  if (best_s > 1) {
+    t.dp_tiles = total_tiles - r;
+    t.splits = best_s;
+    t.ws = ws;
+  }
+  return t;
 }
 
 void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

@@ -31,7 +31,11 @@ class FTCCError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("n_tau", ctypes.c_int), ("nodes_per_panel", ctypes.c_int), ("propagator", ctypes.c_int),
                 ("occ_thresh", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("checkpoint", ctypes.c_int), ("diis_depth", ctypes.c_int)]
+                ("checkpoint", ctypes.c_int), ("diis_depth", ctypes.c_int), ("mem_cap_bytes", ctypes.c_size_t)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -53,6 +57,7 @@ def library():
                                        ctypes.POINTER(Options)]),
         "ftcc_destroy": (ctypes.c_int, [ctypes.c_void_p]),
         "ftcc_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+        "ftcc_set_allocator": (ctypes.c_int, [ctypes.c_void_p, ALLOC_FN, FREE_FN, ctypes.c_void_p]),
         "ftcc_set_hamiltonian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
         "ftcc_solve_amplitudes": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _I, _I]),
         "ftcc_grand_potential": (ctypes.c_int, [ctypes.c_void_p, _D, _D]),
@@ -78,7 +83,8 @@ def library():
 
 def exported_symbols():
     """Names the C header declares (used by the CPU-side load test)."""
-    return ["ftcc_default_options", "ftcc_create", "ftcc_destroy", "ftcc_set_stream", "ftcc_set_hamiltonian",
+    return ["ftcc_default_options", "ftcc_create", "ftcc_destroy", "ftcc_set_stream", "ftcc_set_allocator",
+            "ftcc_set_hamiltonian",
             "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
             "ftcc_get_lambda", "ftcc_response", "ftcc_eval_residual", "ftcc_time_residual", "ftcc_stats",
             "ftcc_kernel_profile",
@@ -143,6 +149,21 @@ class Context:
 
     def set_stream(self, stream_ptr):
         _check(self.lib.ftcc_set_stream(self._h, ctypes.c_void_p(stream_ptr)))
+
+    def set_allocator(self, alloc, free):
+        """Python callables alloc(nbytes) -> device address (int, 0 on failure) and
+        free(address); called from the library for its bulk device buffers."""
+        def _a(nbytes, _user):
+            try:
+                return int(alloc(int(nbytes))) or None
+            except Exception:
+                return None
+
+        def _f(ptr, _user):
+            free(int(ptr))
+        # keep the C thunks alive as long as the context
+        self._alloc_thunks = (ALLOC_FN(_a), FREE_FN(_f))
+        _check(self.lib.ftcc_set_allocator(self._h, self._alloc_thunks[0], self._alloc_thunks[1], None))
 
     def set_hamiltonian(self, inst, h, eri, eps):
         h = _f64(h)

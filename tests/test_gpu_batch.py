@@ -84,3 +84,35 @@ def test_one_slot_mode_matches(F, monkeypatch):
         assert np.allclose(r0[key], r1[key], rtol=1e-12, atol=1e-13), key
     for a, b in zip(r0["h"], r1["h"]):
         assert np.abs(a - b).max() < 1e-12
+
+
+def test_failed_instance_does_not_disturb_batch(F):
+    """An instance whose march diverges (a low-temperature, strongly coupled ring
+    with the restricted reference) is reported in its status slot and stops
+    running; the other instance of the batch gets the single-instance results."""
+    good = fi.hubbard_config(L=4, U=2.0, T=1.0)
+    kind, kw = fi.batched_configs(0)[21]
+    assert kind == "hubbard"
+    bad = fi.hubbard_config(**kw)
+    print(f"[batch] diverging instance {kw} next to hubbard L=4", flush=True)
+    opt = dict(n_tau=20, nodes_per_panel=4, occ_thresh=1e-6, tol=1e-13, max_iter=100)
+
+    def run(systems):
+        ctx = F.Context(len(systems), **opt)
+        for i, s in enumerate(systems):
+            ctx.set_hamiltonian(i, s.h, s.eri, s.eps)
+        _, st = ctx.solve([s.mu for s in systems], [s.beta for s in systems], raise_on_status=False)
+        om, _ = ctx.grand_potential()
+        _, lst = ctx.lam(raise_on_status=False)
+        r = ctx.response(want_mu=True, want_beta=True, want_h=False)
+        ctx.close()
+        return st, lst, om, r
+
+    st, lst, om, r = run([good, bad])
+    assert st[0] == 0 and st[1] in (F.ENOCONV, F.ENONFINITE)
+    assert lst[0] == 0 and lst[1] != 0
+    st1, _, om1, r1 = run([good])
+    assert st1[0] == 0
+    assert abs(om[0] - om1[0]) < 1e-12 * abs(om1[0])
+    assert abs(r["mu"][0] - r1["mu"][0]) < 1e-11 * max(1.0, abs(r1["mu"][0]))
+    assert abs(r["beta"][0] - r1["beta"][0]) < 1e-11 * max(1.0, abs(r1["beta"][0]))
