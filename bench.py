@@ -16,12 +16,17 @@ metric: tau-point T2 residual evaluations per second of whole-step wall time
 re-evaluations inside the adjoint and response phases).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|hubbard6|hubbard10]
-                       [--no-cpu-baseline] [--mode step|residual|copy] [--reps R]
+                       [--no-cpu-baseline] [--mode step|residual|copy|batch] [--reps R]
+                       [--per-instance]
 
 --mode residual times R back-to-back residual evaluations of every node of the
 last panel at the converged amplitudes (kernel throughput alone); --mode copy
 runs R device-to-device copies of 1 GiB (the byte-counter calibration for the
-traffic figures).  Both print one JSON line of their own.
+traffic figures).  --mode batch runs one step of the 32-instance mixed batch
+(16 UEG 57-PW points over r_s x Theta, 16 Hubbard rings L = 6..14 with random U
+and T, 20 tau points, occupation threshold 1e-6) in one context, and with
+--per-instance the same instances one context each; several minutes.  These
+print one JSON line of their own.
 """
 from __future__ import annotations
 
@@ -36,6 +41,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix, flop/s
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm128_ueg57_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_01729_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant GEMM family from the committed
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy); None when
+    the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        src = open(KERNEL_SOURCE, "rb").read()
+    except OSError:
+        return None
+    b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+-]+)", text)
+    h = re.search(r"kernels_hip_sha256:\s*([0-9a-f]{64})", text)
+    if not b or not h or hashlib.sha256(src).hexdigest() != h.group(1):
+        return None
+    return float(b.group(1))
 
 
 def workload(name):
@@ -100,6 +125,45 @@ def copy_calibration(reps, nbytes=1 << 30):
                 gbps=2 * nbytes * reps / el / 1e9)
 
 
+def batch_bench(per_instance):
+    """One step (forward + Lambda + response for mu, beta, h) of the mixed batch,
+    batched and optionally per instance."""
+    import ftcc_inputs as fi
+    from paper_2004_01729_amd import ftcc as F
+    systems = []
+    for kind, kw in fi.batched_configs(0):
+        if kind == "ueg":
+            systems.append(fi.ueg_config(kw["n_pw"], 14, kw["rs"], kw["theta"]))
+        else:
+            systems.append(fi.hubbard_config(L=kw["L"], U=kw["U"], T=kw["T"]))
+    opts = dict(n_tau=20, nodes_per_panel=4, occ_thresh=1e-6, tol=1e-12, max_iter=200)
+
+    def run(sys_):
+        ctx = F.Context(len(sys_), **opts)
+        for i, s in enumerate(sys_):
+            ctx.set_hamiltonian(i, s.h, s.eri, s.eps)
+        t0 = time.perf_counter()
+        _, st = ctx.solve([s.mu for s in sys_], [s.beta for s in sys_], raise_on_status=False)
+        ctx.grand_potential()
+        evals = ctx.stats()["resid_evals"]
+        t1 = time.perf_counter()
+        ctx.lam(raise_on_status=False)
+        ctx.response(want_mu=True, want_beta=True, want_h=True)
+        t2 = time.perf_counter()
+        ctx.close()
+        return dict(forward_s=t1 - t0, gradient_s=t2 - t1, total_s=t2 - t0, forward_resid_evals=evals,
+                    failed=[i for i, v in enumerate(st.tolist()) if v != 0])
+
+    out = dict(mode="batch", workload="batch32_ueg57pw_x16_hubbard_L6-14_x16", n_instances=len(systems),
+               n_tau=20, occ_thresh=1e-6, batched=run(systems))
+    if per_instance:
+        rows = [run([s]) for s in systems]
+        out["per_instance"] = {k: sum(r[k] for r in rows) for k in ("forward_s", "gradient_s", "total_s")}
+        out["per_instance"]["failed"] = [i for i, r in enumerate(rows) if r["failed"]]
+        out["batched_speedup"] = out["per_instance"]["total_s"] / out["batched"]["total_s"]
+    return out
+
+
 def cpu_baseline(s, budget_s=20.0):
     """The oracle as it stands (spin-summed restricted kernels, numpy/BLAS on
     the host) on a bounded sample: the einsum items of one residual evaluation
@@ -150,8 +214,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ueg57")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy"))
+    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch"))
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--per-instance", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -165,6 +230,9 @@ def main():
         raise SystemExit("no GPU visible")
     if args.mode == "copy":
         print(json.dumps(copy_calibration(args.reps)), flush=True)
+        return
+    if args.mode == "batch":
+        print(json.dumps(batch_bench(args.per_instance)), flush=True)
         return
     s, opts, cfg = workload(args.workload)
     ctx = F.Context(1, **opts)
@@ -242,7 +310,8 @@ def main():
             "peak": PEAK_FP64_MFMA / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_MFMA,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "kernel": "gemm_mfma_kernel<128,128,16,*,*> (FP64 MFMA 16x16x4)",
             "launches": prof["launches"],
             "avg_launch_ms": 1e3 * prof["seconds"] / max(prof["launches"], 1),

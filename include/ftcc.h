@@ -144,6 +144,24 @@ int ftcc_get_lambda(ftcc_ctx* ctx, int inst, int node, double* lam1, double* lam
 int ftcc_response(ftcc_ctx* ctx, double* dO_dmu, double* dO_dbeta, double* dO_dh,
                   const double* const* deri_dtheta, const double* const* dh_dtheta, double* dO_dtheta);
 
+/* Fixed electron number (Section III fixes <N> = 14 for the electron gas this
+ * way; the appendix on the UEG basis-set error chooses mu_CC so that the
+ * coupled-cluster system holds N electrons): for every instance, the chemical
+ * potential at which N = -dOmega/dmu (Section II.D, the mu response at a frozen
+ * reference) equals n_target[i] to |N - n_target| <= tol * max(1, |n_target|).
+ *   mu_inout  start values in, solutions out;  beta  fixed inverse temperatures
+ *   n_out     optional: N at the returned mu
+ *   max_iter  evaluations of N per instance; each is a forward march, the
+ *             Lambda adjoint and the mu response of the whole batch
+ * Bracketing from the start value in steps set by the mean-field
+ * compressibility 2 beta sum_p n_p (1 - n_p), then regula falsi (Illinois).
+ * status_out[i]: 0, FTCC_ENOCONV (max_iter reached) or the status of a failed
+ * march.  On return the context holds the amplitudes and Lambda at the
+ * returned mu of every instance with status 0, so grand_potential and
+ * response need no new solve. */
+int ftcc_find_mu(ftcc_ctx* ctx, const double* n_target, double* mu_inout, const double* beta, double tol,
+                 int max_iter, double* n_out, int* iters_out, int* status_out);
+
 /* One evaluation of the kernels E, S1, S2 (eqn:E, eqn:ccS1, eqn:ccS2) of instance
  * `inst` at the given amplitudes and the thermal integrals of (mu, beta):
  * t1, S1 n*n; t2, S2 n^4; E scalar. */

@@ -262,3 +262,62 @@ def d_omega_dh(model, grid, sol, adj):
         x = k % m
         out = out + model.vjp_fock(s, grid.b[x] / P, adj.lamt[k])
     return out
+
+
+def find_mu(make_model, grid, n_target, mu0, tol=1e-10, max_iter=40, solve_tol=1e-13):
+    """Chemical potential at which the FT-CCSD electron number N = -dOmega/dmu
+    (Section II.D) equals n_target, as the paper fixes <N> for the electron gas
+    (Section III; the appendix on the UEG basis-set error chooses mu_CC so that
+    the coupled-cluster system holds N electrons).
+
+    make_model(mu) builds the model at chemical potential mu (frozen reference:
+    orbitals and eps fixed).  Regula falsi with the Illinois modification on
+    N(mu) - n_target, after expanding a bracket from mu0 in steps set by the
+    mean-field compressibility dN/dmu = 2 sum_p beta n_p (1 - n_p).  Returns
+    (mu, N(mu), iterations)."""
+    def n_of(mu):
+        model = make_model(mu)
+        sol = solve(model, grid, tol=solve_tol)
+        adj = adjoint(model, grid, sol, tol=solve_tol)
+        return -d_omega(model, grid, sol, adj, "mu")
+
+    def mf_slope(mu):
+        ints = make_model(mu).ints
+        return 2.0 * grid.beta * float(np.sum(ints.n_occ * ints.n_vir))
+
+    scale = max(1.0, abs(n_target))
+    a, fa = mu0, n_of(mu0) - n_target
+    its = 1
+    if abs(fa) <= tol * scale:
+        return a, fa + n_target, its
+    step = -fa / max(mf_slope(mu0), 1e-12)
+    b, fb = a + step, None
+    while True:                      # expand until N - n_target changes sign
+        fb = n_of(b) - n_target
+        its += 1
+        if abs(fb) <= tol * scale:
+            return b, fb + n_target, its
+        if fa * fb < 0:
+            break
+        a, fa = b, fb
+        step *= 2.0
+        b = a + step
+        if its > max_iter:
+            raise RuntimeError("find_mu: no bracket")
+    side = 0
+    while its < max_iter:
+        c = (a * fb - b * fa) / (fb - fa)
+        fc = n_of(c) - n_target
+        its += 1
+        if abs(fc) <= tol * scale:
+            return c, fc + n_target, its
+        if fc * fb < 0:
+            a, fa = b, fb
+            b, fb = c, fc
+            side = 0
+        else:
+            b, fb = c, fc
+            if side == -1:
+                fa *= 0.5
+            side = -1
+    raise RuntimeError("find_mu: no convergence")

@@ -201,6 +201,7 @@ struct Instance {
   bool has_ham = false;
   double mu = 0.0, beta = 1.0;
   double *h = nullptr, *eri = nullptr, *eps = nullptr;
+  std::vector<double> eps_host;
   double *occ = nullptr, *wo = nullptr, *wv = nullptr, *fock = nullptr;
   double *dn = nullptr, *dwo = nullptr, *dwv = nullptr, *du_raw = nullptr, *u_raw = nullptr;
   std::map<std::string, double*> blk, dblk;
@@ -709,6 +710,9 @@ void build(ftcc_ctx* c) {
   c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {}, vcache, budget / 2);
   c->ex_d->set_profiler(&c->prof);
   trace_mem(c, "executors");
+  // no kernel-profiler events inside the autotuner or a graph capture
+  const bool prof_on = c->prof.enabled;
+  c->prof.enabled = false;
   c->ex_main->autotune(c->stream);
   c->ex_d->autotune(c->stream);
   FTCC_HIP(hipStreamSynchronize(c->stream));
@@ -728,7 +732,7 @@ void build(ftcc_ctx* c) {
     FTCC_HIP(hipGraphDestroy(g));
   }
 
-  // propagator descriptors: one per (instance, segment) for each mode's buffer roles
+  c->prof.enabled = prof_on;
   c->built = true;
 }
 
@@ -1208,6 +1212,7 @@ int ftcc_set_hamiltonian(ftcc_ctx* c, int i, int n, const double* h, const doubl
     FTCC_HIP(hipMemcpy(I.h, h, sizeof(double) * n2, hipMemcpyHostToDevice));
     FTCC_HIP(hipMemcpy(I.eri, eri, sizeof(double) * n4, hipMemcpyHostToDevice));
     FTCC_HIP(hipMemcpy(I.eps, eps, sizeof(double) * n, hipMemcpyHostToDevice));
+    I.eps_host.assign(eps, eps + n);
     I.has_ham = true;
     c->solved = false;
     c->have_lambda = false;
@@ -1672,6 +1677,106 @@ int ftcc_kernel_profile(ftcc_ctx* c, int enable, double* flops, double* seconds,
     c->prof.reset();
     c->prof.enabled = enable != 0;
   });
+}
+
+int ftcc_find_mu(ftcc_ctx* c, const double* n_target, double* mu, const double* beta, double tol, int max_iter,
+                 double* n_out, int* iters_out, int* status_out) {
+  int any_fail = 0;
+  int rc = run_guarded([&] {
+    if (!c || !n_target || !mu || !beta) fail(FTCC_EINVAL, "null argument");
+    if (!(tol > 0.0) || max_iter < 1) fail(FTCC_EINVAL, "tol must be > 0 and max_iter >= 1");
+    const int B = c->B;
+    for (int i = 0; i < B; ++i)
+      if (!std::isfinite(n_target[i]) || !std::isfinite(mu[i])) fail(FTCC_EINVAL, "non-finite target or start");
+    // per-instance root finder on f(mu) = N(mu) - n_target: bracket from the start
+    // value in steps set by the mean-field compressibility, then regula falsi
+    // with the Illinois modification
+    enum { START, BRACKET, FALSI, DONE };
+    std::vector<int> phase(B, START), side(B, 0), its(B, 0), st(B, 0);
+    std::vector<double> x(mu, mu + B), a(B), fa(B), b(B), fb(B), step(B), nval(B, 0.0);
+    auto mf_slope = [&](int i, double m) {
+      double s = 0.0;
+      for (double e : c->inst[i].eps_host) {
+        const double z = beta[i] * (e - m);
+        const double nocc = 1.0 / (1.0 + std::exp(z)), nvir = 1.0 / (1.0 + std::exp(-z));
+        s += nocc * nvir;
+      }
+      return std::max(2.0 * beta[i] * s, 1e-12);
+    };
+    std::vector<int> fst(B), lst(B);
+    std::vector<double> dmu(B);
+    for (int it = 0; it < max_iter; ++it) {
+      bool any = false;
+      for (int i = 0; i < B; ++i) any = any || phase[i] != DONE;
+      if (!any) break;
+      int r = ftcc_solve_amplitudes(c, x.data(), beta, nullptr, fst.data());
+      if (r != FTCC_OK && r != FTCC_ENOCONV && r != FTCC_ENONFINITE) fail(r, g_err);
+      r = ftcc_lambda(c, nullptr, lst.data());
+      if (r != FTCC_OK && r != FTCC_ENOCONV && r != FTCC_ENONFINITE) fail(r, g_err);
+      r = ftcc_response(c, dmu.data(), nullptr, nullptr, nullptr, nullptr, nullptr);
+      if (r != FTCC_OK) fail(r, g_err);
+      for (int i = 0; i < B; ++i) {
+        if (phase[i] == DONE) continue;
+        if (fst[i] || lst[i]) {
+          st[i] = fst[i] ? fst[i] : lst[i];
+          phase[i] = DONE;
+          continue;
+        }
+        ++its[i];
+        nval[i] = -dmu[i];
+        const double f = nval[i] - n_target[i];
+        if (std::fabs(f) <= tol * std::max(1.0, std::fabs(n_target[i]))) {
+          phase[i] = DONE;
+          continue;
+        }
+        if (phase[i] == START) {
+          a[i] = x[i];
+          fa[i] = f;
+          step[i] = -f / mf_slope(i, x[i]);
+          x[i] = a[i] + step[i];
+          phase[i] = BRACKET;
+        } else if (phase[i] == BRACKET) {
+          b[i] = x[i];
+          fb[i] = f;
+          if (fa[i] * fb[i] < 0.0) {
+            phase[i] = FALSI;
+            side[i] = 0;
+            x[i] = (a[i] * fb[i] - b[i] * fa[i]) / (fb[i] - fa[i]);
+          } else {
+            a[i] = b[i];
+            fa[i] = fb[i];
+            step[i] *= 2.0;
+            x[i] = a[i] + step[i];
+          }
+        } else {   // FALSI: x is the new point c
+          if (f * fb[i] < 0.0) {
+            a[i] = b[i];
+            fa[i] = fb[i];
+            side[i] = 0;
+          } else {
+            if (side[i] == -1) fa[i] *= 0.5;
+            side[i] = -1;
+          }
+          b[i] = x[i];
+          fb[i] = f;
+          x[i] = (a[i] * fb[i] - b[i] * fa[i]) / (fb[i] - fa[i]);
+        }
+      }
+    }
+    for (int i = 0; i < B; ++i) {
+      if (phase[i] != DONE) st[i] = FTCC_ENOCONV;
+      mu[i] = x[i];
+      if (n_out) n_out[i] = nval[i];
+      if (iters_out) iters_out[i] = its[i];
+      if (status_out) status_out[i] = st[i];
+      if (st[i]) any_fail = st[i];
+    }
+  });
+  if (rc == FTCC_OK && any_fail) {
+    g_err = "at least one instance did not reach its electron number (see status_out)";
+    return any_fail;
+  }
+  return rc;
 }
 
 int ftcc_stats(ftcc_ctx* c, long* resid_evals, long* vjp_evals, double* solve_seconds, double* lambda_seconds) {

@@ -178,6 +178,7 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     for (int i = 0; i < FM; ++i) af[0][i] = as[i * ASTEP_I];
 #pragma unroll
     for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * BSTEP_J];
+    __builtin_amdgcn_s_setprio(1);   // MFMA section: issue priority over waves in their load phase
 #pragma unroll
     for (int kq = 0; kq < BK / 4; ++kq) {
       const int c = kq & 1;
@@ -193,6 +194,7 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[c][i], bf[c][j], acc[i][j], 0, 0, 0);
     }
+    __builtin_amdgcn_s_setprio(0);
     if (more) store_tiles(cur ^ 1);
     __syncthreads();
   }

@@ -69,6 +69,7 @@ def library():
                                               _D, _D, _D, _D, _D]),
         "ftcc_time_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D]),
         "ftcc_stats": (ctypes.c_int, [ctypes.c_void_p, _L, _L, _D, _D]),
+        "ftcc_find_mu": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, ctypes.c_double, ctypes.c_int, _D, _I, _I]),
         "ftcc_kernel_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D, _L]),
         "ftcc_last_error": (ctypes.c_char_p, []),
         "ftcc_abi_version": (ctypes.c_int, []),
@@ -86,7 +87,8 @@ def exported_symbols():
     return ["ftcc_default_options", "ftcc_create", "ftcc_destroy", "ftcc_set_stream", "ftcc_set_allocator",
             "ftcc_set_hamiltonian",
             "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
-            "ftcc_get_lambda", "ftcc_response", "ftcc_eval_residual", "ftcc_time_residual", "ftcc_stats",
+            "ftcc_get_lambda", "ftcc_response", "ftcc_find_mu", "ftcc_eval_residual", "ftcc_time_residual",
+            "ftcc_stats",
             "ftcc_kernel_profile",
             "ftcc_last_error", "ftcc_abi_version"]
 
@@ -252,6 +254,20 @@ class Context:
                 dh.append(dh_flat[off:off + k * k].reshape(k, k))
                 off += k * k
         return dict(mu=dmu, beta=dbeta, h=dh, theta=dth)
+
+    def find_mu(self, n_target, mu0, beta, tol=1e-10, max_iter=40, raise_on_status=True):
+        """mu of every instance with -dOmega/dmu = n_target; returns (mu, N, iters, status)."""
+        B = self.B
+        nt = _f64(np.broadcast_to(np.asarray(n_target, float), (B,)))
+        mu = _f64(np.array(np.broadcast_to(np.asarray(mu0, float), (B,))))
+        beta = _f64(np.broadcast_to(np.asarray(beta, float), (B,)))
+        n_out = np.zeros(B)
+        its = np.zeros(B, dtype=np.int32)
+        st = np.zeros(B, dtype=np.int32)
+        rc = self.lib.ftcc_find_mu(self._h, _ptr(nt), _ptr(mu), _ptr(beta), float(tol), int(max_iter), _ptr(n_out),
+                                   its.ctypes.data_as(_I), st.ctypes.data_as(_I))
+        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE))
+        return mu, n_out, its, st
 
     def eval_residual(self, inst, mu, beta, t1, t2):
         n = self._size(inst)

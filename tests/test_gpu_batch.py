@@ -116,3 +116,21 @@ def test_failed_instance_does_not_disturb_batch(F):
     assert abs(om[0] - om1[0]) < 1e-12 * abs(om1[0])
     assert abs(r["mu"][0] - r1["mu"][0]) < 1e-11 * max(1.0, abs(r1["mu"][0]))
     assert abs(r["beta"][0] - r1["beta"][0]) < 1e-11 * max(1.0, abs(r1["beta"][0]))
+
+
+def test_kernel_profile_enabled_before_first_solve(F):
+    """The plan is built (autotuned, graph-captured) inside the first solve; an
+    enabled kernel profiler must not record inside that capture."""
+    s = fi.hubbard_config(L=12, U=2.0, T=1.0)
+    print("[profile] hubbard L=12, profiler on before the first solve", flush=True)
+    ctx = F.Context(1, n_tau=8, nodes_per_panel=4, tol=1e-12)
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    ctx.kernel_profile(1)
+    ctx.solve(s.mu, s.beta)
+    kp = ctx.kernel_profile(0)
+    om0 = ctx.grand_potential()[0][0]
+    ctx.solve(s.mu, s.beta)
+    om1 = ctx.grand_potential()[0][0]
+    ctx.close()
+    assert kp["launches"] > 0 and kp["seconds"] > 0.0 and kp["flops"] > 0.0
+    assert om0 == om1

@@ -306,3 +306,41 @@ def test_p10_electron_number(p10_case):
     n_ref = 2.0 * float(np.sum(c["model"].ints.n_occ))
     assert 0.0 < n_el < 2 * c["model"].n
     assert abs(n_el - n_ref) < 0.2
+
+
+def test_find_mu_free_fermions_closed_form():
+    """U = 0 with the exact reference: N(mu) = 2 sum_k f(eps_k - mu), so the
+    fixed-<N> search must land on the root of the closed form."""
+    from scipy.optimize import brentq
+    s = fi.hubbard_config(L=6, U=0.0, T=1.0)
+    gr = G.Grid(s.beta, 2, 4)
+
+    def make(mu):
+        return R.RestrictedModel(R.RestrictedIntegrals(s.h, s.eri, s.eps, mu, s.beta))
+    mu, n, _ = S.find_mu(make, gr, 5.0, mu0=0.0, tol=1e-12)
+
+    def n_exact(m):
+        return 2.0 * np.sum(1.0 / (1.0 + np.exp(s.beta * (s.eps - m)))) - 5.0
+    mu_exact = brentq(n_exact, -5.0, 5.0, xtol=1e-15)
+    assert abs(mu - mu_exact) < 1e-10
+    assert abs(n - 5.0) < 1e-11
+
+
+def test_find_mu_interacting_against_finite_differences():
+    """U != 0: at the returned mu, -dOmega/dmu from central differences of Omega
+    itself (no adjoint) equals the target electron number."""
+    s = fi.hubbard_config(L=4, U=2.0, T=1.0)
+    gr = G.Grid(s.beta, 2, 4)
+
+    def make(mu):
+        return R.RestrictedModel(R.RestrictedIntegrals(s.h, s.eri, s.eps, mu, s.beta))
+    mu, n, _ = S.find_mu(make, gr, 3.5, mu0=s.mu, tol=1e-12)
+    assert abs(n - 3.5) < 1e-11
+
+    def om(m):
+        return S.solve(make(m), gr, tol=1e-14).omega
+    d = 1e-3
+    d1 = (om(mu + d) - om(mu - d)) / (2 * d)
+    d2 = (om(mu + d / 2) - om(mu - d / 2)) / d
+    n_fd = -(4 * d2 - d1) / 3
+    assert abs(n_fd - 3.5) < 1e-8
