@@ -15,9 +15,9 @@ metric: tau-point T2 residual evaluations per second of whole-step wall time
 (forward residual evaluations of every node and sweep, including the forward
 re-evaluations inside the adjoint and response phases).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|hubbard6|hubbard10]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|ueg123|hubbard6|hubbard10]
                        [--no-cpu-baseline] [--mode step|residual|copy|batch] [--reps R]
-                       [--per-instance]
+                       [--per-instance] [--momentum]
 
 --mode residual times R back-to-back residual evaluations of every node of the
 last panel at the converged amplitudes (kernel throughput alone); --mode copy
@@ -26,7 +26,9 @@ traffic figures).  --mode batch runs one step of the 32-instance mixed batch
 (16 UEG 57-PW points over r_s x Theta, 16 Hubbard rings L = 6..14 with random U
 and T, 20 tau points, occupation threshold 1e-6) in one context, and with
 --per-instance the same instances one context each; several minutes.  These
-print one JSON line of their own.
+print one JSON line of their own.  --momentum evaluates the contractions over
+their crystal-momentum-allowed blocks only (a different algorithm from the dense
+one the metric's FP64-MFMA share refers to; its line has no GEMM roofline).
 """
 from __future__ import annotations
 
@@ -70,6 +72,11 @@ def workload(name):
         cfg = dict(workload="ueg_57pw_N14_rs1_theta0.5", n_orb=57, n_tau=16, nodes_per_panel=4,
                    propagator="exponential-collocation", phases="forward+lambda+response")
         return s, dict(n_tau=16, nodes_per_panel=4, tol=1e-12), cfg
+    if name == "ueg123":
+        s = fi.ueg_config(123, 14, 4.0, 1.0)
+        cfg = dict(workload="ueg_123pw_N14_rs4_theta1_thr1e-6", n_orb=123, n_tau=16, nodes_per_panel=4,
+                   propagator="exponential-collocation", phases="forward+lambda+response", checkpoint=1)
+        return s, dict(n_tau=16, nodes_per_panel=4, tol=1e-12, occ_thresh=1e-6, checkpoint=1), cfg
     if name == "hubbard6":
         s = fi.hubbard_config(L=6, U=4.0, T=1.0)
         cfg = dict(workload="hubbard_L6_U4_T1", n_orb=6, n_tau=20, nodes_per_panel=4,
@@ -125,9 +132,10 @@ def copy_calibration(reps, nbytes=1 << 30):
                 gbps=2 * nbytes * reps / el / 1e9)
 
 
-def batch_bench(per_instance):
+def batch_bench(per_instance, group=32):
     """One step (forward + Lambda + response for mu, beta, h) of the mixed batch,
-    batched and optionally per instance."""
+    batched in contexts of `group` instances (electron-gas and ring instances
+    interleaved) and optionally per instance."""
     import ftcc_inputs as fi
     from paper_2004_01729_amd import ftcc as F
     systems = []
@@ -154,8 +162,15 @@ def batch_bench(per_instance):
         return dict(forward_s=t1 - t0, gradient_s=t2 - t1, total_s=t2 - t0, forward_resid_evals=evals,
                     failed=[i for i, v in enumerate(st.tolist()) if v != 0])
 
+    # interleave the two families so that every context mixes large and small instances
+    order = [i for pair in zip(range(16), range(16, 32)) for i in pair]
+    groups = [order[k:k + group] for k in range(0, len(order), group)]
+    rows = [run([systems[i] for i in g]) for g in groups]
+    batched = {k: sum(r[k] for r in rows) for k in ("forward_s", "gradient_s", "total_s", "forward_resid_evals")}
+    batched["failed"] = sorted(g[j] for g, r in zip(groups, rows) for j in r["failed"])
+    batched["contexts"] = len(groups)
     out = dict(mode="batch", workload="batch32_ueg57pw_x16_hubbard_L6-14_x16", n_instances=len(systems),
-               n_tau=20, occ_thresh=1e-6, batched=run(systems))
+               n_tau=20, occ_thresh=1e-6, group=group, batched=batched)
     if per_instance:
         rows = [run([s]) for s in systems]
         out["per_instance"] = {k: sum(r[k] for r in rows) for k in ("forward_s", "gradient_s", "total_s")}
@@ -217,6 +232,8 @@ def main():
     ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch"))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
+    ap.add_argument("--group", type=int, default=32)
+    ap.add_argument("--momentum", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -232,10 +249,13 @@ def main():
         print(json.dumps(copy_calibration(args.reps)), flush=True)
         return
     if args.mode == "batch":
-        print(json.dumps(batch_bench(args.per_instance)), flush=True)
+        print(json.dumps(batch_bench(args.per_instance, args.group)), flush=True)
         return
     s, opts, cfg = workload(args.workload)
     ctx = F.Context(1, **opts)
+    if args.momentum:
+        ctx.set_momentum(0, *s.momentum)
+        cfg = dict(cfg, momentum_blocked=True)
     ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
     if args.mode == "residual":
         ctx.solve(s.mu, s.beta)
@@ -287,6 +307,19 @@ def main():
                     fd_rel_diff=abs(fd_mu - resp["mu"][0]) / max(1.0, abs(resp["mu"][0])))
     value = evals / el
     achieved = prof["flops"] / prof["seconds"] if prof["seconds"] > 0 else 0.0
+    roofline = {
+        "bound": "mfma",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP64_MFMA / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_MFMA,
+        "traffic": measured_traffic(),
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "kernel": "gemm_mfma_kernel<128,128,16,*,*> (FP64 MFMA 16x16x4)",
+        "launches": prof["launches"],
+        "avg_launch_ms": 1e3 * prof["seconds"] / max(prof["launches"], 1),
+        "flop_per_launch": prof["flops"] / max(prof["launches"], 1),
+    } if prof["launches"] > 0 else None
     line = {
         "metric": "tau-point T2 residual evals/s",
         "value": value,
@@ -304,19 +337,7 @@ def main():
                        omega=float(om[0]), omega_cc=float(parts[0, 2]), dOmega_dmu=float(resp["mu"][0]),
                        dOmega_dbeta=float(resp["beta"][0]), gradient_vs_fd=gradient,
                        residual_throughput=m1),
-        "roofline": {
-            "bound": "mfma",
-            "achieved": achieved / 1e12,
-            "peak": PEAK_FP64_MFMA / 1e12,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_MFMA,
-            "traffic": measured_traffic(),
-            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-            "kernel": "gemm_mfma_kernel<128,128,16,*,*> (FP64 MFMA 16x16x4)",
-            "launches": prof["launches"],
-            "avg_launch_ms": 1e3 * prof["seconds"] / max(prof["launches"], 1),
-            "flop_per_launch": prof["flops"] / max(prof["launches"], 1),
-        },
+        "roofline": roofline,
     }
     ctx.close()
     if not args.no_cpu_baseline:

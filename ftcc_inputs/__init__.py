@@ -52,6 +52,14 @@ class System:
     def n(self) -> int:
         return self.h.shape[0]
 
+    @property
+    def momentum(self):
+        """(labels (n, dims) int array, modulus per component, 0 = none) of the
+        conserved crystal momentum, or None when the basis carries none."""
+        if "momentum_labels" not in self.meta:
+            return None
+        return self.meta["momentum_labels"], self.meta["momentum_modulus"]
+
 
 # ---------------------------------------------------------------- Hubbard ring
 def hubbard_ring(L: int, t: float, U: float):
@@ -165,7 +173,8 @@ def hubbard_config(L=6, t=1.0, U=4.0, T=1.0, mu=None):
     h, eri = hubbard_ring(L, t, U)
     eps, _ = restricted_thermal_hf(h, eri, beta, mu=mu)
     return System(f"hubbard_L{L}_U{U:g}_T{T:g}", h, eri, eps, mu, beta,
-                  dict(L=L, t=t, U=U, T=T))
+                  dict(L=L, t=t, U=U, T=T, momentum_labels=np.arange(L).reshape(L, 1),
+                       momentum_modulus=[L]))
 
 
 def ueg_config(n_pw=57, n_el=14, rs=1.0, theta=0.5):
@@ -177,7 +186,9 @@ def ueg_config(n_pw=57, n_el=14, rs=1.0, theta=0.5):
     h, eri, geo = ueg_plane_waves(n_el, rs, n_pw)
     eps, mu = restricted_thermal_hf(h, eri, beta, n_el=n_el)
     return System(f"ueg_{n_pw}pw_rs{rs:g}_theta{theta:g}", h, eri, eps, mu, beta,
-                  dict(n_pw=n_pw, n_el=n_el, rs=rs, theta=theta, T=T, **{k: v for k, v in geo.items() if k != "kvec"}))
+                  dict(n_pw=n_pw, n_el=n_el, rs=rs, theta=theta, T=T,
+                       momentum_labels=ueg_shell_basis(n_pw).astype(np.int64), momentum_modulus=[0, 0, 0],
+                       **{k: v for k, v in geo.items() if k != "kvec"}))
 
 
 def batched_configs(seed=0, n_pw=57):

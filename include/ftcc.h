@@ -102,6 +102,21 @@ typedef void* (*ftcc_alloc_fn)(size_t bytes, void* user);
 typedef void (*ftcc_free_fn)(void* ptr, void* user);
 int ftcc_set_allocator(ftcc_ctx* ctx, ftcc_alloc_fn alloc, ftcc_free_fn free_fn, void* user);
 
+/* Crystal momentum of the orbitals of instance `inst` (plane waves of the
+ * electron gas, Bloch orbitals of a ring): orbital p carries the integer
+ * vector labels[p * dims + c], c < dims <= 3, component c compared modulo
+ * modulus[c] when modulus[c] > 0 (e.g. k mod L on an L-site ring), |label| <
+ * 65536.  When every instance has labels, every two-operand contraction of the
+ * residual, of its reverse and of the response runs over its momentum-allowed
+ * blocks only: an amplitude s_{ij..}^{ab..} or integral <pq|rs> is nonzero only
+ * when k_i + k_j = k_a + k_b (the translation invariance that Section II.D
+ * notes for the electron gas), which removes all but 1/36 (6-site ring) to
+ * 1/1e5 (123 plane waves) of the dense O(n^6) work.  h, <pq|rs> and any
+ * response direction must vanish where the labels forbid (checked on the
+ * device when the plan is built or the direction is passed: FTCC_EINVAL).
+ * Must be called before the first solve; labels are copied. */
+int ftcc_set_momentum(ftcc_ctx* ctx, int inst, int n, int dims, const int* labels, const int* modulus);
+
 /* Instance `inst` (0 <= inst < n_instances) with n spatial orbitals:
  *   h    n*n row-major one-body matrix (reference orbital basis)
  *   eri  n^4 row-major <pq|rs> = int phi_p*(1) phi_q*(2) r12^-1 phi_r(1) phi_s(2);

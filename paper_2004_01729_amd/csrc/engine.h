@@ -64,8 +64,13 @@ class Program {
   }
   void finalize();
   bool finalized() const { return finalized_; }
+  // Conservation law of a tensor: sum over its axes of sign[axis] * k(index) = 0
+  // for every nonzero element (k: the orbitals' conserved momentum).  Declared
+  // for inputs and constants; the executor infers the laws of the other tensors.
+  void set_law(const std::string& name, const std::vector<int>& signs);
   std::vector<TensorDecl> t;
   std::vector<SymOp> ops;
+  std::vector<std::vector<int>> law;   // per tensor, empty: not declared
 
  private:
   bool finalized_ = false;
@@ -75,13 +80,15 @@ class Program {
 Program build_residual_program();
 
 struct Launch {
-  enum Kind { PERM, GEMM, DOT, FILL } kind = PERM;
+  enum Kind { PERM, GEMM, DOT, FILL, SGEMM } kind = PERM;
   int n_prob = 0;
   int total = 0;
   int cfg = 0;
   bool ta = false, tb = false;
   int splitk_blocks = 0;
   int min_k = 0;                    // smallest K of the launch's GEMM problems
+  void* d_tasks = nullptr;          // SGEMM: task list
+  int n_tasks = 0;
   int dot_blocks = 0;
   void* d_desc = nullptr;
   int* d_prefix = nullptr;
@@ -98,6 +105,14 @@ struct ProblemRef {
   int inst;
   int node;
   int n;
+};
+
+// Conserved momentum of the orbitals of one instance: orbital p has components
+// labels[p * dims + c], compared modulo modulus[c] when modulus[c] > 0.
+struct InstMomentum {
+  int dims = 0;
+  std::vector<int> modulus;
+  std::vector<int> labels;
 };
 
 // (tensor id, problem index, gradient buffer?) -> device pointer
@@ -158,6 +173,11 @@ class Executor {
     gate_ = d_flags;
     gate_host_ = h_flags;
   }
+  // Momentum labels per instance (indexed by ProblemRef::inst; every instance
+  // needs them).  Set before build(): every two-operand contraction is then
+  // evaluated over its momentum-allowed blocks only (laws from the Program).
+  void set_momentum(const std::vector<const InstMomentum*>& by_instance) { mom_ = by_instance; }
+  double sgemm_flops_forward() const;
   double gemm_flops_forward() const;
   double gemm_flops_backward() const;
   int n_launches_forward() const { return (int)fwd_.size(); }
@@ -167,7 +187,8 @@ class Executor {
   void run(const std::vector<Launch>& L, hipStream_t s) const;
   void contract(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
                 const PerProb& A, const std::string& ai, int a_const, const PerProb* B, const std::string& bi,
-                int b_const, bool acc, const std::string& tag, int a_val = -1, int b_val = -1);
+                int b_const, bool acc, const std::string& tag, int a_val = -1, int b_val = -1, int t_out = -1,
+                int t_a = -1, int t_b = -1);
   PerProb value_permuted(std::vector<Launch>& dst, int tensor, const PerProb& X, const std::string& xi,
                          const std::string& yi, const PerProb& scratch, const std::string& tag);
   void perm(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
@@ -196,6 +217,22 @@ class Executor {
   KernelProfiler* prof_ = nullptr;
   const int* gate_ = nullptr;
   const int* gate_host_ = nullptr;
+  // momentum blocking
+  std::vector<const InstMomentum*> mom_;
+  std::vector<std::vector<int>> law_;      // per tensor (empty: no usable law)
+  std::vector<char> law_ok_;
+  struct GroupTable {
+    void* off1 = nullptr;                  // device: element offsets in the first operand
+    void* off2 = nullptr;                  // device: element offsets in the second operand
+    std::map<long long, std::pair<int, int>> blocks;   // packed momentum -> (first tuple, count)
+  };
+  std::map<std::string, GroupTable> group_cache_;
+  void infer_laws();
+  bool contract_blocked(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
+                        const PerProb& A, const std::string& ai, const PerProb& B, const std::string& bi, bool acc,
+                        const std::string& tag, int t_out, int t_a, int t_b);
+  const GroupTable& group_table(int inst, long n, const std::string& letters, const std::string& xi,
+                                const std::string& yi, const std::vector<int>& signs);
   double run_flops(const Launch& l) const;
   GemmTail tail_of(const Launch& l, int cfg) const {
     return plan_gemm_tail(cfg, l.total, l.min_k, l.splitk_blocks > 0, scratch_ ? scratch_->tail_ws : nullptr,

@@ -46,7 +46,15 @@ void Program::op(const std::string& out, const std::string& oi, double alpha, co
 
 // An intermediate is derived (a constant combination) when every op writing it
 // reads only constants or derived tensors; those ops form the set-up list.
+void Program::set_law(const std::string& name, const std::vector<int>& signs) {
+  const int k = id(name);
+  if ((int)signs.size() != t[k].rank) throw std::runtime_error("law rank mismatch: " + name);
+  if ((int)law.size() < (int)t.size()) law.resize(t.size());
+  law[k] = signs;
+}
+
 void Program::finalize() {
+  law.resize(t.size());
   for (auto& d : t) d.derived = false;
   bool changed = true;
   while (changed) {
@@ -268,9 +276,12 @@ Executor::PerProb Executor::value_permuted(std::vector<Launch>& dst, int tensor,
 void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
                         const PerProb& A, const std::string& ai, int a_const, const PerProb* B,
                         const std::string& bi, int b_const, bool acc, const std::string& tag, int a_val,
-                        int b_val) {
+                        int b_val, int t_out, int t_a, int t_b) {
   const double beta = acc ? 1.0 : 0.0;
   const int np = (int)probs_.size();
+  if (B && !oi.empty() && !ai.empty() && !bi.empty() && &dst != &setup_ &&
+      contract_blocked(dst, out, oi, alpha, A, ai, *B, bi, acc, tag, t_out, t_a, t_b))
+    return;
   if (!B) {
     for (char c : ai)
       if (!has(oi, c)) throw std::runtime_error("single-operand reduction unsupported: " + tag);
@@ -479,6 +490,234 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
   if (!c_direct) perm(dst, scratch_->c, M + N, out, oi, 1.0, beta, nullptr, tag + ":permC");
 }
 
+
+// ------------------------------------------------------------------ momentum blocking
+// Laws of the intermediates from the ops, in program order: a unary op copies
+// its operand's signs; for out = A * B the contracted letters fix the relative
+// orientation s of B's law (sign_A * sign_B, the same for every contracted
+// letter), and out gets sign_A on A's free letters and -s * sign_B on B's.
+// Every op writing a tensor must give the same law up to an overall sign.
+void Executor::infer_laws() {
+  const int nt = (int)prog_->t.size();
+  law_.assign(nt, {});
+  law_ok_.assign(nt, 0);
+  std::vector<char> bad(nt, 0), known(nt, 0);
+  for (int k = 0; k < nt; ++k)
+    if ((k < (int)prog_->law.size() && !prog_->law[k].empty()) || prog_->t[k].rank == 0) {
+      if (k < (int)prog_->law.size()) law_[k] = prog_->law[k];
+      known[k] = 1;
+    }
+  for (const SymOp& o : prog_->ops) {
+    bool ok = known[o.a] && !bad[o.a] && (o.b < 0 || (known[o.b] && !bad[o.b]));
+    std::vector<int> lc;
+    if (ok) {
+      auto sg = [&](int t, const std::string& idx, char c) { return law_[t][idx.find(c)]; };
+      int s = -1;
+      bool first = true;
+      if (o.b >= 0)
+        for (char c : o.ai)
+          if (has(o.bi, c)) {
+            const int r = sg(o.a, o.ai, c) * sg(o.b, o.bi, c);
+            if (first) {
+              s = r;
+              first = false;
+            } else if (r != s) {
+              ok = false;
+            }
+          }
+      if (ok)
+        for (char c : o.oi) lc.push_back(has(o.ai, c) ? sg(o.a, o.ai, c) : -s * sg(o.b, o.bi, c));
+    }
+    const int k = o.out;
+    if (!ok) {
+      bad[k] = 1;
+    } else if (!known[k]) {
+      law_[k] = lc;
+      known[k] = 1;
+    } else {
+      std::vector<int> neg(lc);
+      for (int& v : neg) v = -v;
+      if (law_[k] != lc && law_[k] != neg) bad[k] = 1;
+    }
+  }
+  for (int k = 0; k < nt; ++k) law_ok_[k] = known[k] && !bad[k];
+}
+
+static long long pack_momentum(const std::vector<int>& q) {
+  long long key = 0;
+  for (size_t c = 0; c < q.size(); ++c) key |= (long long)(q[c] + (1 << 19)) << (21 * c);
+  return key;
+}
+
+// Tuples of `letters` (each 0..n-1) in momentum-block order, with their element
+// offsets in the operands indexed by xi and yi (row-major, every axis n) and
+// the packed momentum sum_l signs[l] k(index_l) of each block.
+const Executor::GroupTable& Executor::group_table(int inst, long n, const std::string& letters,
+                                                  const std::string& xi, const std::string& yi,
+                                                  const std::vector<int>& signs) {
+  std::string key = std::to_string(inst) + "|" + letters + "|" + xi + "|" + yi + "|";
+  for (int v : signs) key += (v > 0 ? '+' : '-');
+  auto it = group_cache_.find(key);
+  if (it != group_cache_.end()) return it->second;
+  const InstMomentum& M = *mom_[inst];
+  const int g = (int)letters.size(), D = M.dims;
+  auto stride = [&](const std::string& idx, char c) -> unsigned long {
+    const size_t pos = idx.find(c);
+    return (unsigned long)ipow(n, (int)idx.size() - 1 - (int)pos);
+  };
+  std::vector<unsigned long> sx(g), sy(g);
+  for (int l = 0; l < g; ++l) {
+    sx[l] = stride(xi, letters[l]);
+    sy[l] = stride(yi, letters[l]);
+  }
+  const long count = ipow(n, g);
+  struct Row {
+    long long key;
+    unsigned ox, oy;
+  };
+  std::vector<Row> rows(count);
+  std::vector<int> idx(g, 0), q(D);
+  for (long t = 0; t < count; ++t) {
+    unsigned long ox = 0, oy = 0;
+    std::fill(q.begin(), q.end(), 0);
+    for (int l = 0; l < g; ++l) {
+      ox += idx[l] * sx[l];
+      oy += idx[l] * sy[l];
+      for (int c = 0; c < D; ++c) q[c] += signs[l] * M.labels[(size_t)idx[l] * D + c];
+    }
+    for (int c = 0; c < D; ++c)
+      if (M.modulus[c] > 0) q[c] = ((q[c] % M.modulus[c]) + M.modulus[c]) % M.modulus[c];
+    rows[t] = Row{pack_momentum(q), (unsigned)ox, (unsigned)oy};
+    for (int l = g - 1; l >= 0; --l) {   // next tuple, last letter fastest
+      if (++idx[l] < n) break;
+      idx[l] = 0;
+    }
+  }
+  std::stable_sort(rows.begin(), rows.end(), [](const Row& a, const Row& b) { return a.key < b.key; });
+  GroupTable T;
+  std::vector<unsigned> o1(count), o2(count);
+  for (long t = 0; t < count; ++t) {
+    o1[t] = rows[t].ox;
+    o2[t] = rows[t].oy;
+    auto b = T.blocks.find(rows[t].key);
+    if (b == T.blocks.end()) T.blocks[rows[t].key] = std::make_pair((int)t, 1);
+    else b->second.second++;
+  }
+  T.off1 = upload(o1.data(), sizeof(unsigned) * count);
+  T.off2 = upload(o2.data(), sizeof(unsigned) * count);
+  return group_cache_.emplace(key, std::move(T)).first->second;
+}
+
+// C[oi] (+)= alpha A[ai] B[bi] over the momentum-allowed blocks: rows M (letters
+// of A and C), inner K (A and B), columns N (B and C).  A row tuple of momentum
+// q pairs with inner tuples of A-momentum -q and column tuples of B-momentum s q.
+// Returns false (dense lowering) when a law is unknown.
+bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
+                                const PerProb& A, const std::string& ai, const PerProb& B, const std::string& bi,
+                                bool acc, const std::string& tag, int t_out, int t_a, int t_b) {
+  if (mom_.empty() || t_out < 0 || t_a < 0 || t_b < 0) return false;
+  if (!law_ok_[t_out] || !law_ok_[t_a] || !law_ok_[t_b]) return false;
+  const std::vector<int>&la = law_[t_a], &lb = law_[t_b];
+  auto sa = [&](char c) { return la[ai.find(c)]; };
+  auto sb = [&](char c) { return lb[bi.find(c)]; };
+  const std::string M = filter(ai, bi, oi, false, true);   // A and C
+  const std::string K = filter(ai, bi, oi, true, false);   // A and B
+  const std::string N = filter(bi, ai, oi, false, true);   // B and C
+  int s = -1;
+  bool first = true;
+  for (char c : K) {
+    const int r = sa(c) * sb(c);
+    if (first) {
+      s = r;
+      first = false;
+    } else if (r != s) {
+      return false;
+    }
+  }
+  std::vector<int> sgM, sgK, sgN;
+  for (char c : M) sgM.push_back(sa(c));
+  for (char c : K) sgK.push_back(sa(c));
+  for (char c : N) sgN.push_back(sb(c));
+  const int np = (int)probs_.size();
+  std::vector<SgemmProblem> ps(np);
+  std::vector<SgemmTask> tasks;
+  std::vector<double> pf(np, 0.0);
+  std::vector<int> pinst(np);
+  double flops = 0.0;
+  for (int p = 0; p < np; ++p) {
+    const int inst = probs_[p].inst;
+    const long n = probs_[p].n;
+    if (inst < 0 || inst >= (int)mom_.size() || !mom_[inst]) throw std::runtime_error("momentum labels missing");
+    if (ipow(n, (int)std::max(std::max(ai.size(), bi.size()), oi.size())) >= (1L << 32))
+      throw std::runtime_error("tensor exceeds 2^32 elements: " + tag);
+    const GroupTable& TM = group_table(inst, n, M, ai, oi, sgM);
+    const GroupTable& TK = group_table(inst, n, K, ai, bi, sgK);
+    const GroupTable& TN = group_table(inst, n, N, bi, oi, sgN);
+    SgemmProblem& P = ps[p];
+    P.A = A[p];
+    P.B = B[p];
+    P.C = out[p];
+    P.offAM = (const unsigned*)TM.off1;
+    P.offCM = (const unsigned*)TM.off2;
+    P.offAK = (const unsigned*)TK.off1;
+    P.offBK = (const unsigned*)TK.off2;
+    P.offBN = (const unsigned*)TN.off1;
+    P.offCN = (const unsigned*)TN.off2;
+    P.alpha = alpha;
+    P.beta = acc ? 1.0 : 0.0;
+    P.active = gate_for(dst, p);
+    pinst[p] = inst;
+    const InstMomentum& Mm = *mom_[inst];
+    for (const auto& blk : TM.blocks) {
+      std::vector<int> q(Mm.dims), qk(Mm.dims), qn(Mm.dims);
+      for (int c = 0; c < Mm.dims; ++c) {
+        q[c] = (int)((blk.first >> (21 * c)) & ((1 << 21) - 1)) - (1 << 19);
+        qk[c] = -q[c];
+        qn[c] = s * q[c];
+        if (Mm.modulus[c] > 0) {
+          qk[c] = ((qk[c] % Mm.modulus[c]) + Mm.modulus[c]) % Mm.modulus[c];
+          qn[c] = ((qn[c] % Mm.modulus[c]) + Mm.modulus[c]) % Mm.modulus[c];
+        }
+      }
+      auto nb = TN.blocks.find(pack_momentum(qn));
+      if (nb == TN.blocks.end()) continue;
+      auto kb = TK.blocks.find(pack_momentum(qk));
+      const int k0 = kb == TK.blocks.end() ? 0 : kb->second.first;
+      const int kl = kb == TK.blocks.end() ? 0 : kb->second.second;
+      if (kl == 0 && acc) continue;   // nothing to add; a set writes its zeros
+      const int m0 = blk.second.first, ml = blk.second.second;
+      const int n0 = nb->second.first, nl = nb->second.second;
+      for (int r = 0; r < ml; r += 16)
+        for (int c = 0; c < nl; c += 16)
+          tasks.push_back(SgemmTask{p, m0 + r, std::min(16, ml - r), k0, kl, n0 + c, std::min(16, nl - c)});
+      pf[p] += 2.0 * ml * (double)nl * kl;
+    }
+    flops += pf[p];
+  }
+  Launch L;
+  L.kind = Launch::SGEMM;
+  L.n_prob = np;
+  L.d_desc = upload(ps.data(), sizeof(SgemmProblem) * np);
+  L.n_tasks = (int)tasks.size();
+  L.d_tasks = upload(tasks.data(), sizeof(SgemmTask) * std::max<size_t>(tasks.size(), 1));
+  L.total = (L.n_tasks + 3) / 4;
+  L.flops = flops;
+  if (&dst != &setup_) {
+    L.prob_flops = pf;
+    L.prob_inst = pinst;
+  }
+  L.tag = tag + "(blocked)";
+  dst.push_back(L);
+  return true;
+}
+
+double Executor::sgemm_flops_forward() const {
+  double f = 0.0;
+  for (const Launch& l : fwd_)
+    if (l.kind == Launch::SGEMM) f += l.flops;
+  return f;
+}
+
 // ------------------------------------------------------------------ build
 void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, Binder bind, Scratch* scratch,
                      std::function<double*(int, size_t)> const_alloc, bool want_backward,
@@ -491,6 +730,7 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
   probs_ = probs;
   scratch_ = scratch;
   const_alloc_ = const_alloc;
+  if (!mom_.empty()) infer_laws();
   const int np = (int)probs.size();
   const int nt = (int)prog->t.size();
   std::vector<PerProb> fwd(nt, PerProb(np)), grd(nt, PerProb(np));
@@ -546,7 +786,7 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
   for (const SymOp& o : prog->ops) {
     if (o.setup) continue;
     contract(fwd_, fwd[o.out], o.oi, o.alpha, fwd[o.a], o.ai, cidx(o.a), o.b >= 0 ? &fwd[o.b] : nullptr, o.bi,
-             cidx(o.b), o.accumulate, prog->t[o.out].name, vidx(o.a), vidx(o.b));
+             cidx(o.b), o.accumulate, prog->t[o.out].name, vidx(o.a), vidx(o.b), o.out, o.a, o.b);
     version_[o.out]++;
   }
   if (!want_backward) {
@@ -566,10 +806,10 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
     }
     if (need_grad[o.a])
       contract(bwd_, grd[o.a], o.ai, o.alpha, grd[o.out], o.oi, -1, &fwd[o.b], o.bi, cidx(o.b), true, tag + ":dA",
-               -1, vidx(o.b));
+               -1, vidx(o.b), o.a, o.out, o.b);
     if (need_grad[o.b])
       contract(bwd_, grd[o.b], o.bi, o.alpha, fwd[o.a], o.ai, cidx(o.a), &grd[o.out], o.oi, -1, true, tag + ":dB",
-               vidx(o.a), -1);
+               vidx(o.a), -1, o.b, o.a, o.out);
   }
   dump_plan();
 }
@@ -618,11 +858,11 @@ void Executor::autotune(hipStream_t s) {
 void Executor::dump_plan() const {
   const char* env = std::getenv("FTCC_PLAN_DUMP");
   if (!env || env[0] != '1') return;
-  const char* kinds[] = {"perm", "gemm", "dot", "fill"};
+  const char* kinds[] = {"perm", "gemm", "dot", "fill", "sgemm"};
   const std::pair<const char*, const std::vector<Launch>*> lists[] = {
       {"setup", &setup_}, {"forward", &fwd_}, {"backward", &bwd_}};
   for (const auto& pl : lists) {
-    int counts[4] = {0, 0, 0, 0};
+    int counts[5] = {0, 0, 0, 0, 0};
     double fl = 0.0;
     for (const Launch& l : *pl.second) {
       counts[l.kind]++;
@@ -631,8 +871,8 @@ void Executor::dump_plan() const {
                    pl.first, kinds[l.kind], l.cfg, (int)l.ta, (int)l.tb, l.total, l.splitk_blocks > 0,
                    l.flops * 1e-9, l.tuned_ms, l.tag.c_str());
     }
-    std::fprintf(stderr, "[plan] %s: %d perm, %d gemm, %d dot, %d fill, %.3f GFLOP\n", pl.first, counts[0],
-                 counts[1], counts[2], counts[3], fl * 1e-9);
+    std::fprintf(stderr, "[plan] %s: %d perm, %d gemm, %d dot, %d fill, %d blocked, %.3f GFLOP\n", pl.first,
+                 counts[0], counts[1], counts[2], counts[3], counts[4], fl * 1e-9);
   }
 }
 
@@ -665,6 +905,9 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
         break;
       case Launch::DOT:
         launch_dot((const DotProblem*)l.d_desc, l.n_prob, l.dot_blocks, l.d_partial, s);
+        break;
+      case Launch::SGEMM:
+        launch_sgemm((const SgemmProblem*)l.d_desc, (const SgemmTask*)l.d_tasks, l.n_tasks, s);
         break;
     }
   }

@@ -188,6 +188,32 @@ __global__ void dh_assemble_kernel(int n, const double* occ, const double* wo, c
   out[e] = v;
 }
 
+// Elements of a one-body (rank 2, law k_p = k_q) or two-body (rank 4,
+// k_p + k_q = k_r + k_s) array that are nonzero although momentum forbids them;
+// any such element sets *bad (plain stores of the same value).
+__global__ void momentum_check_kernel(int n, int rank, int dims, const int* __restrict__ labels,
+                                      const int* __restrict__ modulus, const double* __restrict__ x, int* bad) {
+  const long total = rank == 2 ? (long)n * n : (long)n * n * n * n;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+    if (x[e] == 0.0) continue;
+    long r = e;
+    int idx[4];
+    for (int a = rank - 1; a >= 0; --a) {
+      idx[a] = (int)(r % n);
+      r /= n;
+    }
+    bool ok = true;
+    for (int c = 0; c < dims; ++c) {
+      int q = rank == 2 ? labels[idx[0] * dims + c] - labels[idx[1] * dims + c]
+                        : labels[idx[0] * dims + c] + labels[idx[1] * dims + c] - labels[idx[2] * dims + c] -
+                              labels[idx[3] * dims + c];
+      if (modulus[c] > 0) q %= modulus[c];
+      ok = ok && q == 0;
+    }
+    if (!ok) *bad = 1;
+  }
+}
+
 __global__ void zero_u64_kernel(unsigned long long* p, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0ull;
@@ -202,6 +228,9 @@ struct Instance {
   double mu = 0.0, beta = 1.0;
   double *h = nullptr, *eri = nullptr, *eps = nullptr;
   std::vector<double> eps_host;
+  InstMomentum mom;                // dims == 0: no momentum labels
+  int* d_labels = nullptr;         // device copies for the conservation checks
+  int* d_modulus = nullptr;
   double *occ = nullptr, *wo = nullptr, *wv = nullptr, *fock = nullptr;
   double *dn = nullptr, *dwo = nullptr, *dwv = nullptr, *du_raw = nullptr, *u_raw = nullptr;
   std::map<std::string, double*> blk, dblk;
@@ -279,6 +308,9 @@ struct ftcc_ctx {
       fail(FTCC_ENOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed (" + std::to_string(bytes) +
                             " bytes already held)");
     }
+    // every buffer starts zeroed: momentum-blocked contractions write only the
+    // allowed blocks of their outputs and rely on the forbidden elements being 0
+    if (hipMemset(p, 0, nb) != hipSuccess) fail(FTCC_EDEVICE, "hipMemset of a new buffer failed");
     bytes += nb;
     allocs.push_back(p);
     return (double*)p;
@@ -445,6 +477,28 @@ void deriv_setup(ftcc_ctx* c, int i, int which, const double* d_dh, const double
 
 long node_len_of(long n) { return n * n + n * n * n * n; }
 
+// Throws FTCC_EINVAL when a rank-2 or rank-4 array of instance i breaks the
+// instance's momentum conservation.
+void check_momentum(ftcc_ctx* c, int i, const double* x, int rank, const char* what) {
+  Instance& I = c->inst[i];
+  int* d_bad = (int*)c->dalloc(1);   // zeroed
+  hipLaunchKernelGGL(momentum_check_kernel, dim3(1024), dim3(256), 0, c->stream, I.n, rank, I.mom.dims, I.d_labels,
+                     I.d_modulus, x, d_bad);
+  FTCC_HIP(hipGetLastError());
+  int bad = 0;
+  FTCC_HIP(hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  FTCC_HIP(hipStreamSynchronize(c->stream));
+  if (bad)
+    fail(FTCC_EINVAL, std::string(what) + " of instance " + std::to_string(i) +
+                          " has nonzero elements that its momentum labels forbid");
+}
+
+bool momentum_on(const ftcc_ctx* c) {
+  for (const Instance& I : c->inst)
+    if (I.mom.dims == 0) return false;
+  return !c->inst.empty();
+}
+
 // ------------------------------------------------------------------ build
 void build(ftcc_ctx* c) {
   if (c->built) return;
@@ -452,6 +506,18 @@ void build(ftcc_ctx* c) {
     if (!c->inst[i].has_ham) fail(FTCC_ESTATE, "instance " + std::to_string(i) + " has no Hamiltonian");
   const int m = c->m, P = c->P, B = c->B;
   c->prog = build_residual_program();
+  const bool mom = momentum_on(c);
+  if (mom)
+    for (int i = 0; i < B; ++i) {
+      Instance& I = c->inst[i];
+      I.d_labels = (int*)c->dalloc(I.mom.labels.size() / 2 + 1);
+      I.d_modulus = (int*)c->dalloc(I.mom.modulus.size() / 2 + 1);
+      FTCC_HIP(hipMemcpy(I.d_labels, I.mom.labels.data(), sizeof(int) * I.mom.labels.size(), hipMemcpyHostToDevice));
+      FTCC_HIP(
+          hipMemcpy(I.d_modulus, I.mom.modulus.data(), sizeof(int) * I.mom.modulus.size(), hipMemcpyHostToDevice));
+      check_momentum(c, i, I.h, 2, "h");
+      check_momentum(c, i, I.eri, 4, "<pq|rs>");
+    }
   const Program& prog = c->prog;
 
   for (int i = 0; i < B; ++i) {
@@ -701,12 +767,18 @@ void build(ftcc_ctx* c) {
   auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
   auto vcache = [c](size_t count) { return c->dalloc(count); };
   // reuse budget for permuted operand copies: a quarter of the memory still available
-  const size_t budget = (size_t)(c->available() / 4);
+  // (the blocked contractions address their operands in place: no permuted copies)
+  const size_t budget = mom ? 0 : (size_t)(c->available() / 4);
+  std::vector<const InstMomentum*> by_inst;
+  if (mom)
+    for (const Instance& I : c->inst) by_inst.push_back(&I.mom);
   c->ex_main.reset(new Executor());
   c->ex_main->set_gate(c->d_run, c->run_host.data());
+  if (mom) c->ex_main->set_momentum(by_inst);
   c->ex_main->build(&prog, probs, bind_main, &c->scratch, calloc_, true, ugrads, vcache, budget);
   c->ex_main->set_profiler(&c->prof);
   c->ex_d.reset(new Executor());
+  if (mom) c->ex_d->set_momentum(by_inst);
   c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {}, vcache, budget / 2);
   c->ex_d->set_profiler(&c->prof);
   trace_mem(c, "executors");
@@ -1188,6 +1260,26 @@ int ftcc_set_allocator(ftcc_ctx* c, ftcc_alloc_fn alloc, ftcc_free_fn free_fn, v
   });
 }
 
+int ftcc_set_momentum(ftcc_ctx* c, int i, int n, int dims, const int* labels, const int* modulus) {
+  return run_guarded([&] {
+    if (!c || !labels || !modulus) fail(FTCC_EINVAL, "null argument");
+    if (i < 0 || i >= c->B) fail(FTCC_EINVAL, "instance index out of range");
+    if (c->built) fail(FTCC_ESTATE, "momentum labels must be set before the first solve");
+    if (n < 1 || n > 255) fail(FTCC_EINVAL, "n must be 1..255");
+    if (dims < 1 || dims > 3) fail(FTCC_EINVAL, "dims must be 1..3");
+    Instance& I = c->inst[i];
+    if (I.has_ham && I.n != n) fail(FTCC_EINVAL, "n differs from the instance's Hamiltonian");
+    for (int d = 0; d < dims; ++d)
+      if (modulus[d] < 0) fail(FTCC_EINVAL, "modulus must be >= 0");
+    for (long k = 0; k < (long)n * dims; ++k)
+      if (labels[k] <= -(1 << 16) || labels[k] >= (1 << 16)) fail(FTCC_EINVAL, "labels must lie in (-65536, 65536)");
+    I.mom.dims = dims;
+    I.mom.modulus.assign(modulus, modulus + dims);
+    I.mom.labels.assign(labels, labels + (long)n * dims);
+    if (!I.has_ham) I.n = n;
+  });
+}
+
 int ftcc_set_hamiltonian(ftcc_ctx* c, int i, int n, const double* h, const double* eri, const double* eps) {
   return run_guarded([&] {
     if (!c || !h || !eri || !eps) fail(FTCC_EINVAL, "null argument");
@@ -1203,6 +1295,8 @@ int ftcc_set_hamiltonian(ftcc_ctx* c, int i, int n, const double* h, const doubl
       if (!std::isfinite(eps[k])) fail(FTCC_EINVAL, "eps has a non-finite entry");
     for (long k = 0; k < n4; ++k)
       if (!std::isfinite(eri[k])) fail(FTCC_EINVAL, "eri has a non-finite entry");
+    if (I.mom.dims && (long)I.mom.labels.size() != (long)n * I.mom.dims)
+      fail(FTCC_EINVAL, "n differs from the instance's momentum labels");
     if (!I.h) {
       I.n = n;
       I.h = c->dalloc(n2);
@@ -1505,11 +1599,13 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
           FTCC_HIP(hipMalloc((void**)&d_deri[i], sizeof(double) * n4));
           tmp.push_back(d_deri[i]);
           FTCC_HIP(hipMemcpy(d_deri[i], deri_dtheta[i], sizeof(double) * n4, hipMemcpyHostToDevice));
+          if (momentum_on(c)) check_momentum(c, i, d_deri[i], 4, "deri_dtheta");
         }
         if (dh_dtheta && dh_dtheta[i]) {
           FTCC_HIP(hipMalloc((void**)&d_dh[i], sizeof(double) * n2));
           tmp.push_back(d_dh[i]);
           FTCC_HIP(hipMemcpy(d_dh[i], dh_dtheta[i], sizeof(double) * n2, hipMemcpyHostToDevice));
+          if (momentum_on(c)) check_momentum(c, i, d_dh[i], 2, "dh_dtheta");
         }
       }
     }

@@ -73,6 +73,32 @@ constexpr size_t kTailWorkspaceDoubles = (size_t)1024 * 128 * 128;   // 128 MiB
 
 void launch_gemm(int cfg, bool ta, bool tb, const GemmProblem* d_probs, const int* d_prefix, int n_prob,
                  int total_tiles, const GemmTail& tail, hipStream_t s);
+// Momentum-blocked contraction: C[m, n] = alpha * sum_k A[m, k] B[k, n] + beta * C
+// restricted to the blocks allowed by a conserved quantity.  Rows, inner indices
+// and columns of a block are lists of element offsets into the dense operands
+// (the row offset of A plus the inner offset of A addresses A[m, k], and so on),
+// so no operand is permuted.  One task is one 16 x 16 output tile of one block.
+struct SgemmProblem {
+  const double* A;
+  const double* B;
+  double* C;
+  const unsigned* offAM;
+  const unsigned* offAK;
+  const unsigned* offBK;
+  const unsigned* offBN;
+  const unsigned* offCM;
+  const unsigned* offCN;
+  double alpha, beta;
+  const int* active;     // optional run flag (0: skip)
+};
+struct SgemmTask {
+  int prob;
+  int mb, mlen;          // first row (index into offAM / offCM) and rows (<= 16)
+  int kb, klen;          // first inner index (into offAK / offBK) and count
+  int nb, nlen;          // first column (into offBN / offCN) and columns (<= 16)
+};
+void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, hipStream_t s);
+
 void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,
                           hipStream_t s);
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

@@ -272,6 +272,43 @@ __global__ void __launch_bounds__(256) gemm_tail_reduce_kernel(const GemmProblem
   }
 }
 
+// Momentum-blocked tiles: one wave per 16 x 16 output tile; operands are gathered
+// through the block's offset lists straight into MFMA fragments (the blocks are
+// small, so nothing is staged in LDS).  No barriers: waves leave independently.
+__global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restrict__ probs,
+                                                    const SgemmTask* __restrict__ tasks, int n_tasks) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ti = blockIdx.x * 4 + wave;
+  if (ti >= n_tasks) return;
+  const SgemmTask T = tasks[ti];
+  const SgemmProblem& P = probs[T.prob];
+  if (P.active && *P.active == 0) return;
+  const int r = lane & 15, q = lane >> 4;
+  const bool row_ok = r < T.mlen, col_ok = r < T.nlen;
+  const unsigned am = row_ok ? P.offAM[T.mb + r] : 0u;
+  const unsigned bn = col_ok ? P.offBN[T.nb + r] : 0u;
+  double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < T.klen; k0 += 4) {
+    const int k = k0 + q;
+    double a = 0.0, b = 0.0;
+    if (k < T.klen) {
+      if (row_ok) a = P.A[am + P.offAK[T.kb + k]];     // A fragment: row r, inner q
+      if (col_ok) b = P.B[P.offBK[T.kb + k] + bn];     // B fragment: inner q, column r
+    }
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = 4 * i + q, col = r;
+    if (row < T.mlen && col < T.nlen) {
+      double* c = P.C + P.offCM[T.mb + row] + P.offCN[T.nb + col];
+      double v = P.alpha * acc[i];
+      if (P.beta != 0.0) v += P.beta * (*c);
+      *c = v;
+    }
+  }
+}
+
 // C = alpha * sum_s partial[s] + beta * C for split-K problems
 __global__ void splitk_reduce_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ prefix,
                                      int n_prob, int total) {
@@ -498,6 +535,11 @@ void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n
   if (total_blocks <= 0) return;
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(total_blocks), dim3(256), 0, s, d_probs, d_prefix, n_prob,
                      total_blocks);
+}
+
+void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, hipStream_t s) {
+  if (n_tasks <= 0) return;
+  hipLaunchKernelGGL(sgemm_kernel, dim3((n_tasks + 3) / 4), dim3(256), 0, s, d_probs, d_tasks, n_tasks);
 }
 
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

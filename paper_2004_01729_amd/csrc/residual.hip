@@ -50,6 +50,15 @@ Program build_residual_program() {
   P.tensor("S1", 2, T_OUTPUT);
   P.tensor("S2", 4, T_OUTPUT);
   P.tensor("E", 0, T_OUTPUT);
+  // Conservation laws for crystal momentum: an amplitude s_{i..}^{a..} or an
+  // integral <pq|rs> is nonzero only when the momenta of its creation slots sum
+  // to those of its annihilation slots.
+  P.set_law("t1", {+1, -1});
+  P.set_law("t2", {+1, +1, -1, -1});
+  for (const char* u : {"u_oo", "u_ov", "u_vo", "u_vv"}) P.set_law(u, {+1, -1});
+  for (const char* g : {"g_oooo", "g_ooov", "g_oovo", "g_oovv", "g_ovov", "g_ovvo", "g_ovvv", "g_vovv", "g_vvvv",
+                        "g_vvvo", "g_ovoo", "g_vvoo"})
+    P.set_law(g, {+1, +1, -1, -1});
 
   // constant combinations (evaluated once per set of thermal integrals)
   P.set("L", "mnef", 2.0, "g_oovv", "mnef");

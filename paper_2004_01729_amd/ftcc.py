@@ -59,6 +59,7 @@ def library():
         "ftcc_set_stream": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
         "ftcc_set_allocator": (ctypes.c_int, [ctypes.c_void_p, ALLOC_FN, FREE_FN, ctypes.c_void_p]),
         "ftcc_set_hamiltonian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
+        "ftcc_set_momentum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _I, _I]),
         "ftcc_solve_amplitudes": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _I, _I]),
         "ftcc_grand_potential": (ctypes.c_int, [ctypes.c_void_p, _D, _D]),
         "ftcc_get_amplitudes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D]),
@@ -85,7 +86,7 @@ def library():
 def exported_symbols():
     """Names the C header declares (used by the CPU-side load test)."""
     return ["ftcc_default_options", "ftcc_create", "ftcc_destroy", "ftcc_set_stream", "ftcc_set_allocator",
-            "ftcc_set_hamiltonian",
+            "ftcc_set_momentum", "ftcc_set_hamiltonian",
             "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
             "ftcc_get_lambda", "ftcc_response", "ftcc_find_mu", "ftcc_eval_residual", "ftcc_time_residual",
             "ftcc_stats",
@@ -174,6 +175,17 @@ class Context:
         eps = _f64(eps, (n,))
         _check(self.lib.ftcc_set_hamiltonian(self._h, int(inst), n, _ptr(h), _ptr(eri), _ptr(eps)))
         self.sizes[int(inst)] = n
+
+    def set_momentum(self, inst, labels, modulus):
+        """Integer momentum labels (n x dims) and per-component modulus (0 = none)."""
+        lab = np.ascontiguousarray(np.asarray(labels), dtype=np.int32)
+        if lab.ndim == 1:
+            lab = lab.reshape(-1, 1)
+        mod = np.ascontiguousarray(np.asarray(modulus), dtype=np.int32).reshape(-1)
+        if mod.size != lab.shape[1]:
+            raise ValueError("modulus needs one entry per label component")
+        _check(self.lib.ftcc_set_momentum(self._h, int(inst), lab.shape[0], lab.shape[1], lab.ctypes.data_as(_I),
+                                          mod.ctypes.data_as(_I)))
 
     def solve(self, mu, beta, raise_on_status=True):
         mu = _f64(np.broadcast_to(np.asarray(mu, float), (self.B,)))

@@ -1,0 +1,115 @@
+"""Momentum-blocked contractions (ftcc_set_momentum) against the dense oracle
+and against the dense GPU path: the same discrete equations, with the O(n^6)
+contractions restricted to the blocks that crystal momentum allows."""
+import numpy as np
+import pytest
+
+import ftcc_inputs as fi
+from oracle import grid as G, restricted as R, solver as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_01729_amd import ftcc
+    return ftcc
+
+
+def _allowed(s):
+    lab, mod = s.momentum
+    lab = np.asarray(lab)
+    mod = np.asarray(mod)
+
+    def red(x):
+        return np.where(mod > 0, np.mod(x, np.where(mod > 0, mod, 1)), x)
+    d1 = red(lab[:, None, :] - lab[None, :, :])
+    a1 = np.all(d1 == 0, axis=-1)
+    d2 = red(lab[:, None, None, None, :] + lab[None, :, None, None, :] - lab[None, None, :, None, :]
+             - lab[None, None, None, :, :])
+    a2 = np.all(d2 == 0, axis=-1)
+    return a1, a2
+
+
+def _ctx(F, systems, momentum=True, **opt):
+    ctx = F.Context(len(systems), **opt)
+    for i, s in enumerate(systems):
+        if momentum:
+            ctx.set_momentum(i, *s.momentum)
+        ctx.set_hamiltonian(i, s.h, s.eri, s.eps)
+    return ctx
+
+
+@pytest.mark.parametrize("case", ["ueg19", "hubbard6"])
+def test_blocked_residual_matches_oracle(F, case):
+    s = fi.ueg_config(19, 14, 1.0, 0.5) if case == "ueg19" else fi.hubbard_config(L=6, U=4.0, T=1.0)
+    a1, a2 = _allowed(s)
+    t1, t2 = fi.random_amplitudes(s.n, seed=5, scale=0.2)
+    t1, t2 = t1 * a1, t2 * a2
+    print(f"[momentum] residual {case} n={s.n} seed=5", flush=True)
+    ctx = _ctx(F, [s], n_tau=4, nodes_per_panel=4)
+    S1, S2, E = ctx.eval_residual(0, s.mu, s.beta, t1, t2)
+    ctx.close()
+    m = R.RestrictedModel(R.RestrictedIntegrals(s.h, s.eri, s.eps, s.mu, s.beta))
+    R1, R2 = m.residual((t1, t2))
+    Er = m.energy((t1, t2))
+    assert np.abs(S1 - R1).max() < 1e-12 * max(1.0, np.abs(R1).max())
+    assert np.abs(S2 - R2).max() < 1e-12 * max(1.0, np.abs(R2).max())
+    assert abs(E - Er) < 1e-12 * max(1.0, abs(Er))
+    assert np.all(S2[~a2] == 0.0) and np.all(S1[~a1] == 0.0)
+
+
+def test_blocked_forward_adjoint_response_matches_oracle(F):
+    s = fi.hubbard_config(L=6, U=4.0, T=1.0)
+    print("[momentum] hubbard L=6 U=4 T=1 n_tau=8: forward, Lambda, response", flush=True)
+    ctx = _ctx(F, [s], n_tau=8, nodes_per_panel=4, tol=1e-14)
+    ctx.solve(s.mu, s.beta)
+    om, _ = ctx.grand_potential()
+    ctx.lam()
+    r = ctx.response(want_mu=True, want_beta=True, want_h=True, deri_dtheta=[s.eri / 4.0])
+    ctx.close()
+    model = R.RestrictedModel(R.RestrictedIntegrals(s.h, s.eri, s.eps, s.mu, s.beta))
+    gr = G.Grid(s.beta, 2, 4)
+    sol = S.solve(model, gr, tol=1e-14)
+    adj = S.adjoint(model, gr, sol, tol=1e-14)
+    assert abs(om[0] - sol.omega) < 1e-10 * abs(sol.omega)
+    for key, theta, kw in (("mu", "mu", {}), ("beta", "beta", {}), ("theta", "h", dict(deri=s.eri / 4.0))):
+        ref = S.d_omega(model, gr, sol, adj, theta, **kw)
+        assert abs(r[key][0] - ref) < 1e-8 * max(1.0, abs(ref)), key
+    ref_h = S.d_omega_dh(model, gr, sol, adj)
+    assert np.abs(r["h"][0] - ref_h).max() < 1e-8 * max(1.0, np.abs(ref_h).max())
+
+
+def test_blocked_mixed_batch_equals_dense(F):
+    systems = [fi.ueg_config(19, 14, 1.0, 1.0), fi.hubbard_config(L=5, U=3.0, T=0.8),
+               fi.hubbard_config(L=6, U=2.0, T=1.0)]
+    print("[momentum] mixed batch blocked vs dense", [s.n for s in systems], flush=True)
+    out = []
+    for mom in (True, False):
+        ctx = _ctx(F, systems, momentum=mom, n_tau=8, nodes_per_panel=4, tol=1e-13)
+        ctx.solve([s.mu for s in systems], [s.beta for s in systems])
+        om, _ = ctx.grand_potential()
+        ctx.lam()
+        r = ctx.response(want_mu=True, want_beta=True, want_h=True)
+        ctx.close()
+        out.append((om, r))
+    (om_b, r_b), (om_d, r_d) = out
+    assert np.allclose(om_b, om_d, rtol=1e-11, atol=0)
+    assert np.allclose(r_b["mu"], r_d["mu"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(r_b["beta"], r_d["beta"], rtol=1e-10, atol=1e-12)
+    for a, b in zip(r_b["h"], r_d["h"]):
+        assert np.abs(a - b).max() < 1e-10
+
+
+def test_labels_that_break_the_integrals_are_refused(F):
+    s = fi.hubbard_config(L=4, U=2.0, T=1.0)
+    print("[momentum] wrong labels are refused", flush=True)
+    ctx = F.Context(1, n_tau=4, nodes_per_panel=4)
+    ctx.set_momentum(0, np.array([[0], [1], [3], [2]]), [4])   # permuted labels: <pq|rs> breaks them
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    with pytest.raises(F.FTCCError, match="forbid"):
+        ctx.solve(s.mu, s.beta)
+    ctx.close()
