@@ -47,20 +47,32 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm128_ueg57_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_01729_amd", "csrc", "kernels.hip")
 
 
+GEMM_REGION = ("// ------------------------------------------------------------------ helpers",
+               "// Momentum-blocked tiles")
+
+
+def gemm_source_hash():
+    """SHA-256 of the GEMM kernel's source (its tile mapping, the kernel and the
+    tail reduce: the part of kernels.hip between the two markers)."""
+    import hashlib
+    src = open(KERNEL_SOURCE).read()
+    a, b = src.index(GEMM_REGION[0]), src.index(GEMM_REGION[1])
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the dominant GEMM family from the committed
     FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy); None when
-    the kernel source has changed since the counters were taken."""
-    import hashlib
+    the GEMM kernel's source has changed since the counters were taken."""
     import re
     try:
         text = open(TRAFFIC_PROFILE).read()
-        src = open(KERNEL_SOURCE, "rb").read()
-    except OSError:
+        cur = gemm_source_hash()
+    except (OSError, ValueError):
         return None
     b = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+-]+)", text)
-    h = re.search(r"kernels_hip_sha256:\s*([0-9a-f]{64})", text)
-    if not b or not h or hashlib.sha256(src).hexdigest() != h.group(1):
+    h = re.search(r"gemm_source_sha256:\s*([0-9a-f]{64})", text)
+    if not b or not h or cur != h.group(1):
         return None
     return float(b.group(1))
 
@@ -132,7 +144,7 @@ def copy_calibration(reps, nbytes=1 << 30):
                 gbps=2 * nbytes * reps / el / 1e9)
 
 
-def batch_bench(per_instance, group=32):
+def batch_bench(per_instance, group=32, momentum=False, subset="all"):
     """One step (forward + Lambda + response for mu, beta, h) of the mixed batch,
     batched in contexts of `group` instances (electron-gas and ring instances
     interleaved) and optionally per instance."""
@@ -149,6 +161,8 @@ def batch_bench(per_instance, group=32):
     def run(sys_):
         ctx = F.Context(len(sys_), **opts)
         for i, s in enumerate(sys_):
+            if momentum:
+                ctx.set_momentum(i, *s.momentum)
             ctx.set_hamiltonian(i, s.h, s.eri, s.eps)
         t0 = time.perf_counter()
         _, st = ctx.solve([s.mu for s in sys_], [s.beta for s in sys_], raise_on_status=False)
@@ -164,17 +178,20 @@ def batch_bench(per_instance, group=32):
 
     # interleave the two families so that every context mixes large and small instances
     order = [i for pair in zip(range(16), range(16, 32)) for i in pair]
+    if subset == "rings":
+        order = list(range(16, 32))
     groups = [order[k:k + group] for k in range(0, len(order), group)]
     rows = [run([systems[i] for i in g]) for g in groups]
     batched = {k: sum(r[k] for r in rows) for k in ("forward_s", "gradient_s", "total_s", "forward_resid_evals")}
     batched["failed"] = sorted(g[j] for g, r in zip(groups, rows) for j in r["failed"])
     batched["contexts"] = len(groups)
-    out = dict(mode="batch", workload="batch32_ueg57pw_x16_hubbard_L6-14_x16", n_instances=len(systems),
-               n_tau=20, occ_thresh=1e-6, group=group, batched=batched)
+    wl = "batch32_ueg57pw_x16_hubbard_L6-14_x16" if subset == "all" else "batch16_hubbard_L6-14_x16"
+    out = dict(mode="batch", workload=wl, n_instances=len(order),
+               n_tau=20, occ_thresh=1e-6, group=group, momentum_blocked=momentum, batched=batched)
     if per_instance:
-        rows = [run([s]) for s in systems]
+        rows = [run([systems[i]]) for i in order]
         out["per_instance"] = {k: sum(r[k] for r in rows) for k in ("forward_s", "gradient_s", "total_s")}
-        out["per_instance"]["failed"] = [i for i, r in enumerate(rows) if r["failed"]]
+        out["per_instance"]["failed"] = [order[i] for i, r in enumerate(rows) if r["failed"]]
         out["batched_speedup"] = out["per_instance"]["total_s"] / out["batched"]["total_s"]
     return out
 
@@ -233,6 +250,7 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
     ap.add_argument("--group", type=int, default=32)
+    ap.add_argument("--subset", default="all", choices=("all", "rings"))
     ap.add_argument("--momentum", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -249,7 +267,7 @@ def main():
         print(json.dumps(copy_calibration(args.reps)), flush=True)
         return
     if args.mode == "batch":
-        print(json.dumps(batch_bench(args.per_instance, args.group)), flush=True)
+        print(json.dumps(batch_bench(args.per_instance, args.group, args.momentum, args.subset)), flush=True)
         return
     s, opts, cfg = workload(args.workload)
     ctx = F.Context(1, **opts)
@@ -298,13 +316,21 @@ def main():
     om_ = ctx.grand_potential()[0][0]
     t_fd_mu = time.perf_counter() - tf0
     fd_mu = (op - om_) / (2 * d)
+    # Richardson-extrapolated difference (accuracy check only; not in the FD timing)
+    ctx.solve(s.mu + d / 2, s.beta)
+    oph = ctx.grand_potential()[0][0]
+    ctx.solve(s.mu - d / 2, s.beta)
+    omh = ctx.grand_potential()[0][0]
+    fd_mu_rich = (4.0 * (oph - omh) / d - fd_mu) / 3.0
     n_h = s.n * (s.n + 1) // 2
     gradient = dict(adjoint_s=t_grad, forward_s=t_fwd, fd_mu_measured_s=t_fd_mu,
                     fd_mu_beta_s=2 * t_fd_mu, fd_all_params_s_extrapolated=(2 + n_h) * t_fd_mu,
                     n_params=2 + n_h, adjoint_vs_fd_speedup_mu_beta=2 * t_fd_mu / t_grad,
                     adjoint_vs_fd_speedup_all=(2 + n_h) * t_fd_mu / t_grad,
                     dOmega_dmu_adjoint=float(resp["mu"][0]), dOmega_dmu_fd=float(fd_mu),
-                    fd_rel_diff=abs(fd_mu - resp["mu"][0]) / max(1.0, abs(resp["mu"][0])))
+                    fd_rel_diff=abs(fd_mu - resp["mu"][0]) / max(1.0, abs(resp["mu"][0])),
+                    dOmega_dmu_fd_richardson=float(fd_mu_rich),
+                    fd_richardson_rel_diff=abs(fd_mu_rich - resp["mu"][0]) / max(1.0, abs(resp["mu"][0])))
     value = evals / el
     achieved = prof["flops"] / prof["seconds"] if prof["seconds"] > 0 else 0.0
     roofline = {

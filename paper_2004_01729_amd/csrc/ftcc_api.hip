@@ -104,6 +104,17 @@ PanelRule make_rule(int m, int lawson) {
       }
       R.A[x][y] = a;
     }
+  for (int x = 0; x <= m; ++x) {
+    const double cx = (x < m) ? R.c[x] : 1.0;
+    for (int y = 0; y < m; ++y) {
+      double p = cx, f = 1.0;   // c_x^(k+1), k!
+      for (int k = 0; k < m; ++k) {
+        R.gc[x][y][k] = R.lc[y][k] * p * f;
+        p *= cx;
+        f *= (k + 1);
+      }
+    }
+  }
   return R;
 }
 
@@ -982,7 +993,7 @@ void tau_run(ftcc_ctx* c, int mode, int panel) {
     c->tau_shape[key] = std::make_pair((int)ps.size(), total);
   }
   const auto shp = c->tau_shape[key];
-  launch_tau(c->d_rule, mode, it->second.first, it->second.second, shp.first, shp.second, c->stream);
+  launch_tau(c->d_rule, c->m, mode, it->second.first, it->second.second, shp.first, shp.second, c->stream);
   FTCC_HIP(hipGetLastError());
 }
 

@@ -288,6 +288,8 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
   const unsigned am = row_ok ? P.offAM[T.mb + r] : 0u;
   const unsigned bn = col_ok ? P.offBN[T.nb + r] : 0u;
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
+  // unrolled so that the gathers of several k groups are in flight together
+#pragma unroll 4
   for (int k0 = 0; k0 < T.klen; k0 += 4) {
     const int k = k0 + q;
     double a = 0.0, b = 0.0;

@@ -16,6 +16,9 @@ struct PanelRule {
   double b[kMaxNodes];
   double lc[kMaxNodes][kMaxNodes];
   double A[kMaxNodes][kMaxNodes];   // int_0^{c_x} l_y(u) du (Lawson)
+  // gc[x][y][k] = lc[y][k] c_x^(k+1) k!  (x = m: the panel end, c = 1), so that
+  // W_xy = h sum_k gc[x][y][k] phi_{k+1}(-D h c_x)
+  double gc[kMaxNodes + 1][kMaxNodes][kMaxNodes];
 };
 
 enum TauMode {
@@ -47,7 +50,7 @@ struct TauProblem {
 };
 
 // blocks: 1024 elements each, per problem; d_rule is a device copy of the rule
-void launch_tau(const PanelRule* d_rule, int mode, const TauProblem* d_probs, const int* d_prefix, int n_prob,
+void launch_tau(const PanelRule* d_rule, int m, int mode, const TauProblem* d_probs, const int* d_prefix, int n_prob,
                 int total_blocks, hipStream_t s);
 hipError_t init_tau_constants();
 

@@ -29,15 +29,17 @@ hipError_t init_tau_constants() {
   return hipMemcpyToSymbol(HIP_SYMBOL(c_inv_fact), f, sizeof(f));
 }
 
-// phi[k] = phi_k(z) for k = 1..kmax
-__device__ __forceinline__ void phi_all(double z, int kmax, double* phi) {
+// phi[k] = phi_k(z) for k = 1..kmax.  Small |z|: phi_kmax by its Taylor series,
+// then downward phi_k = z phi_{k+1} + 1/k! (stable there: |z| <= 4 and every term
+// of the series is positive for z > 0).
+template <int kmax>
+__device__ __forceinline__ void phi_all(double z, double* phi) {
   if (fabs(z) <= 4.0) {
-    for (int k = 1; k <= kmax; ++k) {
-      double acc = c_inv_fact[k + 34];
+    double acc = c_inv_fact[kmax + 34];
 #pragma unroll 4
-      for (int j = 33; j >= 0; --j) acc = fma(acc, z, c_inv_fact[j + k]);
-      phi[k] = acc;
-    }
+    for (int j = 33; j >= 0; --j) acc = fma(acc, z, c_inv_fact[j + kmax]);
+    phi[kmax] = acc;
+    for (int k = kmax - 1; k >= 1; --k) phi[k] = fma(z, phi[k + 1], c_inv_fact[k]);
   } else {
     double p = expm1(z) / z;
     phi[1] = p;
@@ -48,22 +50,21 @@ __device__ __forceinline__ void phi_all(double z, int kmax, double* phi) {
   }
 }
 
+// Weights of one amplitude for a panel of M nodes (M is a compile-time constant,
+// so the arrays live in registers).
+template <int M>
 struct Weights {
-  double E[kMaxNodes], W[kMaxNodes][kMaxNodes], We[kMaxNodes], Ee;
+  double E[M], W[M][M], We[M], Ee;
 };
 
-// coefficients gx[x][y][k] = lc[y][k] c_x^(k+1) k!  (x = m: the panel end, c = 1)
-__device__ __forceinline__ double gcoef(const PanelRule& R, int x, int y, int k) {
-  const double cx = (x < R.m) ? R.c[x] : 1.0;
-  double p = cx;
-  for (int t = 0; t < k; ++t) p *= cx;
-  return R.lc[y][k] * p / c_inv_fact[k];
-}
-
-__device__ void weights(const PanelRule& R, double D, double h, Weights& w, bool deriv) {
-  const int m = R.m;
-  double phi[kMaxNodes + 1];
+// need_end: also the panel-end row (Ee, We).
+template <int M>
+__device__ void weights(const PanelRule& R, double D, double h, Weights<M>& w, bool deriv, bool need_end) {
+  // R is the rule in global memory (uniform across the grid: scalar loads)
+  constexpr int m = M;
+  double phi[M + 1];
   for (int x = 0; x <= m; ++x) {
+    if (x == m && !need_end) break;
     const double cx = (x < m) ? R.c[x] : 1.0;
     const double z = -D * h * cx;
     double e = exp(z);
@@ -78,11 +79,11 @@ __device__ void weights(const PanelRule& R, double D, double h, Weights& w, bool
       }
       continue;
     }
-    phi_all(z, m, phi);
+    phi_all<M>(z, phi);
     for (int y = 0; y < m; ++y) {
       double acc = 0.0;
       for (int k = 0; k < m; ++k) {
-        const double g = gcoef(R, x, y, k);
+        const double g = R.gc[x][y][k];
         acc += deriv ? g * ((z - k) * phi[k + 1] + c_inv_fact[k]) : g * phi[k + 1];
       }
       if (!deriv) acc *= h;
@@ -117,6 +118,7 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* p, double v) 
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
+template <int M>
 __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ rule, int mode,
                                                   const TauProblem* __restrict__ probs,
                                                   const int* __restrict__ prefix, int n_prob) {
@@ -128,15 +130,15 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
   }
   const TauProblem& P = probs[lo];
   if (P.active && *P.active == 0) return;   // converged instance of a batch: left unchanged
-  const PanelRule R = *rule;
-  const int m = R.m;
+  const PanelRule& R = *rule;
+  constexpr int m = M;
   const long base = (long)(b - prefix[lo]) * 1024;
   double mchg = 0.0, mval = 0.0, acc = 0.0;
   for (int u = 0; u < 4; ++u) {
     const long e = base + u * 256 + threadIdx.x;
     if (e >= P.len) break;
     const double sb = P.sb ? P.sb[e] : 0.0;
-    double Sv[kMaxNodes];
+    double Sv[M];
     bool any = (sb != 0.0);
     for (int y = 0; y < m; ++y) {
       Sv[y] = P.S[y] ? P.S[y][e] : 0.0;
@@ -152,15 +154,15 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
       continue;
     }
     if (mode == TAU_BETA) {
-      double Rv[kMaxNodes];
+      double Rv[M];
       bool anyb = any || (P.lam_a && P.lam_a[e] != 0.0);
       for (int y = 0; y < m; ++y) {
         Rv[y] = P.R[y][e];
         anyb = anyb || (Rv[y] != 0.0);
       }
       if (!anyb) continue;
-      Weights w;
-      weights(R, delta_of(P, e), P.h, w, true);
+      Weights<M> w;
+      weights<M>(R, delta_of(P, e), P.h, w, true, P.lam_a != nullptr);
       for (int x = 0; x < m; ++x) {
         double f = (sb != 0.0) ? -w.E[x] * sb : 0.0;
         for (int y = 0; y < m; ++y)
@@ -189,8 +191,8 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
       }
       continue;
     }
-    Weights w;
-    weights(R, delta_of(P, e), P.h, w, false);
+    Weights<M> w;
+    weights<M>(R, delta_of(P, e), P.h, w, false, mode != TAU_INIT && mode != TAU_STEP);
     if (mode == TAU_INIT) {
       for (int x = 0; x < m; ++x) P.s[x][e] = (sb != 0.0) ? w.E[x] * sb : 0.0;
     } else if (mode == TAU_STEP) {
@@ -249,10 +251,22 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
   }
 }
 
-void launch_tau(const PanelRule* d_rule, int mode, const TauProblem* d_probs, const int* d_prefix, int n_prob,
+void launch_tau(const PanelRule* d_rule, int m, int mode, const TauProblem* d_probs, const int* d_prefix, int n_prob,
                 int total_blocks, hipStream_t s) {
   if (total_blocks <= 0) return;
-  hipLaunchKernelGGL(tau_kernel, dim3(total_blocks), dim3(256), 0, s, d_rule, mode, d_probs, d_prefix, n_prob);
+#define FTCC_TAU(MM)                                                                                              \
+  case MM:                                                                                                        \
+    hipLaunchKernelGGL(tau_kernel<MM>, dim3(total_blocks), dim3(256), 0, s, d_rule, mode, d_probs, d_prefix, n_prob); \
+    break;
+  switch (m) {
+    FTCC_TAU(1)
+    FTCC_TAU(2)
+    FTCC_TAU(3)
+    FTCC_TAU(4)
+    FTCC_TAU(5)
+    FTCC_TAU(6)
+  }
+#undef FTCC_TAU
 }
 
 // ------------------------------------------------------------------ thermal quantities
