@@ -80,15 +80,16 @@ class Program {
 Program build_residual_program();
 
 struct Launch {
-  enum Kind { PERM, GEMM, DOT, FILL, SGEMM } kind = PERM;
+  enum Kind { PERM, GEMM, DOT, FILL, SGEMM, ELEM } kind = PERM;
   int n_prob = 0;
   int total = 0;
   int cfg = 0;
   bool ta = false, tb = false;
   int splitk_blocks = 0;
   int min_k = 0;                    // smallest K of the launch's GEMM problems
-  void* d_tasks = nullptr;          // SGEMM: task list
+  void* d_tasks = nullptr;          // SGEMM / ELEM: task list
   int n_tasks = 0;
+  long long n_elem = 0;             // ELEM: allowed elements
   int dot_blocks = 0;
   void* d_desc = nullptr;
   int* d_prefix = nullptr;
@@ -194,7 +195,9 @@ class Executor {
   void perm(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
             const std::string& yi, double alpha, double beta, const std::vector<const double*>* scale,
             const std::string& tag);
-  void fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag);
+  void fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag, int t_y = -1);
+  bool elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
+                    const std::string& yi, double alpha, double beta, int t_y, int t_x, const std::string& tag);
   PerProb const_permuted(int tensor, const PerProb& X, const std::string& xi, const std::string& yi);
   void* upload(const void* host, size_t bytes);
   void dump_plan() const;

@@ -168,8 +168,14 @@ void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::strin
   dst.push_back(L);
 }
 
-void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag) {
-  // zero fill: the contiguous permute path with alpha = 0 and beta = 0 reads neither X nor Y
+void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag, int t_y) {
+  // zero fill: the contiguous permute path with alpha = 0 and beta = 0 reads neither X nor Y;
+  // with momentum laws only the allowed elements (the others never leave zero)
+  if (rank > 0) {
+    std::string idx;
+    for (int k = 0; k < rank; ++k) idx.push_back((char)('p' + k));
+    if (elem_blocked(dst, Y, idx, Y, idx, 0.0, 0.0, t_y, t_y, tag)) return;
+  }
   const int np = (int)probs_.size();
   std::vector<PermProblem> ps(np);
   std::vector<int> prefix(np);
@@ -285,6 +291,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
   if (!B) {
     for (char c : ai)
       if (!has(oi, c)) throw std::runtime_error("single-operand reduction unsupported: " + tag);
+    if (&dst != &setup_ && elem_blocked(dst, A, ai, out, oi, alpha, beta, t_out, t_a, tag)) return;
     perm(dst, A, ai, out, oi, alpha, beta, nullptr, tag);
     return;
   }
@@ -711,6 +718,72 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
   return true;
 }
 
+// Y[yi] = alpha X[xi] + beta Y over the allowed elements of Y (its law known):
+// Y's letters split into two halves whose momentum blocks q and -q pair up.
+// Returns false (dense lowering) when a law is unknown.
+bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
+                            const std::string& yi, double alpha, double beta, int t_y, int t_x,
+                            const std::string& tag) {
+  if (mom_.empty() || t_y < 0 || t_x < 0 || !law_ok_[t_y] || !law_ok_[t_x] || yi.empty()) return false;
+  const std::vector<int>& ly = law_[t_y];
+  const std::vector<int>& lx = law_[t_x];
+  // the operand's law must describe the same allowed set (equal or opposite signs)
+  int rel = 0;
+  for (size_t a = 0; a < yi.size(); ++a) {
+    const int r = ly[a] * lx[xi.find(yi[a])];
+    if (rel == 0) rel = r;
+    else if (r != rel) return false;
+  }
+  const std::string G1 = yi.substr(0, yi.size() / 2), G2 = yi.substr(yi.size() / 2);
+  std::vector<int> s1, s2;
+  for (size_t a = 0; a < G1.size(); ++a) s1.push_back(ly[a]);
+  for (size_t a = 0; a < G2.size(); ++a) s2.push_back(ly[G1.size() + a]);
+  const int np = (int)probs_.size();
+  std::vector<ElemProblem> ps(np);
+  std::vector<ElemTask> tasks;
+  long long total = 0;
+  for (int p = 0; p < np; ++p) {
+    const int inst = probs_[p].inst;
+    const long n = probs_[p].n;
+    if (ipow(n, (int)yi.size()) >= (1L << 32)) throw std::runtime_error("tensor exceeds 2^32 elements: " + tag);
+    const GroupTable& T1 = group_table(inst, n, G1, xi, yi, s1);
+    const GroupTable& T2 = group_table(inst, n, G2, xi, yi, s2);
+    ElemProblem& P = ps[p];
+    P.X = X[p];
+    P.Y = Y[p];
+    P.ox1 = (const unsigned*)T1.off1;
+    P.oy1 = (const unsigned*)T1.off2;
+    P.ox2 = (const unsigned*)T2.off1;
+    P.oy2 = (const unsigned*)T2.off2;
+    P.alpha = alpha;
+    P.beta = beta;
+    P.active = gate_for(dst, p);
+    const InstMomentum& Mm = *mom_[inst];
+    for (const auto& blk : T1.blocks) {
+      std::vector<int> q(Mm.dims);
+      for (int c = 0; c < Mm.dims; ++c) {
+        q[c] = -((int)((blk.first >> (21 * c)) & ((1 << 21) - 1)) - (1 << 19));
+        if (Mm.modulus[c] > 0) q[c] = ((q[c] % Mm.modulus[c]) + Mm.modulus[c]) % Mm.modulus[c];
+      }
+      auto b2 = T2.blocks.find(pack_momentum(q));
+      if (b2 == T2.blocks.end()) continue;
+      tasks.push_back(ElemTask{total, p, blk.second.first, blk.second.second, b2->second.first, b2->second.second});
+      total += (long long)blk.second.second * b2->second.second;
+    }
+  }
+  Launch L;
+  L.kind = Launch::ELEM;
+  L.n_prob = np;
+  L.d_desc = upload(ps.data(), sizeof(ElemProblem) * np);
+  L.n_tasks = (int)tasks.size();
+  L.d_tasks = upload(tasks.data(), sizeof(ElemTask) * std::max<size_t>(tasks.size(), 1));
+  L.n_elem = total;
+  L.total = (int)std::min<long long>((total + 255) / 256, 1 << 30);
+  L.tag = tag + "(blocked)";
+  dst.push_back(L);
+  return true;
+}
+
 double Executor::sgemm_flops_forward() const {
   double f = 0.0;
   for (const Launch& l : fwd_)
@@ -795,13 +868,16 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
   }
   // zero every gradient buffer except the cotangents of the outputs
   for (int k = 0; k < nt; ++k)
-    if (need_grad[k] && prog->t[k].kind != T_OUTPUT) fill(bwd_, grd[k], prog->t[k].rank, "zero:" + prog->t[k].name);
+    if (need_grad[k] && prog->t[k].kind != T_OUTPUT)
+      fill(bwd_, grd[k], prog->t[k].rank, "zero:" + prog->t[k].name, k);
   for (int i = (int)prog->ops.size() - 1; i >= 0; --i) {
     const SymOp& o = prog->ops[i];
     if (o.setup) continue;
     const std::string tag = "bwd:" + prog->t[o.out].name;
     if (o.b < 0) {
-      if (need_grad[o.a]) contract(bwd_, grd[o.a], o.ai, o.alpha, grd[o.out], o.oi, -1, nullptr, "", -1, true, tag);
+      if (need_grad[o.a])
+        contract(bwd_, grd[o.a], o.ai, o.alpha, grd[o.out], o.oi, -1, nullptr, "", -1, true, tag, -1, -1, o.a, o.out,
+                 -1);
       continue;
     }
     if (need_grad[o.a])
@@ -858,11 +934,11 @@ void Executor::autotune(hipStream_t s) {
 void Executor::dump_plan() const {
   const char* env = std::getenv("FTCC_PLAN_DUMP");
   if (!env || env[0] != '1') return;
-  const char* kinds[] = {"perm", "gemm", "dot", "fill", "sgemm"};
+  const char* kinds[] = {"perm", "gemm", "dot", "fill", "sgemm", "elem"};
   const std::pair<const char*, const std::vector<Launch>*> lists[] = {
       {"setup", &setup_}, {"forward", &fwd_}, {"backward", &bwd_}};
   for (const auto& pl : lists) {
-    int counts[5] = {0, 0, 0, 0, 0};
+    int counts[6] = {0, 0, 0, 0, 0, 0};
     double fl = 0.0;
     for (const Launch& l : *pl.second) {
       counts[l.kind]++;
@@ -871,8 +947,8 @@ void Executor::dump_plan() const {
                    pl.first, kinds[l.kind], l.cfg, (int)l.ta, (int)l.tb, l.total, l.splitk_blocks > 0,
                    l.flops * 1e-9, l.tuned_ms, l.tag.c_str());
     }
-    std::fprintf(stderr, "[plan] %s: %d perm, %d gemm, %d dot, %d fill, %d blocked, %.3f GFLOP\n", pl.first,
-                 counts[0], counts[1], counts[2], counts[3], counts[4], fl * 1e-9);
+    std::fprintf(stderr, "[plan] %s: %d perm, %d gemm, %d dot, %d fill, %d blocked, %d blocked-elem, %.3f GFLOP\n",
+                 pl.first, counts[0], counts[1], counts[2], counts[3], counts[4], counts[5], fl * 1e-9);
   }
 }
 
@@ -908,6 +984,9 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
         break;
       case Launch::SGEMM:
         launch_sgemm((const SgemmProblem*)l.d_desc, (const SgemmTask*)l.d_tasks, l.n_tasks, s);
+        break;
+      case Launch::ELEM:
+        launch_elem((const ElemProblem*)l.d_desc, (const ElemTask*)l.d_tasks, l.n_tasks, l.n_elem, s);
         break;
     }
   }

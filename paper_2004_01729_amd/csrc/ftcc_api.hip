@@ -240,6 +240,8 @@ struct Instance {
   double *h = nullptr, *eri = nullptr, *eps = nullptr;
   std::vector<double> eps_host;
   InstMomentum mom;                // dims == 0: no momentum labels
+  unsigned* d_allowed[2] = {nullptr, nullptr};   // momentum-allowed elements of the t1 / t2 segments
+  long n_allowed[2] = {0, 0};
   int* d_labels = nullptr;         // device copies for the conservation checks
   int* d_modulus = nullptr;
   double *occ = nullptr, *wo = nullptr, *wv = nullptr, *fock = nullptr;
@@ -510,6 +512,53 @@ bool momentum_on(const ftcc_ctx* c) {
   return !c->inst.empty();
 }
 
+// Offsets, in memory order, of the amplitude elements momentum allows:
+// t1[i][a] with k_i = k_a and t2[i][j][a][b] with k_i + k_j = k_a + k_b.
+void allowed_elements(ftcc_ctx* c, int i) {
+  Instance& I = c->inst[i];
+  const int n = I.n, D = I.mom.dims;
+  auto mom = [&](int p, int q, int sign) {
+    std::vector<int> v(D);
+    for (int d = 0; d < D; ++d) {
+      int x = I.mom.labels[(size_t)p * D + d] + sign * (q >= 0 ? I.mom.labels[(size_t)q * D + d] : 0);
+      const int m = I.mom.modulus[d];
+      if (m > 0) x = ((x % m) + m) % m;
+      v[d] = x;
+    }
+    return v;
+  };
+  std::vector<unsigned> l1, l2;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q)
+      if (mom(p, -1, 0) == mom(q, -1, 0)) l1.push_back((unsigned)(p * n + q));
+  std::map<std::vector<int>, std::vector<unsigned>> pairs;   // pair momentum -> offsets a*n+b (ascending)
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) pairs[mom(a, b, +1)].push_back((unsigned)(a * n + b));
+  const unsigned n2 = (unsigned)n * n;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      auto it = pairs.find(mom(p, q, +1));
+      if (it == pairs.end()) continue;
+      const unsigned row = (unsigned)(p * n + q) * n2;
+      for (unsigned ab : it->second) l2.push_back(row + ab);
+    }
+  for (int seg = 0; seg < 2; ++seg) {
+    const std::vector<unsigned>& l = seg ? l2 : l1;
+    I.n_allowed[seg] = (long)l.size();
+    I.d_allowed[seg] = (unsigned*)c->dalloc(l.size() / 2 + 1);
+    if (!l.empty())
+      FTCC_HIP(hipMemcpy(I.d_allowed[seg], l.data(), sizeof(unsigned) * l.size(), hipMemcpyHostToDevice));
+  }
+}
+
+// elements the propagator visits in segment seg (0: t1, 1: t2) of instance i
+long seg_len(const ftcc_ctx* c, int i, int seg) {
+  const Instance& I = c->inst[i];
+  if (I.d_allowed[seg]) return I.n_allowed[seg];
+  const long n2 = (long)I.n * I.n;
+  return seg ? n2 * n2 : n2;
+}
+
 // ------------------------------------------------------------------ build
 void build(ftcc_ctx* c) {
   if (c->built) return;
@@ -528,6 +577,7 @@ void build(ftcc_ctx* c) {
           hipMemcpy(I.d_modulus, I.mom.modulus.data(), sizeof(int) * I.mom.modulus.size(), hipMemcpyHostToDevice));
       check_momentum(c, i, I.h, 2, "h");
       check_momentum(c, i, I.eri, 4, "<pq|rs>");
+      allowed_elements(c, i);
     }
   const Program& prog = c->prog;
 
@@ -710,9 +760,8 @@ void build(ftcc_ctx* c) {
     size_t blocks = 16;
     c->beta_part_off.assign(B, 0);
     for (int i = 0; i < B; ++i) {
-      const long n2 = (long)c->inst[i].n * c->inst[i].n;
       c->beta_part_off[i] = (int)blocks - 16;
-      blocks += (n2 + 1023) / 1024 + (n2 * n2 + 1023) / 1024;
+      blocks += (seg_len(c, i, 0) + 1023) / 1024 + (seg_len(c, i, 1) + 1023) / 1024;
     }
     c->d_partial = c->dalloc(blocks);
   }
@@ -939,7 +988,8 @@ void tau_run(ftcc_ctx* c, int mode, int panel) {
         t.eps = I.eps;
         t.n = (int)n;
         t.rank = seg ? 4 : 2;
-        t.len = seg ? n4 : n2;
+        t.len = seg_len(c, i, seg);
+        t.idx = I.d_allowed[seg];
         t.h = I.beta / c->P;
         t.maxbits = c->d_maxbits + 2 * i;
         t.active = (mode == TAU_STEP || mode == TAU_LSTEP) ? c->d_active + i : nullptr;
@@ -1676,7 +1726,7 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         // partial sums per (instance, segment) -> acc[3]
         for (int i = 0; i < B; ++i) {
           const long n2 = (long)c->inst[i].n * c->inst[i].n;
-          const int nb1 = (int)((n2 + 1023) / 1024), nb2 = (int)((n2 * n2 + 1023) / 1024);
+          const int nb1 = (int)((seg_len(c, i, 0) + 1023) / 1024), nb2 = (int)((seg_len(c, i, 1) + 1023) / 1024);
           launch_sum(c->d_partial + c->beta_part_off[i], nb1 + nb2, c->inst[i].acc + 4, c->stream);
           launch_axpby(1, 1.0 / P, c->inst[i].acc + 4, 1.0, c->inst[i].acc + 3, c->stream);
         }

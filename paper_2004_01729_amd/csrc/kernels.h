@@ -99,6 +99,27 @@ struct SgemmTask {
 };
 void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, hipStream_t s);
 
+// Momentum-blocked elementwise op over the allowed elements of Y only:
+// Y[oy1[u] + oy2[v]] = alpha * X[ox1[u] + ox2[v]] + beta * Y[oy1[u] + oy2[v]] for
+// every pair (u, v) of a matched pair of index-group blocks (alpha = beta = 0:
+// zero fill, nothing read).  Forbidden elements are never touched.
+struct ElemProblem {
+  const double* X;
+  double* Y;
+  const unsigned* ox1;
+  const unsigned* oy1;
+  const unsigned* ox2;
+  const unsigned* oy2;
+  double alpha, beta;
+  const int* active;
+};
+struct ElemTask {
+  long long first;       // elements of the tasks before this one
+  int prob;
+  int u0, ulen, v0, vlen;
+};
+void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, int n_tasks, long long total, hipStream_t s);
+
 void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,
                           hipStream_t s);
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

@@ -311,6 +311,30 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
   }
 }
 
+// One thread per allowed element; the task is found by binary search over the
+// element prefix.
+__global__ void __launch_bounds__(256) elem_kernel(const ElemProblem* __restrict__ probs,
+                                                   const ElemTask* __restrict__ tasks, int n_tasks,
+                                                   long long total) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  int lo = 0, hi = n_tasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tasks[mid].first <= e) lo = mid; else hi = mid - 1;
+  }
+  const ElemTask& T = tasks[lo];
+  const ElemProblem& P = probs[T.prob];
+  if (P.active && *P.active == 0) return;
+  const int r = (int)(e - T.first);
+  const int u = T.u0 + r / T.vlen, v = T.v0 + r % T.vlen;
+  double* y = P.Y + P.oy1[u] + P.oy2[v];
+  double val = 0.0;
+  if (P.alpha != 0.0) val = P.alpha * P.X[P.ox1[u] + P.ox2[v]];
+  if (P.beta != 0.0) val += P.beta * (*y);
+  *y = val;
+}
+
 // C = alpha * sum_s partial[s] + beta * C for split-K problems
 __global__ void splitk_reduce_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ prefix,
                                      int n_prob, int total) {
@@ -542,6 +566,12 @@ void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n
 void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, hipStream_t s) {
   if (n_tasks <= 0) return;
   hipLaunchKernelGGL(sgemm_kernel, dim3((n_tasks + 3) / 4), dim3(256), 0, s, d_probs, d_tasks, n_tasks);
+}
+
+void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, int n_tasks, long long total, hipStream_t s) {
+  if (n_tasks <= 0 || total <= 0) return;
+  hipLaunchKernelGGL(elem_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d_probs, d_tasks, n_tasks,
+                     total);
 }
 
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

@@ -47,6 +47,8 @@ struct TauProblem {
   unsigned long long* maxbits;  // [0] max |change|, [1] max |value| (bit patterns of doubles >= 0)
   const int* active;            // STEP / LSTEP: instance still iterating (nullptr: always)
   double* partial;              // TAU_BETA: one partial sum per block
+  const unsigned* idx;          // optional: the elements to visit (momentum-allowed ones), len of them;
+                                // nullptr: every element 0..len-1
 };
 
 // blocks: 1024 elements each, per problem; d_rule is a device copy of the rule

@@ -135,8 +135,9 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
   const long base = (long)(b - prefix[lo]) * 1024;
   double mchg = 0.0, mval = 0.0, acc = 0.0;
   for (int u = 0; u < 4; ++u) {
-    const long e = base + u * 256 + threadIdx.x;
-    if (e >= P.len) break;
+    const long ei = base + u * 256 + threadIdx.x;
+    if (ei >= P.len) break;
+    const long e = P.idx ? (long)P.idx[ei] : ei;   // element offset in the segment
     const double sb = P.sb ? P.sb[e] : 0.0;
     double Sv[M];
     bool any = (sb != 0.0);
