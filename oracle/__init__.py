@@ -15,4 +15,7 @@ Modules
   restricted  the same terms summed over spin explicitly for a spin-restricted
               reference (closed-shell amplitudes)
   ed          grand-canonical exact diagonalisation (thermal FCI)
+  rk          the differential form (Algorithm alg:diff): explicit RK1/RK2/RK4
+              on a uniform grid, Simpson's rule for Omega, reverse-mode
+              derivatives
 """
