@@ -89,6 +89,8 @@ struct Launch {
   int min_k = 0;                    // smallest K of the launch's GEMM problems
   void* d_tasks = nullptr;          // SGEMM / ELEM: task list
   int n_tasks = 0;
+  void* d_red = nullptr;            // SGEMM: reductions of split inner ranges
+  int n_red = 0;
   long long n_elem = 0;             // ELEM: allowed elements
   int dot_blocks = 0;
   void* d_desc = nullptr;

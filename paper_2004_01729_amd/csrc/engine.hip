@@ -648,6 +648,10 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
   const int np = (int)probs_.size();
   std::vector<SgemmProblem> ps(np);
   std::vector<SgemmTask> tasks;
+  struct Tile {
+    int p, m0, ml, k0, kl, n0, nl;
+  };
+  std::vector<Tile> tiles;
   std::vector<double> pf(np, 0.0);
   std::vector<int> pinst(np);
   double flops = 0.0;
@@ -696,10 +700,35 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
       const int n0 = nb->second.first, nl = nb->second.second;
       for (int r = 0; r < ml; r += 16)
         for (int c = 0; c < nl; c += 16)
-          tasks.push_back(SgemmTask{p, m0 + r, std::min(16, ml - r), k0, kl, n0 + c, std::min(16, nl - c)});
+          tiles.push_back(Tile{p, m0 + r, std::min(16, ml - r), k0, kl, n0 + c, std::min(16, nl - c)});
       pf[p] += 2.0 * ml * (double)nl * kl;
     }
     flops += pf[p];
+  }
+  // A tile with a long inner range would be one wave's long serial chain of
+  // dependent gathers: its range is cut into chunks whose partial tiles a
+  // second kernel adds in order.  The chunk grows (powers of two) until every
+  // partial tile fits the workspace.
+  const long ws_tiles = scratch_ && scratch_->tail_ws ? (long)(kTailWorkspaceDoubles / 256) : 0;
+  int chunk = kSgemmChunk;
+  auto parts_needed = [&](int ch) {
+    long n = 0;
+    for (const Tile& t : tiles)
+      if (t.kl > ch + ch / 2) n += (t.kl + ch - 1) / ch;
+    return n;
+  };
+  while (ws_tiles > 0 && parts_needed(chunk) > ws_tiles) chunk *= 2;
+  std::vector<SgemmReduce> reds;
+  int parts = 0;
+  for (const Tile& t : tiles) {
+    if (ws_tiles == 0 || t.kl <= chunk + chunk / 2) {
+      tasks.push_back(SgemmTask{t.p, t.m0, t.ml, t.k0, t.kl, t.n0, t.nl, -1});
+      continue;
+    }
+    const int first = parts;
+    for (int k = 0; k < t.kl; k += chunk)
+      tasks.push_back(SgemmTask{t.p, t.m0, t.ml, t.k0 + k, std::min(chunk, t.kl - k), t.n0, t.nl, parts++});
+    reds.push_back(SgemmReduce{t.p, t.m0, t.ml, t.n0, t.nl, first, parts - first});
   }
   Launch L;
   L.kind = Launch::SGEMM;
@@ -707,6 +736,11 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
   L.d_desc = upload(ps.data(), sizeof(SgemmProblem) * np);
   L.n_tasks = (int)tasks.size();
   L.d_tasks = upload(tasks.data(), sizeof(SgemmTask) * std::max<size_t>(tasks.size(), 1));
+  L.n_red = (int)reds.size();
+  if (L.n_red > 0) {
+    L.d_red = upload(reds.data(), sizeof(SgemmReduce) * reds.size());
+    L.d_partial = scratch_->tail_ws;
+  }
   L.total = (L.n_tasks + 3) / 4;
   L.flops = flops;
   if (&dst != &setup_) {
@@ -983,7 +1017,8 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
         launch_dot((const DotProblem*)l.d_desc, l.n_prob, l.dot_blocks, l.d_partial, s);
         break;
       case Launch::SGEMM:
-        launch_sgemm((const SgemmProblem*)l.d_desc, (const SgemmTask*)l.d_tasks, l.n_tasks, s);
+        launch_sgemm((const SgemmProblem*)l.d_desc, (const SgemmTask*)l.d_tasks, l.n_tasks, l.d_partial,
+                     (const SgemmReduce*)l.d_red, l.n_red, s);
         break;
       case Launch::ELEM:
         launch_elem((const ElemProblem*)l.d_desc, (const ElemTask*)l.d_tasks, l.n_tasks, l.n_elem, s);

@@ -96,8 +96,21 @@ struct SgemmTask {
   int mb, mlen;          // first row (index into offAM / offCM) and rows (<= 16)
   int kb, klen;          // first inner index (into offAK / offBK) and count
   int nb, nlen;          // first column (into offBN / offCN) and columns (<= 16)
+  int part;              // -1: write C; else the 16 x 16 partial tile goes to ws[part * 256 ...]
 };
-void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, hipStream_t s);
+// A tile whose inner range was split into `count` consecutive partial tiles
+// ws[first .. first + count - 1]: C = alpha * (their sum, in order) + beta * C.
+struct SgemmReduce {
+  int prob;
+  int mb, mlen;
+  int nb, nlen;
+  int first, count;
+};
+// Inner ranges longer than this are split into chunks of kSgemmChunk (or a
+// power-of-two multiple of it when the partial tiles would not fit the workspace).
+constexpr int kSgemmChunk = 64;
+void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, double* ws,
+                  const SgemmReduce* d_red, int n_red, hipStream_t s);
 
 // Momentum-blocked elementwise op over the allowed elements of Y only:
 // Y[oy1[u] + oy2[v]] = alpha * X[ox1[u] + ox2[v]] + beta * Y[oy1[u] + oy2[v]] for

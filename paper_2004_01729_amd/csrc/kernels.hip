@@ -272,32 +272,62 @@ __global__ void __launch_bounds__(256) gemm_tail_reduce_kernel(const GemmProblem
   }
 }
 
-// Momentum-blocked tiles: one wave per 16 x 16 output tile; operands are gathered
-// through the block's offset lists straight into MFMA fragments (the blocks are
-// small, so nothing is staged in LDS).  No barriers: waves leave independently.
+// Momentum-blocked tiles: one wave per 16 x 16 output tile, or per chunk of a
+// long inner range (its partial tile then goes to the workspace and
+// sgemm_reduce_kernel adds the chunks); operands are gathered through the
+// block's offset lists straight into MFMA fragments (the blocks are small, so
+// nothing is staged in LDS).  No barriers: waves leave independently.
 __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restrict__ probs,
-                                                    const SgemmTask* __restrict__ tasks, int n_tasks) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ti = blockIdx.x * 4 + wave;
+                                                    const SgemmTask* __restrict__ tasks, int n_tasks,
+                                                    double* __restrict__ ws) {
+  const int lane = threadIdx.x & 63;
+  // the task index is uniform over the wave: task and problem come in through
+  // scalar loads and their pointers stay in scalar registers
+  const int ti = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (ti >= n_tasks) return;
   const SgemmTask T = tasks[ti];
   const SgemmProblem& P = probs[T.prob];
   if (P.active && *P.active == 0) return;
+  const double* __restrict__ A = P.A;
+  const double* __restrict__ B = P.B;
+  const unsigned* __restrict__ offAK = P.offAK + T.kb;
+  const unsigned* __restrict__ offBK = P.offBK + T.kb;
   const int r = lane & 15, q = lane >> 4;
   const bool row_ok = r < T.mlen, col_ok = r < T.nlen;
   const unsigned am = row_ok ? P.offAM[T.mb + r] : 0u;
   const unsigned bn = col_ok ? P.offBN[T.nb + r] : 0u;
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
-  // unrolled so that the gathers of several k groups are in flight together
-#pragma unroll 4
-  for (int k0 = 0; k0 < T.klen; k0 += 4) {
-    const int k = k0 + q;
-    double a = 0.0, b = 0.0;
-    if (k < T.klen) {
-      if (row_ok) a = P.A[am + P.offAK[T.kb + k]];     // A fragment: row r, inner q
-      if (col_ok) b = P.B[P.offBK[T.kb + k] + bn];     // B fragment: inner q, column r
+  // G groups of 4 inner indices per step: the offset loads of all groups are
+  // issued together, then all operand gathers, then the MFMAs, so one step
+  // waits for two memory latencies instead of two per group.  Loads past the
+  // end of the range read the range's first entry (in bounds) and are zeroed.
+  constexpr int G = 8;
+  for (int k0 = 0; k0 < T.klen; k0 += 4 * G) {
+    unsigned ak[G], bk[G];
+    double a[G], b[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const int k = k0 + 4 * u + q;
+      const int kk = k < T.klen ? k : 0;
+      ak[u] = offAK[kk];
+      bk[u] = offBK[kk];
     }
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const bool ok = k0 + 4 * u + q < T.klen;
+      const double va = A[am + ak[u]];     // A fragment: row r, inner q
+      const double vb = B[bk[u] + bn];     // B fragment: inner q, column r
+      a[u] = (ok && row_ok) ? va : 0.0;
+      b[u] = (ok && col_ok) ? vb : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+  if (T.part >= 0) {   // one chunk of a split inner range: the whole tile, lane-major
+    double* w = ws + (size_t)T.part * 256;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[i * 64 + lane] = acc[i];
+    return;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -307,6 +337,31 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
       double v = P.alpha * acc[i];
       if (P.beta != 0.0) v += P.beta * (*c);
       *c = v;
+    }
+  }
+}
+
+// Sum of the partial tiles of a split inner range, in chunk order (deterministic).
+__global__ void __launch_bounds__(256) sgemm_reduce_kernel(const SgemmProblem* __restrict__ probs,
+                                                           const SgemmReduce* __restrict__ red, int n_red,
+                                                           const double* __restrict__ ws) {
+  const int lane = threadIdx.x & 63;
+  const int ti = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (ti >= n_red) return;
+  const SgemmReduce R = red[ti];
+  const SgemmProblem& P = probs[R.prob];
+  if (P.active && *P.active == 0) return;
+  const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = 4 * i + q, col = r;
+    if (row < R.mlen && col < R.nlen) {
+      double acc = 0.0;
+      for (int c = 0; c < R.count; ++c) acc += ws[(size_t)(R.first + c) * 256 + i * 64 + lane];
+      double* out = P.C + P.offCM[R.mb + row] + P.offCN[R.nb + col];
+      double v = P.alpha * acc;
+      if (P.beta != 0.0) v += P.beta * (*out);
+      *out = v;
     }
   }
 }
@@ -563,9 +618,13 @@ void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n
                      total_blocks);
 }
 
-void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, hipStream_t s) {
+void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_tasks, double* ws,
+                  const SgemmReduce* d_red, int n_red, hipStream_t s) {
   if (n_tasks <= 0) return;
-  hipLaunchKernelGGL(sgemm_kernel, dim3((n_tasks + 3) / 4), dim3(256), 0, s, d_probs, d_tasks, n_tasks);
+  hipLaunchKernelGGL(sgemm_kernel, dim3((n_tasks + 3) / 4), dim3(256), 0, s, d_probs, d_tasks, n_tasks, ws);
+  if (n_red > 0)
+    hipLaunchKernelGGL(sgemm_reduce_kernel, dim3((n_red + 3) / 4), dim3(256), 0, s, d_probs, d_red, n_red,
+                       (const double*)ws);
 }
 
 void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, int n_tasks, long long total, hipStream_t s) {
