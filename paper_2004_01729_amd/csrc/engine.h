@@ -80,7 +80,7 @@ class Program {
 Program build_residual_program();
 
 struct Launch {
-  enum Kind { PERM, GEMM, DOT, FILL, SGEMM, ELEM } kind = PERM;
+  enum Kind { PERM, GEMM, DOT, FILL, SGEMM, ELEM, DOTB } kind = PERM;
   int n_prob = 0;
   int total = 0;
   int cfg = 0;
@@ -198,6 +198,10 @@ class Executor {
             const std::string& yi, double alpha, double beta, const std::vector<const double*>* scale,
             const std::string& tag);
   void fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag, int t_y = -1);
+  // full contraction <A, B> over A's momentum-allowed elements
+  bool dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std::string& ai, const PerProb& B,
+                   const std::string& bi, const PerProb& out, double alpha, double beta, int t_a,
+                   const std::string& tag);
   bool elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
                     const std::string& yi, double alpha, double beta, int t_y, int t_x, const std::string& tag);
   PerProb const_permuted(int tensor, const PerProb& X, const std::string& xi, const std::string& yi);

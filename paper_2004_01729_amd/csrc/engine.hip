@@ -313,6 +313,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
 
   // full contraction -> dot
   if (oi.empty()) {
+    if (&dst != &setup_ && dot_blocked(dst, A, ai, *B, bi, out, alpha, beta, t_a, tag)) return;
     PerProb Bp = *B;
     if (bi != ai) {
       if (b_const >= 0) Bp = const_permuted(b_const, *B, bi, ai);
@@ -818,6 +819,66 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
   return true;
 }
 
+bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std::string& ai, const PerProb& B,
+                           const std::string& bi, const PerProb& out, double alpha, double beta, int t_a,
+                           const std::string& tag) {
+  if (mom_.empty() || t_a < 0 || !law_ok_[t_a] || ai.empty() || !scratch_ || !scratch_->tail_ws) return false;
+  const std::vector<int>& la = law_[t_a];
+  const std::string G1 = ai.substr(0, ai.size() / 2), G2 = ai.substr(ai.size() / 2);
+  const std::vector<int> s1(la.begin(), la.begin() + G1.size()), s2(la.begin() + G1.size(), la.end());
+  const int np = (int)probs_.size();
+  std::vector<DotbProblem> ps(np);
+  std::vector<ElemTask> tasks;
+  long long total = 0;
+  for (int p = 0; p < np; ++p) {
+    const int inst = probs_[p].inst;
+    const long n = probs_[p].n;
+    if (ipow(n, (int)ai.size()) >= (1L << 32)) throw std::runtime_error("tensor exceeds 2^32 elements: " + tag);
+    // A's allowed elements: index groups G1 of momentum q with G2 of momentum -q
+    const GroupTable& T1 = group_table(inst, n, G1, ai, bi, s1);
+    const GroupTable& T2 = group_table(inst, n, G2, ai, bi, s2);
+    DotbProblem& P = ps[p];
+    P.X = A[p];
+    P.Y = B[p];
+    P.ox1 = (const unsigned*)T1.off1;
+    P.oy1 = (const unsigned*)T1.off2;
+    P.ox2 = (const unsigned*)T2.off1;
+    P.oy2 = (const unsigned*)T2.off2;
+    P.out = out[p];
+    P.alpha = alpha;
+    P.beta = beta;
+    P.active = gate_for(dst, p);
+    total = (total + 255) / 256 * 256;     // every problem starts on a block boundary
+    const long long start = total;
+    const InstMomentum& Mm = *mom_[inst];
+    for (const auto& blk : T1.blocks) {
+      std::vector<int> q(Mm.dims);
+      for (int c = 0; c < Mm.dims; ++c) {
+        q[c] = -((int)((blk.first >> (21 * c)) & ((1 << 21) - 1)) - (1 << 19));
+        if (Mm.modulus[c] > 0) q[c] = ((q[c] % Mm.modulus[c]) + Mm.modulus[c]) % Mm.modulus[c];
+      }
+      auto b2 = T2.blocks.find(pack_momentum(q));
+      if (b2 == T2.blocks.end()) continue;
+      tasks.push_back(ElemTask{total, p, blk.second.first, blk.second.second, b2->second.first, b2->second.second});
+      total += (long long)blk.second.second * b2->second.second;
+    }
+    P.first_block = (int)(start / 256);
+    P.n_blocks = (int)((total - start + 255) / 256);
+  }
+  if ((total + 255) / 256 > (long long)kTailWorkspaceDoubles) return false;
+  Launch L;
+  L.kind = Launch::DOTB;
+  L.n_prob = np;
+  L.d_desc = upload(ps.data(), sizeof(DotbProblem) * np);
+  L.n_tasks = (int)tasks.size();
+  L.d_tasks = upload(tasks.data(), sizeof(ElemTask) * std::max<size_t>(tasks.size(), 1));
+  L.n_elem = total;
+  L.d_partial = scratch_->tail_ws;
+  L.tag = tag + "(blocked dot)";
+  dst.push_back(L);
+  return true;
+}
+
 double Executor::sgemm_flops_forward() const {
   double f = 0.0;
   for (const Launch& l : fwd_)
@@ -968,11 +1029,11 @@ void Executor::autotune(hipStream_t s) {
 void Executor::dump_plan() const {
   const char* env = std::getenv("FTCC_PLAN_DUMP");
   if (!env || env[0] != '1') return;
-  const char* kinds[] = {"perm", "gemm", "dot", "fill", "sgemm", "elem"};
+  const char* kinds[] = {"perm", "gemm", "dot", "fill", "sgemm", "elem", "dotb"};
   const std::pair<const char*, const std::vector<Launch>*> lists[] = {
       {"setup", &setup_}, {"forward", &fwd_}, {"backward", &bwd_}};
   for (const auto& pl : lists) {
-    int counts[6] = {0, 0, 0, 0, 0, 0};
+    int counts[7] = {0, 0, 0, 0, 0, 0, 0};
     double fl = 0.0;
     for (const Launch& l : *pl.second) {
       counts[l.kind]++;
@@ -981,8 +1042,10 @@ void Executor::dump_plan() const {
                    pl.first, kinds[l.kind], l.cfg, (int)l.ta, (int)l.tb, l.total, l.splitk_blocks > 0,
                    l.flops * 1e-9, l.tuned_ms, l.tag.c_str());
     }
-    std::fprintf(stderr, "[plan] %s: %d perm, %d gemm, %d dot, %d fill, %d blocked, %d blocked-elem, %.3f GFLOP\n",
-                 pl.first, counts[0], counts[1], counts[2], counts[3], counts[4], counts[5], fl * 1e-9);
+    std::fprintf(stderr,
+                 "[plan] %s: %d perm, %d gemm, %d dot, %d fill, %d blocked, %d blocked-elem, %d blocked-dot, "
+                 "%.3f GFLOP\n",
+                 pl.first, counts[0], counts[1], counts[2], counts[3], counts[4], counts[5], counts[6], fl * 1e-9);
   }
 }
 
@@ -1019,6 +1082,10 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
       case Launch::SGEMM:
         launch_sgemm((const SgemmProblem*)l.d_desc, (const SgemmTask*)l.d_tasks, l.n_tasks, l.d_partial,
                      (const SgemmReduce*)l.d_red, l.n_red, s);
+        break;
+      case Launch::DOTB:
+        launch_dotb((const DotbProblem*)l.d_desc, l.n_prob, (const ElemTask*)l.d_tasks, l.n_tasks, l.n_elem,
+                    l.d_partial, s);
         break;
       case Launch::ELEM:
         launch_elem((const ElemProblem*)l.d_desc, (const ElemTask*)l.d_tasks, l.n_tasks, l.n_elem, s);

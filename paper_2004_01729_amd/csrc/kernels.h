@@ -133,6 +133,26 @@ struct ElemTask {
 };
 void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, int n_tasks, long long total, hipStream_t s);
 
+// Momentum-blocked full contraction: out = alpha * sum X[ox1[u] + ox2[v]] * Y[oy1[u] + oy2[v]]
+// + beta * out over the allowed elements (task list as for elem_kernel).  Each
+// problem's elements start at a 256-element block boundary, so a block belongs
+// to one problem; its partial sums are partial[first_block ..
+// first_block + n_blocks - 1], added in order by the final kernel.
+struct DotbProblem {
+  const double* X;
+  const double* Y;
+  const unsigned* ox1;
+  const unsigned* oy1;
+  const unsigned* ox2;
+  const unsigned* oy2;
+  double* out;
+  double alpha, beta;
+  const int* active;
+  int first_block, n_blocks;
+};
+void launch_dotb(const DotbProblem* d_probs, int n_prob, const ElemTask* d_tasks, int n_tasks, long long total,
+                 double* partial, hipStream_t s);
+
 void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,
                           hipStream_t s);
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

@@ -390,6 +390,49 @@ __global__ void __launch_bounds__(256) elem_kernel(const ElemProblem* __restrict
   *y = val;
 }
 
+// Blocked dot: one thread per allowed element (padding threads add 0), then a
+// block sum per 256 elements; every thread reaches the barrier.
+__global__ void __launch_bounds__(256) dotb_partial_kernel(const DotbProblem* __restrict__ probs,
+                                                           const ElemTask* __restrict__ tasks, int n_tasks,
+                                                           long long total, double* __restrict__ partial) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  double v = 0.0;
+  if (e < total) {
+    int lo = 0, hi = n_tasks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tasks[mid].first <= e) lo = mid; else hi = mid - 1;
+    }
+    const ElemTask& T = tasks[lo];
+    const DotbProblem& P = probs[T.prob];
+    const long long r = e - T.first;
+    if (r >= 0 && r < (long long)T.ulen * T.vlen) {
+      const int u = T.u0 + (int)(r / T.vlen), w = T.v0 + (int)(r % T.vlen);
+      v = P.X[P.ox1[u] + P.ox2[w]] * P.Y[P.oy1[u] + P.oy2[w]];
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void dotb_final_kernel(const DotbProblem* __restrict__ probs, int n_prob, const double* partial) {
+  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pi >= n_prob) return;
+  const DotbProblem& P = probs[pi];
+  if (P.active && *P.active == 0) return;
+  double s = 0.0;
+  for (int b = 0; b < P.n_blocks; ++b) s += partial[P.first_block + b];
+  double v = P.alpha * s;
+  if (P.beta != 0.0) v += P.beta * (*P.out);
+  *P.out = v;
+}
+
 // C = alpha * sum_s partial[s] + beta * C for split-K problems
 __global__ void splitk_reduce_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ prefix,
                                      int n_prob, int total) {
@@ -631,6 +674,17 @@ void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, int n_task
   if (n_tasks <= 0 || total <= 0) return;
   hipLaunchKernelGGL(elem_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d_probs, d_tasks, n_tasks,
                      total);
+}
+
+void launch_dotb(const DotbProblem* d_probs, int n_prob, const ElemTask* d_tasks, int n_tasks, long long total,
+                 double* partial, hipStream_t s) {
+  if (n_prob <= 0) return;
+  const long long blocks = (total + 255) / 256;
+  if (blocks > 0 && n_tasks > 0)
+    hipLaunchKernelGGL(dotb_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_probs, d_tasks, n_tasks, total,
+                       partial);
+  hipLaunchKernelGGL(dotb_final_kernel, dim3((n_prob + 63) / 64), dim3(64), 0, s, d_probs, n_prob,
+                     (const double*)partial);
 }
 
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,
