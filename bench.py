@@ -18,6 +18,7 @@ re-evaluations inside the adjoint and response phases).
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|ueg123|hubbard6|hubbard10]
                        [--no-cpu-baseline] [--mode step|residual|copy|batch] [--reps R]
                        [--per-instance] [--momentum]
+       python bench.py --mode numerr [--dense]
 
 --mode residual times R back-to-back residual evaluations of every node of the
 last panel at the converged amplitudes (kernel throughput alone); --mode copy
@@ -29,6 +30,9 @@ and T, 20 tau points, occupation threshold 1e-6) in one context, and with
 print one JSON line of their own.  --momentum evaluates the contractions over
 their crystal-momentum-allowed blocks only (a different algorithm from the dense
 one the metric's FP64-MFMA share refers to; its line has no GEMM roofline).
+--mode numerr measures the grid-error orders of the differential form (explicit
+RK1 / RK2 / RK4 with Simpson's rule, Table tab:numerr) on the 14-electron gas
+in 33 plane waves at r_s = 4, Theta = 0.125 (momentum-blocked unless --dense).
 """
 from __future__ import annotations
 
@@ -196,6 +200,65 @@ def batch_bench(per_instance, group=32, momentum=False, subset="all"):
     return out
 
 
+def numerr_bench(momentum=True, grids=(20, 40, 80, 160, 320)):
+    """Grid-error orders of the differential form (Table tab:numerr): the 14-electron
+    electron gas in 33 plane waves, r_s = 4, Theta = 0.125, occupation threshold
+    1e-6, marched by RK1 / RK2 / RK4 with Simpson's rule on n_g = 20 .. 320
+    steps; Omega, the internal energy E = Omega + beta dOmega/dbeta + mu N and
+    the entropy S = beta^2 dOmega/dbeta (N = -dOmega/dmu, all at a frozen
+    reference) against the exponential-collocation integral form on 16 panels of
+    6 nodes (checked against 8 panels), with the observed orders
+    log2(err(n) / err(2n))."""
+    import math
+    import ftcc_inputs as fi
+    from paper_2004_01729_amd import ftcc as F
+    s = fi.ueg_config(33, 14, 4.0, 0.125)
+
+    def run(**opt):
+        ctx = F.Context(1, occ_thresh=1e-6, **opt)
+        if momentum:
+            ctx.set_momentum(0, *s.momentum)
+        ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+        t0 = time.perf_counter()
+        _, st = ctx.solve(s.mu, s.beta, raise_on_status=False)
+        if st[0] != 0:
+            ctx.close()
+            return dict(status=int(st[0]), seconds=time.perf_counter() - t0)
+        om, _ = ctx.grand_potential()
+        _, st = ctx.lam(raise_on_status=False)
+        r = ctx.response(want_mu=True, want_beta=True, want_h=False)
+        el = time.perf_counter() - t0
+        ctx.close()
+        n_el = -r["mu"][0]
+        dob = r["beta"][0]
+        return dict(status=int(st[0]), seconds=el, omega=float(om[0]), N=float(n_el),
+                    E=float(om[0] + s.beta * dob + s.mu * n_el), S=float(s.beta ** 2 * dob))
+
+    ref = run(n_tau=96, nodes_per_panel=6, tol=1e-12, max_iter=400)
+    chk = run(n_tau=48, nodes_per_panel=6, tol=1e-12, max_iter=400)
+    out = dict(mode="numerr", workload="ueg_33pw_N14_rs4_theta0.125_thr1e-6", beta=s.beta, mu=s.mu,
+               momentum_blocked=momentum, reference=ref,
+               reference_check={k: chk[k] - ref[k] for k in ("omega", "E", "S") if k in chk and k in ref},
+               methods={})
+    for name, prop in (("rk1", 2), ("rk2", 3), ("rk4", 4)):
+        rows = []
+        for n in grids:
+            r = run(n_tau=n, propagator=prop)
+            if r["status"] == 0:
+                r.update({f"err_{k}": r[k] - ref[k] for k in ("omega", "E", "S")})
+            rows.append(dict(n_g=n, **r))
+            print(f"[numerr] {name} n_g={n} status={r['status']} {r['seconds']:.1f} s", file=sys.stderr, flush=True)
+        orders = {}
+        for k in ("omega", "E", "S"):
+            o = []
+            for a, b in zip(rows, rows[1:]):
+                ea, eb = a.get(f"err_{k}"), b.get(f"err_{k}")
+                o.append(math.log2(abs(ea / eb)) if ea is not None and eb is not None and eb != 0.0 else None)
+            orders[k] = o
+        out["methods"][name] = dict(rows=rows, observed_orders=orders)
+    return out
+
+
 def cpu_baseline(s, budget_s=20.0):
     """The oracle as it stands (spin-summed restricted kernels, numpy/BLAS on
     the host) on a bounded sample: the einsum items of one residual evaluation
@@ -246,12 +309,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ueg57")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch"))
+    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch", "numerr"))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
     ap.add_argument("--group", type=int, default=32)
     ap.add_argument("--subset", default="all", choices=("all", "rings"))
     ap.add_argument("--momentum", action="store_true")
+    ap.add_argument("--dense", action="store_true", help="--mode numerr: dense contractions")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -265,6 +329,9 @@ def main():
         raise SystemExit("no GPU visible")
     if args.mode == "copy":
         print(json.dumps(copy_calibration(args.reps)), flush=True)
+        return
+    if args.mode == "numerr":
+        print(json.dumps(numerr_bench(momentum=not args.dense)), flush=True)
         return
     if args.mode == "batch":
         print(json.dumps(batch_bench(args.per_instance, args.group, args.momentum, args.subset)), flush=True)

@@ -17,6 +17,16 @@
  * interpolated (propagator 1, the paper's G^y_x exp(Delta (tau_x - tau_y))).
  * The implicit panel system is solved by fixed-point (Picard) sweeps.
  *
+ * Differential form (Algorithm alg:diff; propagators 2, 3, 4): the amplitudes
+ * obey ds/dtau = -(Delta s + S[s]) (eqn:smud) from s(0) = 0 and are stepped
+ * across the uniform grid tau_k = k beta / n_tau (k = 0..n_tau) by an explicit
+ * Runge-Kutta method (2: forward Euler, 3: explicit trapezoid (Heun), 4: the
+ * classical fourth-order method); Omega_CC uses Simpson's rule on the same grid
+ * (Section III, Table tab:numerr).  Lambda is the reverse-mode adjoint of the
+ * explicit march, and the response derivatives are those of the discrete
+ * Omega.  No fixed-point iteration is involved (tol, max_iter, diis_depth and
+ * checkpoint do not apply; every grid state is kept).
+ *
  * The reference is spin-restricted: h, <pq|rs> and eps are spatial, amplitudes
  * are closed-shell t1[i][a] = s_{i alpha}^{a alpha} and
  * t2[i][j][a][b] = s_{i alpha, j beta}^{a alpha, b beta}.
@@ -44,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FTCC_ABI_VERSION 2
+#define FTCC_ABI_VERSION 3
 
 #define FTCC_OK 0
 #define FTCC_EINVAL -1      /* bad argument */
@@ -57,9 +67,11 @@ extern "C" {
 typedef struct ftcc_ctx ftcc_ctx;
 
 typedef struct {
-  int n_tau;            /* total imaginary-time nodes n_g (multiple of nodes_per_panel) */
-  int nodes_per_panel;  /* m, 1..6 */
-  int propagator;       /* 0: exponential collocation, 1: integrating factor (Lawson) */
+  int n_tau;            /* total imaginary-time nodes n_g (multiple of nodes_per_panel); for the
+                           differential form the number of steps (even, >= 2) */
+  int nodes_per_panel;  /* m, 1..6 (integral form only) */
+  int propagator;       /* 0: exponential collocation, 1: integrating factor (Lawson),
+                           2 / 3 / 4: differential form with RK1 / RK2 / RK4 and Simpson's rule */
   double occ_thresh;    /* Section III.A: hole slot kept if n_p > thr, particle slot if 1 - n_p > thr */
   double tol;           /* Picard stop: max|change| <= tol * max(1, max|s|) over the panel */
   int max_iter;         /* Picard sweeps per panel */
@@ -136,7 +148,7 @@ int ftcc_solve_amplitudes(ftcc_ctx* ctx, const double* mu, const double* beta, i
 int ftcc_grand_potential(ftcc_ctx* ctx, double* omega, double* parts);
 
 /* Converged amplitudes of node k (0 <= k < n_tau) of one instance: t1 n*n, t2 n^4.
- * Needs checkpoint == 0. */
+ * Needs checkpoint == 0.  Differential form: the grid state s(tau_k), 0 <= k <= n_tau. */
 int ftcc_get_amplitudes(ftcc_ctx* ctx, int inst, int node, double* t1, double* t2);
 
 /* The Lambda adjoint, swept backward in tau panel by panel (stationarity of the
@@ -144,7 +156,9 @@ int ftcc_get_amplitudes(ftcc_ctx* ctx, int inst, int node, double* t1, double* t
  * lambda-tilde the discrete eqn:ltilde).  Same output conventions as solve. */
 int ftcc_lambda(ftcc_ctx* ctx, int* iters_out, int* status_out);
 
-/* Lambda and lambda-tilde of node k of one instance (n*n then n^4 each). */
+/* Lambda and lambda-tilde of node k of one instance (n*n then n^4 each).
+ * Differential form: lam = the cotangent dOmega_CC/ds(tau_k) of the grid state
+ * (0 <= k <= n_tau) and lamt must be NULL. */
 int ftcc_get_lambda(ftcc_ctx* ctx, int inst, int node, double* lam1, double* lam2, double* lamt1, double* lamt2);
 
 /* Derivatives of Omega at a frozen reference (orbitals, eps and the dropped

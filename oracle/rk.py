@@ -131,7 +131,7 @@ def solve(model, beta, n_g, method="rk4"):
 class RKAdjoint:
     kbar: list         # per step: cotangents of the slopes k_j
     hbar: float        # d Omega_CC / d h at fixed thermal integrals
-    sbar0: tuple
+    sbar: list         # per grid point: d Omega_CC / d s_i (total, through every later step)
 
 
 def adjoint(model, sol: RKSolution):
@@ -139,6 +139,8 @@ def adjoint(model, sol: RKSolution):
     h, n_g = sol.h, sol.n_g
     wts = simpson_weights(n_g, h) / sol.beta
     sbar = model.vjp(sol.states[n_g], wts[n_g], (None, None))
+    sbar_all = [None] * (n_g + 1)
+    sbar_all[n_g] = sbar
     kbar_all = [None] * n_g
     hbar = 0.0
     for n in reversed(range(n_g)):
@@ -169,8 +171,9 @@ def adjoint(model, sol: RKSolution):
             new = _axpy(new, 1.0, Ybar[j])
         new = _axpy(new, 1.0, model.vjp(sol.states[n], wts[n], (None, None)))
         sbar = new
+        sbar_all[n] = sbar
         kbar_all[n] = Kbar
-    return RKAdjoint(kbar_all, hbar, sbar)
+    return RKAdjoint(kbar_all, hbar, sbar_all)
 
 
 def _integral_term(model, sol, adj, dints):

@@ -15,6 +15,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "engine.h"
@@ -254,6 +255,8 @@ struct Instance {
   double omega0 = 0, omega1 = 0, omega_cc = 0;
   int iters = 0, status = 0, lam_iters = 0, lam_status = 0;
   double* ugrad_acc[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* rk_tmp[2] = {nullptr, nullptr};   // differential form: reverse-pass temporaries
+  double* rk_hbar = nullptr;                // d Omega_CC / d(step) at fixed integrals
 };
 
 struct ftcc_ctx {
@@ -302,6 +305,14 @@ struct ftcc_ctx {
   long resid_evals = 0, vjp_evals = 0;
   double t_solve = 0.0, t_lambda = 0.0;
   size_t bytes = 0;
+  // differential form (propagator >= 2): explicit Runge-Kutta with m = stages,
+  // P = n_tau steps; tableau a (row-major m x m, strictly lower) and b
+  bool rk = false;
+  std::vector<double> rk_a, rk_b;
+  double* d_rkw = nullptr;                    // [P + 1] Simpson weight / beta of each grid point
+  std::map<std::tuple<int, int, int>, std::pair<RKProblem*, int*>> rk_cache;
+  std::map<std::tuple<int, int, int>, int> rk_blocks;
+  std::map<std::tuple<int, int, int>, DotProblem*> rk_dots;
   ftcc_alloc_fn ualloc = nullptr;   // caller's device memory supplier (or hipMalloc)
   ftcc_free_fn ufree = nullptr;
   void* uuser = nullptr;
@@ -625,7 +636,7 @@ void build(ftcc_ctx* c) {
     for (int k = 0; k < P * m; ++k) I.lam[k] = c->dalloc(len);
     I.abuf.resize(P + 1);
     for (int p = 0; p <= P; ++p) I.abuf[p] = c->dalloc(len);
-    if (!c->opt.checkpoint) {
+    if (!c->opt.checkpoint && !c->rk) {
       I.grid.resize(P * m);
       I.resid.resize(P * m);
       for (int k = 0; k < P * m; ++k) {
@@ -633,7 +644,19 @@ void build(ftcc_ctx* c) {
         I.resid[k] = c->dalloc(len);
       }
     }
-    I.energies.assign(P * m, 0.0);
+    I.energies.assign(c->rk ? P + 1 : P * m, 0.0);
+    if (c->rk) {
+      I.rk_tmp[0] = c->dalloc(len);
+      I.rk_tmp[1] = c->dalloc(len);
+      I.rk_hbar = c->dalloc(1);
+    }
+  }
+  if (c->rk) {
+    // (1/beta) g_k of Simpson's rule on the uniform grid: w_k / (3 n_g), w = 1 4 2 ... 4 1
+    std::vector<double> w(P + 1);
+    for (int k = 0; k <= P; ++k) w[k] = ((k == 0 || k == P) ? 1.0 : (k % 2 ? 4.0 : 2.0)) / (3.0 * P);
+    c->d_rkw = c->dalloc(P + 1);
+    FTCC_HIP(hipMemcpy(c->d_rkw, w.data(), sizeof(double) * (P + 1), hipMemcpyHostToDevice));
   }
   trace_mem(c, "integrals, panel states and Lambda storage");
   // Executor slots per instance: every node of a panel evaluated in one grouped
@@ -646,6 +669,7 @@ void build(ftcc_ctx* c) {
     c->slots = (need > 0.5 * c->available()) ? 1 : m;
     const char* senv = std::getenv("FTCC_NODE_SLOTS");
     if (senv && senv[0] == '1') c->slots = 1;
+    if (c->rk) c->slots = 1;   // the stages of an explicit step are evaluated in turn
   }
   const int SL = c->slots;
   const int nn = B * m;
@@ -965,6 +989,14 @@ void clear_tau_cache(ftcc_ctx* c) {
   }
   c->tau_cache.clear();
   c->tau_shape.clear();
+  for (auto& kv : c->rk_cache) {
+    (void)hipFree(kv.second.first);
+    (void)hipFree(kv.second.second);
+  }
+  c->rk_cache.clear();
+  c->rk_blocks.clear();
+  for (auto& kv : c->rk_dots) (void)hipFree(kv.second);
+  c->rk_dots.clear();
 }
 
 // Descriptor set for the propagator: per instance two segments (t1, t2).
@@ -1226,6 +1258,382 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
   return its;
 }
 
+
+// ------------------------------------------------------------------ differential form
+// Algorithm alg:diff: ds/dtau = -(Delta s + S[s]) (eqn:smud) stepped across the
+// uniform grid tau_k = k h, h = beta / n_g, by an explicit Runge-Kutta method
+// (Section III: RK1, RK2, RK4 with Simpson's rule for Omega_CC).  The executor
+// has one slot per instance; "node" x of the node buffers is stage x of the
+// current step: amp[x] its state Y_x, S[x] its residual, gr[x] its reverse-pass
+// gradient.  Grid states s_k live in sb[k] (k = 0..n_g), their cotangents in
+// abuf[k], and the slope cotangents kbar of step p, stage x in lam[p m + x].
+
+// stage x of every running instance: amp[x] -> S[x], e[x]
+void forward_one(ftcc_ctx* c, int x) {
+  for (int i = 0; i < c->B; ++i)
+    if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+  run_fwd_slots(c);
+  c->resid_evals += n_running(c);
+  for (int i = 0; i < c->B; ++i) {
+    if (!c->run_host[i]) continue;
+    dcopy(c, c->S[i * c->m + x], c->s_S[i], node_len(c, i));
+    dcopy(c, c->e[i * c->m + x], c->s_e[i], 1);
+  }
+}
+
+// reverse pass of stage x (tape recomputed first): cot[x], ebar[x] -> gr[x], ugrad[x]; also S[x]
+void backward_one(ftcc_ctx* c, int x) {
+  for (int i = 0; i < c->B; ++i)
+    if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+  run_fwd_slots(c);
+  c->resid_evals += n_running(c);
+  for (int i = 0; i < c->B; ++i) {
+    if (!c->run_host[i]) continue;
+    const int q = i * c->m + x;
+    dcopy(c, c->S[q], c->s_S[i], node_len(c, i));
+    dcopy(c, c->s_cot[i], c->cot[q], node_len(c, i));
+    dcopy(c, c->s_ebar[i], c->ebar[q], 1);
+  }
+  run_bwd_slots(c);
+  c->vjp_evals += n_running(c);
+  for (int i = 0; i < c->B; ++i) {
+    if (!c->run_host[i]) continue;
+    const int q = i * c->m + x;
+    const long n = c->inst[i].n;
+    dcopy(c, c->gr[q], c->s_gr[i], node_len(c, i));
+    for (int k = 0; k < 4; ++k) dcopy(c, c->ugrad[q][k], c->s_ugrad[i][k], n * n);
+  }
+}
+
+// derivative-integral residual of stage x: amp[x] -> dS[x], de[x]
+void d_forward_one(ftcc_ctx* c, int x) {
+  for (int i = 0; i < c->B; ++i)
+    if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+  c->ex_d->run_forward(c->stream);
+  for (int i = 0; i < c->B; ++i) {
+    if (!c->run_host[i]) continue;
+    dcopy(c, c->dS[i * c->m + x], c->s_dS[i], node_len(c, i));
+    dcopy(c, c->de[i * c->m + x], c->s_de[i], 1);
+  }
+}
+
+struct RKSpec {
+  const double* base = nullptr;
+  double x0 = 0.0;
+  int nst = 0;
+  double coef[kMaxStages] = {0.0, 0.0, 0.0, 0.0};
+  const double* Y[kMaxStages] = {nullptr, nullptr, nullptr, nullptr};
+  const double* S[kMaxStages] = {nullptr, nullptr, nullptr, nullptr};
+  double* out = nullptr;
+};
+
+// out = x0 base + sum_l coef_l (-Delta Y_l + sigma S_l) for every instance (both
+// amplitude segments); descriptors cached under (kind, step, stage) until the
+// next solve.  track: max |out| into maxbits[2 i + 1].
+void rk_combine(ftcc_ctx* c, int kind, int p, int x, double sigma, bool track,
+                const std::function<RKSpec(int)>& spec) {
+  const auto key = std::make_tuple(kind, p, x);
+  auto it = c->rk_cache.find(key);
+  if (it == c->rk_cache.end()) {
+    std::vector<RKProblem> ps;
+    std::vector<int> prefix;
+    int total = 0;
+    for (int i = 0; i < c->B; ++i) {
+      const RKSpec sp = spec(i);
+      const Instance& I = c->inst[i];
+      const long n2 = (long)I.n * I.n;
+      for (int seg = 0; seg < 2; ++seg) {
+        RKProblem r;
+        std::memset(&r, 0, sizeof(r));
+        const long off = seg ? n2 : 0;
+        r.eps = I.eps;
+        r.n = I.n;
+        r.rank = seg ? 4 : 2;
+        r.len = seg_len(c, i, seg);
+        r.idx = I.d_allowed[seg];
+        r.base = sp.base ? sp.base + off : nullptr;
+        r.x0 = sp.x0;
+        r.nst = sp.nst;
+        for (int l = 0; l < sp.nst; ++l) {
+          r.coef[l] = sp.coef[l];
+          r.Y[l] = sp.Y[l] ? sp.Y[l] + off : nullptr;
+          r.S[l] = sp.S[l] ? sp.S[l] + off : nullptr;
+        }
+        r.sigma = sigma;
+        r.out = sp.out + off;
+        r.maxbits = track ? c->d_maxbits + 2 * i + 1 : nullptr;
+        r.active = c->d_run + i;
+        prefix.push_back(total);
+        total += (int)((r.len + 1023) / 1024);
+        ps.push_back(r);
+      }
+    }
+    RKProblem* d_ps = nullptr;
+    int* d_pre = nullptr;
+    FTCC_HIP(hipMalloc((void**)&d_ps, sizeof(RKProblem) * ps.size()));
+    FTCC_HIP(hipMalloc((void**)&d_pre, sizeof(int) * prefix.size()));
+    FTCC_HIP(hipMemcpy(d_ps, ps.data(), sizeof(RKProblem) * ps.size(), hipMemcpyHostToDevice));
+    FTCC_HIP(hipMemcpy(d_pre, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice));
+    it = c->rk_cache.emplace(key, std::make_pair(d_ps, d_pre)).first;
+    c->rk_blocks[key] = total;
+  }
+  launch_rk_combine(it->second.first, it->second.second, 2 * c->B, c->rk_blocks[key], c->stream);
+  FTCC_HIP(hipGetLastError());
+}
+
+// acc_i += <X_i, Y_i> over whole amplitude vectors, one deterministic dot per instance
+void rk_dot(ftcc_ctx* c, int kind, int p, int x, const std::function<std::array<const double*, 3>(int)>& xyz) {
+  for (int i = 0; i < c->B; ++i) {
+    if (!c->run_host[i]) continue;
+    const auto key = std::make_tuple(kind * 65536 + i, p, x);
+    auto it = c->rk_dots.find(key);
+    if (it == c->rk_dots.end()) {
+      const auto v = xyz(i);
+      DotProblem d{};
+      d.X = v[0];
+      d.Y = v[1];
+      d.out = const_cast<double*>(v[2]);
+      d.len = node_len(c, i);
+      d.alpha = 1.0;
+      d.beta = 1.0;
+      DotProblem* dd = nullptr;
+      FTCC_HIP(hipMalloc((void**)&dd, sizeof(DotProblem)));
+      FTCC_HIP(hipMemcpy(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice));
+      it = c->rk_dots.emplace(key, dd).first;
+    }
+    launch_dot(it->second, 1, 64, c->scratch.dot_partial, c->stream);
+  }
+}
+
+double rk_h(const ftcc_ctx* c, int i) { return c->inst[i].beta / c->P; }
+double rk_a(const ftcc_ctx* c, int j, int l) { return c->rk_a[j * c->m + l]; }
+
+// stage state Y_x of step p: sb[p] + h sum_{l<x} a_xl k_l, k_l = -(Delta Y_l + S_l)
+void rk_stage_state(ftcc_ctx* c, int p, int x) {
+  if (x == 0) {
+    for (int i = 0; i < c->B; ++i)
+      if (c->run_host[i]) dcopy(c, c->amp[i * c->m], c->inst[i].sb[p], node_len(c, i));
+    return;
+  }
+  rk_combine(c, 0, p, x, -1.0, false, [c, p, x](int i) {
+    RKSpec sp;
+    sp.base = c->inst[i].sb[p];
+    sp.x0 = 1.0;
+    for (int l = 0; l < x; ++l) {
+      sp.coef[sp.nst] = rk_h(c, i) * rk_a(c, x, l);
+      sp.Y[sp.nst] = c->amp[i * c->m + l];
+      sp.S[sp.nst] = c->S[i * c->m + l];
+      ++sp.nst;
+    }
+    sp.out = c->amp[i * c->m + x];
+    return sp;
+  });
+}
+
+// every stage state of step p with the residuals of stages 0..m-2 (the last
+// stage's residual comes from the tape of its reverse pass, or is evaluated by
+// the caller)
+void rk_recompute_stages(ftcc_ctx* c, int p) {
+  for (int x = 0; x < c->m; ++x) {
+    rk_stage_state(c, p, x);
+    if (x < c->m - 1) forward_one(c, x);
+  }
+}
+
+void set_ebar(ftcc_ctx* c, int x, int grid_point) {
+  for (int i = 0; i < c->B; ++i) {
+    if (!c->run_host[i]) continue;
+    double* e = c->ebar[i * c->m + x];
+    if (grid_point >= 0) dcopy(c, e, c->d_rkw + grid_point, 1);
+    else zero_d(c, e, 1);
+  }
+}
+
+void rk_solve(ftcc_ctx* c, std::vector<int>& status) {
+  const int B = c->B, m = c->m, P = c->P;
+  std::vector<double> ebuf((size_t)B * (P + 1), 0.0);
+  std::vector<bool> ok(B);
+  const auto wall0 = std::chrono::steady_clock::now();
+  auto energy_to_host = [&](int k) {
+    for (int i = 0; i < B; ++i)
+      if (c->run_host[i])
+        FTCC_HIP(hipMemcpyAsync(&ebuf[(size_t)i * (P + 1) + k], c->e[i * m], sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+  };
+  for (int p = 0; p < P; ++p) {
+    for (int i = 0; i < B; ++i) ok[i] = status[i] == 0;
+    set_run(c, ok);
+    for (int x = 0; x < m; ++x) {
+      rk_stage_state(c, p, x);
+      forward_one(c, x);
+      if (x == 0) energy_to_host(p);     // E at the grid point s_p = Y_0
+    }
+    reset_maxbits(c);
+    rk_combine(c, 1, p, 0, -1.0, true, [c, p](int i) {
+      RKSpec sp;
+      sp.base = c->inst[i].sb[p];
+      sp.x0 = 1.0;
+      for (int l = 0; l < c->m; ++l) {
+        sp.coef[sp.nst] = rk_h(c, i) * c->rk_b[l];
+        sp.Y[sp.nst] = c->amp[i * c->m + l];
+        sp.S[sp.nst] = c->S[i * c->m + l];
+        ++sp.nst;
+      }
+      sp.out = c->inst[i].sb[p + 1];
+      return sp;
+    });
+    const std::vector<double> mb = read_maxbits(c);
+    for (int i = 0; i < B; ++i)
+      if (status[i] == 0 && !std::isfinite(mb[2 * i + 1])) status[i] = FTCC_ENONFINITE;
+    trace(c, "forward (Runge-Kutta)", p + 1, P, std::vector<int>(1, m), wall0);
+  }
+  for (int i = 0; i < B; ++i) ok[i] = status[i] == 0;
+  set_run(c, ok);
+  rk_stage_state(c, P, 0);
+  forward_one(c, 0);
+  energy_to_host(P);
+  run_all(c);
+  sync(c);
+  for (int i = 0; i < B; ++i) {
+    Instance& I = c->inst[i];
+    double om = 0.0;
+    for (int k = 0; k <= P; ++k) {
+      I.energies[k] = ebuf[(size_t)i * (P + 1) + k];
+      om += ((k == 0 || k == P) ? 1.0 : (k % 2 ? 4.0 : 2.0)) / (3.0 * P) * I.energies[k];
+    }
+    I.omega_cc = status[i] == 0 ? om : std::nan("");
+    I.iters = P;
+  }
+}
+
+// Reverse-mode sweep: sbar_{n_g} = (g/beta) dE/ds(s_{n_g}); per step p (last first)
+//   kbar_x = h b_x sbar_{p+1} + h sum_{y>x} a_yx Z_y,  Z_y = -Delta kbar_y + J_S(Y_y)^T (-kbar_y)
+//   sbar_p = sbar_{p+1} + sum_x Z_x   (Z_0 carries (g_p/beta) dE/ds(s_p) as well)
+// and the explicit step-length term
+//   hbar += <sbar_{p+1}, sum_x b_x k_x> + sum_{x>0} <Z_x, sum_{l<x} a_xl k_l>.
+void rk_lambda(ftcc_ctx* c, std::vector<int>& status) {
+  const int B = c->B, m = c->m, P = c->P;
+  std::vector<bool> ok(B);
+  for (int i = 0; i < B; ++i) ok[i] = status[i] == 0;
+  set_run(c, ok);
+  for (int i = 0; i < B; ++i) zero_d(c, c->inst[i].rk_hbar, 1);
+  const auto wall0 = std::chrono::steady_clock::now();
+  // final grid point: only the energy term
+  rk_stage_state(c, P, 0);
+  for (int i = 0; i < B; ++i)
+    if (ok[i]) zero_d(c, c->cot[i * m], node_len(c, i));
+  set_ebar(c, 0, P);
+  backward_one(c, 0);
+  for (int i = 0; i < B; ++i)
+    if (ok[i]) dcopy(c, c->inst[i].abuf[P], c->gr[i * m], node_len(c, i));
+  for (int p = P - 1; p >= 0; --p) {
+    rk_recompute_stages(c, p);
+    for (int x = m - 1; x >= 0; --x) {
+      rk_combine(c, 2, p, x, +1.0, false, [c, p, x](int i) {
+        RKSpec sp;
+        const Instance& I = c->inst[i];
+        const double h = rk_h(c, i);
+        sp.base = I.abuf[p + 1];
+        sp.x0 = h * c->rk_b[x];
+        for (int y = x + 1; y < c->m; ++y) {
+          if (rk_a(c, y, x) == 0.0) continue;
+          sp.coef[sp.nst] = h * rk_a(c, y, x);
+          sp.Y[sp.nst] = I.lam[p * c->m + y];
+          sp.S[sp.nst] = c->gr[i * c->m + y];
+          ++sp.nst;
+        }
+        sp.out = I.lam[p * c->m + x];
+        return sp;
+      });
+      rk_combine(c, 7, p, x, 0.0, false, [c, p, x](int i) {   // cotangent of S at the stage: -kbar
+        RKSpec sp;
+        sp.base = c->inst[i].lam[p * c->m + x];
+        sp.x0 = -1.0;
+        sp.out = c->cot[i * c->m + x];
+        return sp;
+      });
+      set_ebar(c, x, x == 0 ? p : -1);
+      backward_one(c, x);
+    }
+    rk_combine(c, 3, p, 0, +1.0, false, [c, p](int i) {
+      RKSpec sp;
+      const Instance& I = c->inst[i];
+      sp.base = I.abuf[p + 1];
+      sp.x0 = 1.0;
+      for (int x = 0; x < c->m; ++x) {
+        sp.coef[sp.nst] = 1.0;
+        sp.Y[sp.nst] = I.lam[p * c->m + x];
+        sp.S[sp.nst] = c->gr[i * c->m + x];
+        ++sp.nst;
+      }
+      sp.out = I.abuf[p];
+      return sp;
+    });
+    // explicit dependence on the step length
+    rk_combine(c, 4, p, 0, -1.0, false, [c](int i) {
+      RKSpec sp;
+      for (int l = 0; l < c->m; ++l) {
+        sp.coef[sp.nst] = c->rk_b[l];
+        sp.Y[sp.nst] = c->amp[i * c->m + l];
+        sp.S[sp.nst] = c->S[i * c->m + l];
+        ++sp.nst;
+      }
+      sp.out = c->inst[i].rk_tmp[0];
+      return sp;
+    });
+    rk_dot(c, 0, p, 0, [c, p](int i) {
+      const Instance& I = c->inst[i];
+      return std::array<const double*, 3>{I.abuf[p + 1], I.rk_tmp[0], I.rk_hbar};
+    });
+    for (int x = 1; x < m; ++x) {
+      rk_combine(c, 5, p, x, -1.0, false, [c, x](int i) {
+        RKSpec sp;
+        for (int l = 0; l < x; ++l) {
+          if (rk_a(c, x, l) == 0.0) continue;
+          sp.coef[sp.nst] = rk_a(c, x, l);
+          sp.Y[sp.nst] = c->amp[i * c->m + l];
+          sp.S[sp.nst] = c->S[i * c->m + l];
+          ++sp.nst;
+        }
+        sp.out = c->inst[i].rk_tmp[0];
+        return sp;
+      });
+      rk_combine(c, 6, p, x, +1.0, false, [c, p, x](int i) {
+        RKSpec sp;
+        const Instance& I = c->inst[i];
+        sp.nst = 1;
+        sp.coef[0] = 1.0;
+        sp.Y[0] = I.lam[p * c->m + x];
+        sp.S[0] = c->gr[i * c->m + x];
+        sp.out = I.rk_tmp[1];
+        return sp;
+      });
+      rk_dot(c, 1, p, x, [c](int i) {
+        const Instance& I = c->inst[i];
+        return std::array<const double*, 3>{I.rk_tmp[1], I.rk_tmp[0], I.rk_hbar};
+      });
+    }
+    if (trace_on()) {
+      sync(c);
+      trace(c, "lambda (Runge-Kutta)", P - p, P, std::vector<int>(1, m), wall0);
+    }
+  }
+  // a reverse pass that produced non-finite cotangents
+  reset_maxbits(c);
+  rk_combine(c, 8, 0, 0, 0.0, true, [c](int i) {
+    RKSpec sp;
+    sp.base = c->inst[i].abuf[0];
+    sp.x0 = 1.0;
+    sp.out = c->inst[i].rk_tmp[1];
+    return sp;
+  });
+  const std::vector<double> mb = read_maxbits(c);
+  for (int i = 0; i < B; ++i) {
+    if (status[i] == 0 && !std::isfinite(mb[2 * i + 1])) status[i] = FTCC_ENONFINITE;
+    c->inst[i].lam_iters = P;
+  }
+  run_all(c);
+}
 }  // namespace
 
 // ------------------------------------------------------------------ ABI
@@ -1254,10 +1662,17 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
     ftcc_options o;
     ftcc_default_options(&o);
     if (opt) o = *opt;
-    if (o.nodes_per_panel < 1 || o.nodes_per_panel > kMaxNodes) fail(FTCC_EINVAL, "nodes_per_panel must be 1..6");
-    if (o.n_tau < o.nodes_per_panel || o.n_tau % o.nodes_per_panel)
-      fail(FTCC_EINVAL, "n_tau must be a positive multiple of nodes_per_panel");
-    if (o.propagator < 0 || o.propagator > 1) fail(FTCC_EINVAL, "propagator must be 0 or 1");
+    if (o.propagator < 0 || o.propagator > 4) fail(FTCC_EINVAL, "propagator must be 0..4");
+    const bool rk = o.propagator >= 2;
+    if (rk) {
+      if (o.n_tau < 2 || o.n_tau % 2) fail(FTCC_EINVAL, "the Runge-Kutta forms need an even n_tau >= 2 (Simpson)");
+      if (o.diis_depth != 0) fail(FTCC_EINVAL, "diis_depth applies to the integral form only");
+    } else {
+      if (o.nodes_per_panel < 1 || o.nodes_per_panel > kMaxNodes)
+        fail(FTCC_EINVAL, "nodes_per_panel must be 1..6");
+      if (o.n_tau < o.nodes_per_panel || o.n_tau % o.nodes_per_panel)
+        fail(FTCC_EINVAL, "n_tau must be a positive multiple of nodes_per_panel");
+    }
     if (!(o.tol > 0.0) || o.max_iter < 1) fail(FTCC_EINVAL, "tol must be > 0 and max_iter >= 1");
     if (!(o.occ_thresh >= 0.0)) fail(FTCC_EINVAL, "occ_thresh must be >= 0");
     if (o.diis_depth < 0 || o.diis_depth == 1 || o.diis_depth > kMaxDiis)
@@ -1275,9 +1690,31 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
     c->device = device;
     c->opt = o;
     c->B = n_instances;
-    c->m = o.nodes_per_panel;
-    c->P = o.n_tau / o.nodes_per_panel;
-    c->rule = make_rule(c->m, o.propagator);
+    if (rk) {
+      // Butcher tableaus: forward Euler, explicit trapezoid (Heun), classical RK4
+      c->rk = true;
+      if (o.propagator == 2) {
+        c->rk_b = {1.0};
+      } else if (o.propagator == 3) {
+        c->rk_b = {0.5, 0.5};
+      } else {
+        c->rk_b = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+      }
+      c->m = (int)c->rk_b.size();
+      c->rk_a.assign(c->m * c->m, 0.0);
+      if (c->m == 2) c->rk_a[1 * 2 + 0] = 1.0;
+      if (c->m == 4) {
+        c->rk_a[1 * 4 + 0] = 0.5;
+        c->rk_a[2 * 4 + 1] = 0.5;
+        c->rk_a[3 * 4 + 2] = 1.0;
+      }
+      c->P = o.n_tau;
+      c->rule = make_rule(c->m, 0);   // unused by the march; keeps the device rule valid
+    } else {
+      c->m = o.nodes_per_panel;
+      c->P = o.n_tau / o.nodes_per_panel;
+      c->rule = make_rule(c->m, o.propagator);
+    }
     c->inst.resize(n_instances);
     FTCC_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
     c->stream = c->own_stream;
@@ -1404,7 +1841,8 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
     std::vector<int> status(B, 0), total(B, 0);
     std::vector<double> ebuf(B * m);
     const auto wall0 = std::chrono::steady_clock::now();
-    for (int p = 0; p < P; ++p) {
+    if (c->rk) rk_solve(c, status);
+    for (int p = 0; p < (c->rk ? 0 : P); ++p) {
       std::vector<int> its = panel_solve(c, p, status);
       for (int i = 0; i < B; ++i) total[i] += its[i];
       for (int i = 0; i < B; ++i) {
@@ -1437,14 +1875,16 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
       FTCC_HIP(hipMemcpy(mf, I.mf, sizeof(mf), hipMemcpyDeviceToHost));
       I.omega0 = mf[0];
       I.omega1 = mf[1];
-      double occ_cc = 0.0;
-      for (int p = 0; p < P; ++p)
-        for (int x = 0; x < m; ++x) occ_cc += c->rule.b[x] / P * I.energies[p * m + x];
-      // an instance whose march failed has no grand potential
-      I.omega_cc = status[i] == 0 ? occ_cc : std::nan("");
-      I.iters = total[i];
+      if (!c->rk) {
+        double occ_cc = 0.0;
+        for (int p = 0; p < P; ++p)
+          for (int x = 0; x < m; ++x) occ_cc += c->rule.b[x] / P * I.energies[p * m + x];
+        // an instance whose march failed has no grand potential
+        I.omega_cc = status[i] == 0 ? occ_cc : std::nan("");
+        I.iters = total[i];
+      }
       I.status = status[i];
-      if (iters_out) iters_out[i] = total[i];
+      if (iters_out) iters_out[i] = I.iters;
       if (status_out) status_out[i] = status[i];
       if (status[i] != 0) any_fail = status[i];
     }
@@ -1478,13 +1918,15 @@ int ftcc_get_amplitudes(ftcc_ctx* c, int i, int k, double* t1, double* t2) {
   return run_guarded([&] {
     if (!c || !t1 || !t2) fail(FTCC_EINVAL, "null argument");
     if (!c->solved) fail(FTCC_ESTATE, "call ftcc_solve_amplitudes first");
-    if (c->opt.checkpoint) fail(FTCC_ESTATE, "amplitudes are not kept with checkpoint = 1");
-    if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
+    if (c->opt.checkpoint && !c->rk) fail(FTCC_ESTATE, "amplitudes are not kept with checkpoint = 1");
+    // differential form: the grid states s(tau_k), k = 0..n_tau
+    if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau + (c->rk ? 1 : 0)) fail(FTCC_EINVAL, "index out of range");
     const long n = c->inst[i].n, n2 = n * n;
     FTCC_HIP(hipSetDevice(c->device));
     sync(c);
-    FTCC_HIP(hipMemcpy(t1, c->inst[i].grid[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
-    FTCC_HIP(hipMemcpy(t2, c->inst[i].grid[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+    const double* src = c->rk ? c->inst[i].sb[k] : c->inst[i].grid[k];
+    FTCC_HIP(hipMemcpy(t1, src, sizeof(double) * n2, hipMemcpyDeviceToHost));
+    FTCC_HIP(hipMemcpy(t2, src + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
   });
 }
 
@@ -1540,7 +1982,11 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
     std::vector<int> total(B, 0), status(B, 0);
     for (int i = 0; i < B; ++i) status[i] = c->inst[i].status;   // a failed forward march has no adjoint
     const auto wall0 = std::chrono::steady_clock::now();
-    for (int p = P - 1; p >= 0; --p) {
+    if (c->rk) {
+      rk_lambda(c, status);
+      for (int i = 0; i < B; ++i) total[i] = P;
+    }
+    for (int p = (c->rk ? -1 : P - 1); p >= 0; --p) {
       const std::vector<int> before = total;
       load_panel(c, p);
       // lambda_x = -(g_x/beta) dE/ds : backward with zero S-cotangent
@@ -1626,6 +2072,17 @@ int ftcc_get_lambda(ftcc_ctx* c, int i, int k, double* l1, double* l2, double* l
   return run_guarded([&] {
     if (!c) fail(FTCC_EINVAL, "null context");
     if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
+    if (c->rk) {
+      // differential form: the cotangent of the grid state s(tau_k), k = 0..n_tau
+      if (i < 0 || i >= c->B || k < 0 || k > c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
+      if (lt1 || lt2) fail(FTCC_EINVAL, "the differential form has no lambda-tilde");
+      const long n = c->inst[i].n, n2 = n * n;
+      FTCC_HIP(hipSetDevice(c->device));
+      sync(c);
+      if (l1) FTCC_HIP(hipMemcpy(l1, c->inst[i].abuf[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
+      if (l2) FTCC_HIP(hipMemcpy(l2, c->inst[i].abuf[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+      return;
+    }
     if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
     const long n = c->inst[i].n, n2 = n * n;
     FTCC_HIP(hipSetDevice(c->device));
@@ -1704,7 +2161,65 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
           launch_axpby(1, c->rule.b[x] / P, c->de[i * m + x], 1.0, c->inst[i].acc + slot, c->stream);
     };
     const auto wall0 = std::chrono::steady_clock::now();
-    for (int p = 0; p < P; ++p) {
+    if (c->rk) {
+      // differential form: every grid point k (energy weight) and every stage of
+      // step k (cotangent -kbar of its residual)
+      std::vector<bool> ok(B);
+      for (int i = 0; i < B; ++i) ok[i] = c->inst[i].status == 0 && c->inst[i].lam_status == 0;
+      set_run(c, ok);
+      for (int k = 0; k <= P; ++k) {
+        const int ns = k < P ? m : 1;
+        const double wk = ((k == 0 || k == P) ? 1.0 : (k % 2 ? 4.0 : 2.0)) / (3.0 * P);
+        if (k < P) rk_recompute_stages(c, k);
+        else rk_stage_state(c, P, 0);
+        for (int x = 0; x < ns; ++x) {
+          if (k < P) {
+            rk_combine(c, 7, k, x, 0.0, false, [c, k, x](int i) {
+              RKSpec sp;
+              sp.base = c->inst[i].lam[k * c->m + x];
+              sp.x0 = -1.0;
+              sp.out = c->cot[i * c->m + x];
+              return sp;
+            });
+          } else {
+            for (int i = 0; i < B; ++i)
+              if (ok[i]) zero_d(c, c->cot[i * m], node_len(c, i));
+          }
+          set_ebar(c, x, x == 0 ? k : -1);
+          if (dO_dh) {
+            backward_one(c, x);
+            for (int i = 0; i < B; ++i) {
+              if (!ok[i]) continue;
+              const long n = c->inst[i].n;
+              for (int q = 0; q < 4; ++q)
+                launch_axpby(n * n, 1.0, c->ugrad[i * m + x][q], 1.0, c->inst[i].ugrad_acc[q], c->stream);
+            }
+          }
+          for (int which = 0; which < 3; ++which) {
+            if (which == 0 && !dO_dmu) continue;
+            if (which == 1 && !dO_dbeta) continue;
+            if (which == 2 && !want_theta) continue;
+            for (int i = 0; i < B; ++i) deriv_setup(c, i, which, d_dh[i], d_deri[i]);
+            c->ex_d->run_setup(c->stream);
+            d_forward_one(c, x);
+            rk_dot(c, 2 + which, k, x, [c, x, which](int i) {
+              return std::array<const double*, 3>{c->cot[i * c->m + x], c->dS[i * c->m + x],
+                                                  c->inst[i].acc + which};
+            });
+            if (x == 0)
+              for (int i = 0; i < B; ++i)
+                if (ok[i]) launch_axpby(1, wk, c->de[i * m], 1.0, c->inst[i].acc + which, c->stream);
+          }
+        }
+        if (trace_on()) {
+          sync(c);
+          trace(c, "response (Runge-Kutta)", k + 1, P + 1, std::vector<int>(1, 0), wall0);
+        }
+      }
+      if (dO_dbeta)
+        for (int i = 0; i < B; ++i) launch_axpby(1, 1.0 / P, c->inst[i].rk_hbar, 0.0, c->inst[i].acc + 3, c->stream);
+    }
+    for (int p = 0; p < (c->rk ? 0 : P); ++p) {
       if (trace_on() && p > 0) {
         sync(c);
         trace(c, "response", p, P, std::vector<int>(1, 0), wall0);

@@ -56,6 +56,35 @@ void launch_tau(const PanelRule* d_rule, int m, int mode, const TauProblem* d_pr
                 int total_blocks, hipStream_t s);
 hipError_t init_tau_constants();
 
+// Explicit Runge-Kutta march of the differential form (Algorithm alg:diff,
+// eqn:smud: ds/dtau = -(Delta s + S[s])) and its reverse: one combination per
+// amplitude segment,
+//   out = x0 * base + sum_l coef[l] * (-Delta * Y_l + sigma * S_l)
+// with Delta the segment's orbital-energy difference.  sigma = -1 makes the
+// terms the slopes k_l = -(Delta Y_l + S_l) (stage states, step end);
+// sigma = +1 the reverse-mode terms -Delta kbar_l + g_l (g the residual VJP).
+// Null base / Y_l / S_l read as zero.  maxbits (optional) receives max |out|.
+constexpr int kMaxStages = 4;
+struct RKProblem {
+  const double* eps;
+  int n;
+  int rank;                      // 2 or 4
+  long len;                      // elements to visit
+  const unsigned* idx;           // optional allowed-element list (len entries)
+  const double* base;
+  double x0;
+  int nst;
+  double coef[kMaxStages];
+  const double* Y[kMaxStages];
+  const double* S[kMaxStages];
+  double sigma;
+  double* out;
+  unsigned long long* maxbits;
+  const int* active;             // instance runs (nullptr: always)
+};
+// blocks: 1024 elements each, per problem
+void launch_rk_combine(const RKProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks, hipStream_t s);
+
 // Thermal quantities of one instance.
 struct ThermalProblem {
   int n;

@@ -92,11 +92,12 @@ __device__ void weights(const PanelRule& R, double D, double h, Weights<M>& w, b
   }
 }
 
-__device__ __forceinline__ double delta_of(const TauProblem& P, long e) {
-  const int n = P.n;
-  if (P.rank == 2) {
+// orbital-energy difference of element e of a t1 (rank 2, [i][a]) or t2
+// (rank 4, [i][j][a][b]) segment
+__device__ __forceinline__ double seg_delta(const double* eps, int n, int rank, long e) {
+  if (rank == 2) {
     const int a = (int)(e % n), i = (int)(e / n);
-    return P.eps[a] - P.eps[i];
+    return eps[a] - eps[i];
   }
   const int b = (int)(e % n);
   long r = e / n;
@@ -104,8 +105,10 @@ __device__ __forceinline__ double delta_of(const TauProblem& P, long e) {
   r /= n;
   const int j = (int)(r % n);
   const int i = (int)(r / n);
-  return P.eps[a] + P.eps[b] - P.eps[i] - P.eps[j];
+  return eps[a] + eps[b] - eps[i] - eps[j];
 }
+
+__device__ __forceinline__ double delta_of(const TauProblem& P, long e) { return seg_delta(P.eps, P.n, P.rank, e); }
 
 // max that propagates NaN as +infinity (fmax would drop it)
 __device__ __forceinline__ double nan_max(double a, double b) {
@@ -268,6 +271,51 @@ void launch_tau(const PanelRule* d_rule, int m, int mode, const TauProblem* d_pr
     FTCC_TAU(6)
   }
 #undef FTCC_TAU
+}
+
+// Runge-Kutta combinations (differential form, Algorithm alg:diff):
+//   out = x0 * base + sum_l coef[l] * (-Delta Y_l + sigma S_l)
+// over the (allowed) elements of one segment.  One block covers 1024 elements.
+__global__ void __launch_bounds__(256) rk_combine_kernel(const RKProblem* __restrict__ probs,
+                                                         const int* __restrict__ prefix, int n_prob) {
+  int lo = 0, hi = n_prob - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const RKProblem& P = probs[lo];
+  if (P.active && *P.active == 0) return;   // uniform per block, before the barrier
+  const long first = (long)(b - prefix[lo]) * 1024;
+  double vmax = 0.0;
+  for (int u = 0; u < 4; ++u) {
+    const long ei = first + u * 256 + threadIdx.x;
+    if (ei >= P.len) break;
+    const long e = P.idx ? (long)P.idx[ei] : ei;
+    const double d = seg_delta(P.eps, P.n, P.rank, e);
+    double v = P.base ? P.x0 * P.base[e] : 0.0;
+    for (int l = 0; l < P.nst; ++l) {
+      const double y = P.Y[l] ? P.Y[l][e] : 0.0;
+      const double sv = P.S[l] ? P.S[l][e] : 0.0;
+      v += P.coef[l] * (-d * y + P.sigma * sv);
+    }
+    P.out[e] = v;
+    vmax = nan_max(vmax, fabs(v));
+  }
+  if (!P.maxbits) return;   // uniform per launch problem
+  __shared__ double red[256];
+  red[threadIdx.x] = vmax;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = nan_max(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomic_max_pos(P.maxbits, red[0]);
+}
+
+void launch_rk_combine(const RKProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(rk_combine_kernel, dim3(total_blocks), dim3(256), 0, s, d_probs, d_prefix, n_prob);
 }
 
 // ------------------------------------------------------------------ thermal quantities

@@ -1,0 +1,145 @@
+"""Differential form (Algorithm alg:diff: explicit RK1 / RK2 / RK4 with
+Simpson's rule, propagators 2 / 3 / 4) on the GPU against the FP64 oracle:
+Omega, every grid state, every state cotangent of the reverse pass and the
+response derivatives, element by element on the same inputs."""
+import numpy as np
+import pytest
+
+import ftcc_inputs as fi
+from oracle import restricted as R, rk as K
+
+pytestmark = pytest.mark.gpu
+
+PROP = {"rk1": 2, "rk2": 3, "rk4": 4}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_01729_amd import ftcc
+    return ftcc
+
+
+def _model(s):
+    return R.RestrictedModel(R.RestrictedIntegrals(s.h, s.eri, s.eps, s.mu, s.beta))
+
+
+def _close(a, b, tol):
+    return np.abs(a - b).max() <= tol * max(1.0, np.abs(b).max())
+
+
+def _run(F, systems, method, n_g, momentum=False, theta_dirs=None):
+    ctx = F.Context(len(systems), n_tau=n_g, propagator=PROP[method])
+    for i, s in enumerate(systems):
+        if momentum:
+            ctx.set_momentum(i, *s.momentum)
+        ctx.set_hamiltonian(i, s.h, s.eri, s.eps)
+    ctx.solve([s.mu for s in systems], [s.beta for s in systems])
+    om, parts = ctx.grand_potential()
+    states = [[ctx.amplitudes(i, k) for k in range(n_g + 1)] for i in range(len(systems))]
+    ctx.lam()
+    cots = [[ctx.get_lambda(i, k, tilde=False)[:2] for k in range(n_g + 1)] for i in range(len(systems))]
+    r = ctx.response(want_mu=True, want_beta=True, want_h=True, deri_dtheta=theta_dirs)
+    ctx.close()
+    return om, parts, states, cots, r
+
+
+def _sym(x):
+    # the t2 cotangent is fixed only on the symmetric subspace t2[ijab] = t2[jiba]
+    # the amplitudes live in; two correct restricted formulations may differ by a
+    # component orthogonal to it, which never enters a derivative
+    return 0.5 * (x + x.transpose(1, 0, 3, 2))
+
+
+def _check(s, method, n_g, i, om, parts, states, cots, r, theta=None):
+    model = _model(s)
+    sol = K.solve(model, s.beta, n_g, method)
+    adj = K.adjoint(model, sol)
+    assert abs(parts[i, 2] - sol.omega_cc) <= 1e-10 * max(1e-3, abs(sol.omega_cc))
+    assert abs(om[i] - sol.omega) <= 1e-10 * abs(sol.omega)
+    for k in range(n_g + 1):
+        assert _close(states[i][k][0], sol.states[k][0], 1e-8) and _close(states[i][k][1], sol.states[k][1], 1e-8), k
+        assert _close(cots[i][k][0], adj.sbar[k][0], 1e-8), k
+        assert _close(_sym(cots[i][k][1]), _sym(adj.sbar[k][1]), 1e-8), k
+    for key, th, kw in (("mu", "mu", {}), ("beta", "beta", {})):
+        ref = K.d_omega(model, sol, adj, th, **kw)
+        assert abs(r[key][i] - ref) <= 1e-8 * max(1.0, abs(ref)), key
+    if theta is not None:
+        ref = K.d_omega(model, sol, adj, "h", deri=theta)
+        assert abs(r["theta"][i] - ref) <= 1e-8 * max(1.0, abs(ref))
+    gh = K.d_omega_dh(model, sol, adj)
+    assert _close(r["h"][i], gh, 1e-8)
+
+
+@pytest.mark.parametrize("method", ["rk1", "rk2", "rk4"])
+def test_rk_hubbard_matches_oracle(F, method):
+    s = fi.hubbard_config(L=4, U=2.0, T=1.0)
+    print(f"[rk] hubbard L=4 U=2 T=1 {method} n_g=8", flush=True)
+    out = _run(F, [s], method, 8, theta_dirs=[s.eri / 2.0])
+    _check(s, method, 8, 0, *out, theta=s.eri / 2.0)
+
+
+def test_rk4_random_hamiltonian_several_tiles(F):
+    """n = 11 random real Hamiltonian (not Hartree-Fock, no symmetry blocks): the
+    contractions span several tiles with ragged edges."""
+    h, eri, eps = fi.random_hamiltonian(11, seed=4, scale=0.05)
+    s = fi.System("random11", h, eri, eps, 0.1, 1.0)
+    print("[rk] random n=11 beta=1 rk4 n_g=8", flush=True)
+    out = _run(F, [s], "rk4", 8)
+    _check(s, "rk4", 8, 0, *out)
+
+
+def test_rk4_divergent_march_reports_status(F):
+    """The same Hamiltonian at beta = 2 with 6 steps: the explicit march diverges
+    (the oracle's amplitudes overflow too); the instance reports FTCC_ENONFINITE
+    and Omega = NaN while a good instance of the same batch is unaffected."""
+    h, eri, eps = fi.random_hamiltonian(11, seed=4, scale=0.05)
+    bad = fi.System("random11", h, eri, eps, 0.1, 2.0)
+    good = fi.hubbard_config(L=4, U=2.0, T=1.0)
+    model = _model(bad)
+    with pytest.raises(FloatingPointError):
+        K.solve(model, bad.beta, 6, "rk4")
+    print("[rk] divergent random n=11 beta=2 rk4 n_g=6 + hubbard L=4", flush=True)
+    ctx = F.Context(2, n_tau=6, propagator=4)
+    for i, s in enumerate((bad, good)):
+        ctx.set_hamiltonian(i, s.h, s.eri, s.eps)
+    _, st = ctx.solve([bad.mu, good.mu], [bad.beta, good.beta], raise_on_status=False)
+    om, _ = ctx.grand_potential()
+    ctx.close()
+    assert st[0] == F.ENONFINITE and np.isnan(om[0])
+    ref = K.solve(_model(good), good.beta, 6, "rk4")
+    assert st[1] == 0 and abs(om[1] - ref.omega) <= 1e-10 * abs(ref.omega)
+
+
+def test_rk4_batch_of_two_sizes(F):
+    a = fi.hubbard_config(L=3, U=3.0, T=0.5)
+    b = fi.hubbard_config(L=5, U=1.5, T=1.0)
+    print("[rk] batch hubbard L=3 + L=5 rk4 n_g=6", flush=True)
+    out = _run(F, [a, b], "rk4", 6)
+    for i, s in enumerate((a, b)):
+        _check(s, "rk4", 6, i, *out)
+
+
+def test_rk4_momentum_blocked_matches_oracle(F):
+    s = fi.hubbard_config(L=6, U=4.0, T=1.0)
+    print("[rk] momentum-blocked hubbard L=6 rk4 n_g=4", flush=True)
+    out = _run(F, [s], "rk4", 4, momentum=True)
+    _check(s, "rk4", 4, 0, *out)
+
+
+def test_rk_option_errors(F):
+    for kw in (dict(n_tau=7, propagator=4), dict(n_tau=8, propagator=4, diis_depth=3), dict(n_tau=8, propagator=5)):
+        with pytest.raises(F.FTCCError):
+            F.Context(1, **kw)
+    s = fi.hubbard_config(L=2, U=1.0, T=1.0)
+    ctx = F.Context(1, n_tau=4, propagator=3)
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    ctx.solve(s.mu, s.beta)
+    ctx.lam()
+    with pytest.raises(F.FTCCError):
+        ctx.get_lambda(0, 0, tilde=True)
+    with pytest.raises(F.FTCCError):
+        ctx.amplitudes(0, 5)
+    ctx.close()
