@@ -19,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|ueg
                        [--no-cpu-baseline] [--mode step|residual|copy|batch] [--reps R]
                        [--per-instance] [--momentum]
        python bench.py --mode numerr [--dense]
+       python bench.py --mode afm
 
 --mode residual times R back-to-back residual evaluations of every node of the
 last panel at the converged amplitudes (kernel throughput alone); --mode copy
@@ -33,6 +34,9 @@ one the metric's FP64-MFMA share refers to; its line has no GEMM roofline).
 --mode numerr measures the grid-error orders of the differential form (explicit
 RK1 / RK2 / RK4 with Simpson's rule, Table tab:numerr) on the 14-electron gas
 in 33 plane waves at r_s = 4, Theta = 0.125 (momentum-blocked unless --dense).
+--mode afm runs the 32-site half-filled ring with Neel and UHF references in
+spin orbitals (U = 2, 4, 8; T = 0.25 .. 2): Omega, E, S and the staggered
+magnetisation per site.
 """
 from __future__ import annotations
 
@@ -259,6 +263,48 @@ def numerr_bench(momentum=True, grids=(20, 40, 80, 160, 320)):
     return out
 
 
+def afm_bench(L=32, Us=(2.0, 4.0, 8.0), Ts=(0.25, 0.5, 1.0, 2.0), n_tau=24):
+    """Broken-symmetry references of the half-filled ring (Section IV.A: 32 sites,
+    Neel-state and zero-temperature UHF references, mu = U/2): per site the grand
+    potential, the energy E = Omega + beta dOmega/dbeta + mu N, the entropy
+    S = beta^2 dOmega/dbeta and the staggered magnetisation of the response
+    density dOmega/dh (frozen orbitals), in spin orbitals with S_z-blocked
+    contractions; 24 tau points (6 panels x 4)."""
+    import numpy as np
+    import ftcc_inputs as fi
+    from paper_2004_01729_amd import ftcc as F
+    rows = []
+    for ref in ("neel", "uhf"):
+        for U in Us:
+            for T in Ts:
+                s = fi.hubbard_unrestricted(L=L, U=U, T=T, reference=ref)
+                ctx = F.Context(1, spin_orbital=1, n_tau=n_tau, nodes_per_panel=4, tol=1e-11, max_iter=300)
+                ctx.set_momentum(0, *s.momentum)
+                ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+                t0 = time.perf_counter()
+                _, st = ctx.solve(s.mu, s.beta, raise_on_status=False)
+                row = dict(reference=ref, U=U, T=T, status=int(st[0]))
+                if st[0] == 0:
+                    om, _ = ctx.grand_potential()
+                    _, st2 = ctx.lam(raise_on_status=False)
+                    r = ctx.response(want_mu=True, want_beta=True, want_h=True)
+                    n_el = -r["mu"][0]
+                    C = s.meta["C"]
+                    d = np.diag(C @ r["h"][0] @ C.T)
+                    sign = np.array([(-1.0) ** i for i in range(L)])
+                    row.update(status=int(st2[0]), omega_per_site=float(om[0]) / L, N_per_site=float(n_el) / L,
+                               E_per_site=float(om[0] + s.beta * r["beta"][0] + s.mu * n_el) / L,
+                               S_per_site=float(s.beta ** 2 * r["beta"][0]) / L,
+                               m_staggered=float(sign @ (d[:L] - d[L:])) / L)
+                row["seconds"] = time.perf_counter() - t0
+                ctx.close()
+                rows.append(row)
+                print(f"[afm] {ref} U={U:g} T={T:g} status={row['status']} {row['seconds']:.1f} s",
+                      file=sys.stderr, flush=True)
+    return dict(mode="afm", workload=f"hubbard_ring_L{L}_half_filling_spin_orbitals", n_spin_orbitals=2 * L,
+                n_tau=n_tau, rows=rows)
+
+
 def cpu_baseline(s, budget_s=20.0):
     """The oracle as it stands (spin-summed restricted kernels, numpy/BLAS on
     the host) on a bounded sample: the einsum items of one residual evaluation
@@ -309,7 +355,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ueg57")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch", "numerr"))
+    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch", "numerr", "afm"))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
     ap.add_argument("--group", type=int, default=32)
@@ -329,6 +375,9 @@ def main():
         raise SystemExit("no GPU visible")
     if args.mode == "copy":
         print(json.dumps(copy_calibration(args.reps)), flush=True)
+        return
+    if args.mode == "afm":
+        print(json.dumps(afm_bench()), flush=True)
         return
     if args.mode == "numerr":
         print(json.dumps(numerr_bench(momentum=not args.dense)), flush=True)

@@ -33,7 +33,8 @@ from scipy.special import expit
 __all__ = [
     "System", "hubbard_ring", "ueg_plane_waves", "ueg_shell_basis",
     "restricted_thermal_hf", "hubbard_config", "ueg_config", "batched_configs",
-    "random_amplitudes", "random_hamiltonian",
+    "random_amplitudes", "random_hamiltonian", "hubbard_site_basis", "hubbard_unrestricted",
+    "antisymmetric_amplitudes",
 ]
 
 
@@ -204,6 +205,86 @@ def batched_configs(seed=0, n_pw=57):
         T = float(rng.uniform(0.1, 2.0))
         out.append(("hubbard", dict(L=6 + (i % 9), U=U, T=T)))
     return out
+
+
+# ------------------------------------------- unrestricted (spin-orbital) rings
+def hubbard_site_basis(L: int, t: float, U: float):
+    """Periodic ring in the site basis: hopping matrix h (L x L) and the
+    spin-orbital on-site interaction.  Spin orbitals are ordered (alpha sites,
+    beta sites); <p q|r s> = U when p, r are one site with one spin and q, s the
+    same site with the other spin (U n_up n_dn), zero otherwise."""
+    h = np.zeros((L, L))
+    for i in range(L):
+        h[i, (i + 1) % L] += -t
+        h[(i + 1) % L, i] += -t
+    N = 2 * L
+    eri = np.zeros((N, N, N, N))
+    for i in range(L):
+        a, b = i, L + i
+        eri[a, b, a, b] = U
+        eri[b, a, b, a] = U
+    return h, eri
+
+
+def _rotate_spin_orbital(h_site, eri_site, Ca, Cb):
+    """Spin-orbital h and <pq|rs> in the orbitals C_alpha, C_beta (columns)."""
+    L = h_site.shape[0]
+    C = np.zeros((2 * L, 2 * L))
+    C[:L, :L] = Ca
+    C[L:, L:] = Cb
+    hs = np.kron(np.eye(2), h_site)
+    h = C.T @ hs @ C
+    eri = np.einsum("pqrs,pa,qb,rc,sd->abcd", eri_site, C, C, C, C, optimize=True)
+    return h, eri, C
+
+
+def hubbard_unrestricted(L=4, t=1.0, U=4.0, T=1.0, reference="uhf", mu=None, tol=1e-12, max_iter=5000):
+    """Half-filled periodic ring with a broken-spin-symmetry reference (Section IV.A:
+    Neel state or zero-temperature UHF; in both the reference energies are the
+    diagonal of the zero-temperature Fock matrix).
+
+    reference="neel": site orbitals, alpha electrons on even sites and beta on odd
+    ones, eps_{i sigma} = U n_{i, -sigma}.  reference="uhf": the zero-temperature
+    unrestricted Hartree-Fock orbitals with L/2 electrons of each spin (iterated
+    from the Neel density), eps = their orbital energies.  Returns a spin-orbital
+    System (n = 2L) whose meta holds the orbital coefficients `C` (site-spin x
+    orbital), spin labels for the conservation of S_z and the sites."""
+    beta = 1.0 / T
+    mu = U / 2.0 if mu is None else mu
+    hsite, esite = hubbard_site_basis(L, t, U)
+    na = np.array([1.0 if i % 2 == 0 else 0.0 for i in range(L)])
+    nb = 1.0 - na
+    if reference == "neel":
+        Ca = Cb = np.eye(L)
+        eps_a, eps_b = U * nb, U * na
+    elif reference == "uhf":
+        for _ in range(max_iter):
+            ea, Ca = np.linalg.eigh(hsite + np.diag(U * nb))
+            eb, Cb = np.linalg.eigh(hsite + np.diag(U * na))
+            new_a = (Ca[:, :L // 2] ** 2).sum(1)
+            new_b = (Cb[:, :L // 2] ** 2).sum(1)
+            if max(np.abs(new_a - na).max(), np.abs(new_b - nb).max()) < tol:
+                break
+            na, nb = 0.5 * (na + new_a), 0.5 * (nb + new_b)
+        eps_a, eps_b = ea, eb
+    else:
+        raise ValueError(reference)
+    h, eri, C = _rotate_spin_orbital(hsite, esite, Ca, Cb)
+    eps = np.concatenate([eps_a, eps_b])
+    spin = np.concatenate([np.zeros(L, int), np.ones(L, int)]).reshape(-1, 1)
+    return System(f"hubbard_L{L}_U{U:g}_T{T:g}_{reference}", h, eri, eps, mu, beta,
+                  dict(L=L, t=t, U=U, T=T, reference=reference, C=C,
+                       momentum_labels=spin, momentum_modulus=[0]))
+
+
+def antisymmetric_amplitudes(n, seed=0, scale=0.05):
+    """Random spin-orbital amplitudes with t2 antisymmetric in (i, j) and (a, b)."""
+    rng = np.random.default_rng(seed)
+    t1 = rng.standard_normal((n, n)) * scale
+    t2 = rng.standard_normal((n, n, n, n)) * scale
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    return t1, 0.5 * t2
 
 
 # ------------------------------------------------------------ random tensors

@@ -27,9 +27,11 @@
  * Omega.  No fixed-point iteration is involved (tol, max_iter, diis_depth and
  * checkpoint do not apply; every grid state is kept).
  *
- * The reference is spin-restricted: h, <pq|rs> and eps are spatial, amplitudes
- * are closed-shell t1[i][a] = s_{i alpha}^{a alpha} and
- * t2[i][j][a][b] = s_{i alpha, j beta}^{a alpha, b beta}.
+ * The reference is spin-restricted by default: h, <pq|rs> and eps are spatial,
+ * amplitudes are closed-shell t1[i][a] = s_{i alpha}^{a alpha} and
+ * t2[i][j][a][b] = s_{i alpha, j beta}^{a alpha, b beta}.  With
+ * spin_orbital = 1 every array is over spin orbitals and the amplitudes are
+ * the paper's spin-orbital s_i^a, s_ij^ab (unrestricted references).
  *
  * Conventions of every entry point
  *   - return 0 on success, a negative FTCC_E* code on failure; the message of
@@ -54,7 +56,7 @@
 extern "C" {
 #endif
 
-#define FTCC_ABI_VERSION 3
+#define FTCC_ABI_VERSION 4
 
 #define FTCC_OK 0
 #define FTCC_EINVAL -1      /* bad argument */
@@ -85,10 +87,16 @@ typedef struct {
                            on when the stored tau grid would take more than half the cap, and the
                            nodes of a panel share one executor slot when the per-node working set
                            would not fit.  An allocation beyond the cap fails with FTCC_ENOMEM. */
+  int spin_orbital;     /* 0: spin-restricted spatial orbitals (closed-shell amplitudes);
+                           1: general spin orbitals (unrestricted references such as the Neel
+                           state or UHF, Section IV.A): h is N x N, <pq|rs> N^4 over spin orbitals
+                           (zero between different spins as the Hamiltonian makes them), eps N,
+                           amplitudes t1[i][a], t2[i][j][a][b] antisymmetric in (i,j) and (a,b);
+                           Omega_0 and Omega_1 count one electron per orbital */
 } ftcc_options;
 
 /* Defaults: n_tau 16, m 4, propagator 0, thr 0, tol 1e-12, max_iter 200, checkpoint 0, diis_depth 0,
- * mem_cap_bytes 0. */
+ * mem_cap_bytes 0, spin_orbital 0. */
 void ftcc_default_options(ftcc_options* opt);
 
 /* Create a context for n_instances independent (Hamiltonian, mu, beta) problems

@@ -78,6 +78,7 @@ class Program {
 
 // The spin-restricted FT-CCSD kernels E, S1, S2 as a Program.
 Program build_residual_program();
+Program build_spin_orbital_program();
 
 struct Launch {
   enum Kind { PERM, GEMM, DOT, FILL, SGEMM, ELEM, DOTB } kind = PERM;

@@ -122,9 +122,12 @@ PanelRule make_rule(int m, int lawson) {
 // ------------------------------------------------------------------ mean-field kernel
 // out[0] Omega_0, out[1] Omega_1, out[2] d(Omega_0+Omega_1)/dmu, out[3] .../dbeta,
 // out[4] dOmega_1/dtheta for the direction (dh, deri) at frozen occupations.
+// g = electrons per orbital and occupation (2 spatial restricted, 1 spin orbitals):
+//   Omega_0 = -(g/beta) sum ln(1 + e^{-beta(eps-mu)}),
+//   Omega_1 = g sum (h_pp - eps_p) n_p + (g/2) sum_pq (g <pq|pq> - <pq|qp>) n_p n_q.
 __global__ void meanfield_kernel(int n, const double* eps, const double* h, const double* eri, const double* occ,
                                  const double* fock, double mu, double beta, const double* dh, const double* deri,
-                                 double* out) {
+                                 double g, double* out) {
   __shared__ double red[5][256];
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0;
   const long nn = (long)n * n;
@@ -132,11 +135,11 @@ __global__ void meanfield_kernel(int n, const double* eps, const double* h, cons
     const int p = (int)(e / n), q = (int)(e % n);
     const double gd = eri[(((long)p * n + q) * n + p) * n + q];   // <pq|pq>
     const double gx = eri[(((long)p * n + q) * n + q) * n + p];   // <pq|qp>
-    a1 += (2.0 * gd - gx) * occ[p] * occ[q];
+    a1 += 0.5 * g * (g * gd - gx) * occ[p] * occ[q];
     if (deri) {
       const double dd = deri[(((long)p * n + q) * n + p) * n + q];
       const double dx = deri[(((long)p * n + q) * n + q) * n + p];
-      a4 += (2.0 * dd - dx) * occ[p] * occ[q];
+      a4 += 0.5 * g * (g * dd - dx) * occ[p] * occ[q];
     }
   }
   for (int p = threadIdx.x; p < n; p += blockDim.x) {
@@ -144,15 +147,15 @@ __global__ void meanfield_kernel(int n, const double* eps, const double* h, cons
     const double sp = (x > 0.0) ? log1p(exp(-x)) : (-x + log1p(exp(x)));   // ln(1 + e^-x)
     const double nocc = occ[p], nvir = 1.0 - occ[p];
     a0 += sp;
-    a1 += 2.0 * (h[(long)p * n + p] - eps[p]) * nocc;
+    a1 += g * (h[(long)p * n + p] - eps[p]) * nocc;
     const double fq = fock[(long)p * n + p] - eps[p];
     const double nn1 = (x > 0.0) ? nocc * (1.0 / (1.0 + exp(-x))) : nocc * (exp(x) / (1.0 + exp(x)));
     (void)nvir;
-    // d(Omega_0)/dmu = -2 n ; d(Omega_1)/dmu = 2 (f_qq - eps_q) beta n (1-n)
-    a2 += -2.0 * nocc + 2.0 * fq * beta * nn1;
-    // d(Omega_0)/dbeta = -Omega_0/beta + 2 (eps - mu) n / beta ; d(Omega_1)/dbeta = 2 fq (-(eps-mu) n(1-n))
-    a3 += 2.0 * (eps[p] - mu) * nocc / beta - 2.0 * fq * (eps[p] - mu) * nn1;
-    if (dh) a4 += 2.0 * dh[(long)p * n + p] * nocc;
+    // d(Omega_0)/dmu = -g n ; d(Omega_1)/dmu = g (f_qq - eps_q) beta n (1-n)
+    a2 += -g * nocc + g * fq * beta * nn1;
+    // d(Omega_0)/dbeta = -Omega_0/beta + g (eps - mu) n / beta ; d(Omega_1)/dbeta = g fq (-(eps-mu) n(1-n))
+    a3 += g * (eps[p] - mu) * nocc / beta - g * fq * (eps[p] - mu) * nn1;
+    if (dh) a4 += g * dh[(long)p * n + p] * nocc;
   }
   red[0][threadIdx.x] = a0;
   red[1][threadIdx.x] = a1;
@@ -166,7 +169,7 @@ __global__ void meanfield_kernel(int n, const double* eps, const double* h, cons
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    const double om0 = -2.0 * red[0][0] / beta;
+    const double om0 = -g * red[0][0] / beta;
     out[0] = om0;
     out[1] = red[1][0];
     out[2] = red[2][0];
@@ -189,13 +192,13 @@ __global__ void occ_deriv_kernel(int n, const double* eps, const double* occ, co
   dwv[p] = (wv[p] > 0.0) ? -d / (2.0 * wv[p]) : 0.0;
 }
 
-// dO/dh_pq = 2 n_p delta_pq + sum_XY w^X_p w^Y_q G^XY_pq
+// dO/dh_pq = g n_p delta_pq + sum_XY w^X_p w^Y_q G^XY_pq
 __global__ void dh_assemble_kernel(int n, const double* occ, const double* wo, const double* wv, const double* goo,
-                                   const double* gov, const double* gvo, const double* gvv, double* out) {
+                                   const double* gov, const double* gvo, const double* gvv, double g, double* out) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)n * n) return;
   const int p = (int)(e / n), q = (int)(e % n);
-  double v = (p == q) ? 2.0 * occ[p] : 0.0;
+  double v = (p == q) ? g * occ[p] : 0.0;
   v += wo[p] * wo[q] * goo[e] + wo[p] * wv[q] * gov[e] + wv[p] * wo[q] * gvo[e] + wv[p] * wv[q] * gvv[e];
   out[e] = v;
 }
@@ -308,8 +311,10 @@ struct ftcc_ctx {
   // differential form (propagator >= 2): explicit Runge-Kutta with m = stages,
   // P = n_tau steps; tableau a (row-major m x m, strictly lower) and b
   bool rk = false;
+  double gdeg = 2.0;                          // electrons per orbital and occupation: 2 restricted, 1 spin orbitals
   std::vector<double> rk_a, rk_b;
   double* d_rkw = nullptr;                    // [P + 1] Simpson weight / beta of each grid point
+  int* d_bad = nullptr;                       // flag of the conservation-law checks
   std::map<std::tuple<int, int, int>, std::pair<RKProblem*, int*>> rk_cache;
   std::map<std::tuple<int, int, int>, int> rk_blocks;
   std::map<std::tuple<int, int, int>, DotProblem*> rk_dots;
@@ -418,6 +423,7 @@ void thermal_setup(ftcc_ctx* c, int i) {
   tp.mu = I.mu;
   tp.beta = I.beta;
   tp.thr = c->opt.occ_thresh;
+  tp.g = c->gdeg;
   tp.occ = I.occ;
   tp.wo = I.wo;
   tp.wv = I.wv;
@@ -452,7 +458,7 @@ void thermal_setup(ftcc_ctx* c, int i) {
     launch_block(b, c->stream);
   }
   hipLaunchKernelGGL(meanfield_kernel, dim3(1), dim3(256), 0, c->stream, n, I.eps, I.h, I.eri, I.occ, I.fock, I.mu,
-                     I.beta, nullptr, nullptr, I.mf);
+                     I.beta, nullptr, nullptr, c->gdeg, I.mf);
   FTCC_HIP(hipGetLastError());
 }
 
@@ -463,9 +469,9 @@ void deriv_setup(ftcc_ctx* c, int i, int which, const double* d_dh, const double
   if (which < 2) {
     hipLaunchKernelGGL(occ_deriv_kernel, dim3((n + 63) / 64), dim3(64), 0, c->stream, n, I.eps, I.occ, I.wo, I.wv,
                        I.mu, I.beta, which, I.dn, I.dwo, I.dwv);
-    launch_fock_deriv(n, I.eri, nullptr, nullptr, I.occ, I.dn, I.du_raw, c->stream);
+    launch_fock_deriv(n, I.eri, nullptr, nullptr, I.occ, I.dn, c->gdeg, I.du_raw, c->stream);
   } else {
-    launch_fock_deriv(n, I.eri, d_deri, d_dh, I.occ, nullptr, I.du_raw, c->stream);
+    launch_fock_deriv(n, I.eri, d_deri, d_dh, I.occ, nullptr, c->gdeg, I.du_raw, c->stream);
   }
   for (int k = 0; k < 4; ++k) {
     BlockSpec b;
@@ -505,7 +511,9 @@ long node_len_of(long n) { return n * n + n * n * n * n; }
 // instance's momentum conservation.
 void check_momentum(ftcc_ctx* c, int i, const double* x, int rank, const char* what) {
   Instance& I = c->inst[i];
-  int* d_bad = (int*)c->dalloc(1);   // zeroed
+  if (!c->d_bad) c->d_bad = (int*)c->dalloc(1);
+  int* d_bad = c->d_bad;
+  FTCC_HIP(hipMemsetAsync(d_bad, 0, sizeof(int), c->stream));   // ordinary stream work, never captured
   hipLaunchKernelGGL(momentum_check_kernel, dim3(1024), dim3(256), 0, c->stream, I.n, rank, I.mom.dims, I.d_labels,
                      I.d_modulus, x, d_bad);
   FTCC_HIP(hipGetLastError());
@@ -576,7 +584,7 @@ void build(ftcc_ctx* c) {
   for (int i = 0; i < c->B; ++i)
     if (!c->inst[i].has_ham) fail(FTCC_ESTATE, "instance " + std::to_string(i) + " has no Hamiltonian");
   const int m = c->m, P = c->P, B = c->B;
-  c->prog = build_residual_program();
+  c->prog = c->opt.spin_orbital ? build_spin_orbital_program() : build_residual_program();
   const bool mom = momentum_on(c);
   if (mom)
     for (int i = 0; i < B; ++i) {
@@ -1650,6 +1658,7 @@ void ftcc_default_options(ftcc_options* opt) {
   opt->checkpoint = 0;
   opt->diis_depth = 0;
   opt->mem_cap_bytes = 0;
+  opt->spin_orbital = 0;
 }
 
 int ftcc_abi_version(void) { return FTCC_ABI_VERSION; }
@@ -1675,6 +1684,7 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
     }
     if (!(o.tol > 0.0) || o.max_iter < 1) fail(FTCC_EINVAL, "tol must be > 0 and max_iter >= 1");
     if (!(o.occ_thresh >= 0.0)) fail(FTCC_EINVAL, "occ_thresh must be >= 0");
+    if (o.spin_orbital != 0 && o.spin_orbital != 1) fail(FTCC_EINVAL, "spin_orbital must be 0 or 1");
     if (o.diis_depth < 0 || o.diis_depth == 1 || o.diis_depth > kMaxDiis)
       fail(FTCC_EINVAL, "diis_depth must be 0 (plain fixed-point sweeps) or 2..8");
     int ndev = 0;
@@ -1689,6 +1699,7 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
     std::unique_ptr<ftcc_ctx> c(new ftcc_ctx());
     c->device = device;
     c->opt = o;
+    c->gdeg = o.spin_orbital ? 1.0 : 2.0;
     c->B = n_instances;
     if (rk) {
       // Butcher tableaus: forward Euler, explicit trapezoid (Heun), classical RK4
@@ -1805,6 +1816,10 @@ int ftcc_set_hamiltonian(ftcc_ctx* c, int i, int n, const double* h, const doubl
     FTCC_HIP(hipMemcpy(I.eri, eri, sizeof(double) * n4, hipMemcpyHostToDevice));
     FTCC_HIP(hipMemcpy(I.eps, eps, sizeof(double) * n, hipMemcpyHostToDevice));
     I.eps_host.assign(eps, eps + n);
+    if (c->built && momentum_on(c)) {   // a new Hamiltonian must keep the declared conservation law
+      check_momentum(c, i, I.h, 2, "h");
+      check_momentum(c, i, I.eri, 4, "<pq|rs>");
+    }
     I.has_ham = true;
     c->solved = false;
     c->have_lambda = false;
@@ -2263,14 +2278,14 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
       Instance& I = c->inst[i];
       const long n = I.n, n2 = n * n;
       hipLaunchKernelGGL(meanfield_kernel, dim3(1), dim3(256), 0, c->stream, (int)n, I.eps, I.h, I.eri, I.occ,
-                         I.fock, I.mu, I.beta, d_dh[i], d_deri[i], I.mf);
+                         I.fock, I.mu, I.beta, d_dh[i], d_deri[i], c->gdeg, I.mf);
       FTCC_HIP(hipMemcpyAsync(&mfv[5 * i], I.mf, sizeof(double) * 5, hipMemcpyDeviceToHost, c->stream));
       FTCC_HIP(hipMemcpyAsync(&accs[8 * i], I.acc, sizeof(double) * 8, hipMemcpyDeviceToHost, c->stream));
       if (dO_dh) {
         double* dd = nullptr;
         FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(double) * n2, c->stream));
         hipLaunchKernelGGL(dh_assemble_kernel, dim3((n2 + 255) / 256), dim3(256), 0, c->stream, (int)n, I.occ, I.wo,
-                           I.wv, I.ugrad_acc[0], I.ugrad_acc[1], I.ugrad_acc[2], I.ugrad_acc[3], dd);
+                           I.wv, I.ugrad_acc[0], I.ugrad_acc[1], I.ugrad_acc[2], I.ugrad_acc[3], c->gdeg, dd);
         long off = 0;
         for (int k = 0; k < i; ++k) off += (long)c->inst[k].n * c->inst[k].n;
         FTCC_HIP(hipMemcpyAsync(dO_dh + off, dd, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
@@ -2373,7 +2388,7 @@ int ftcc_find_mu(ftcc_ctx* c, const double* n_target, double* mu, const double* 
         const double nocc = 1.0 / (1.0 + std::exp(z)), nvir = 1.0 / (1.0 + std::exp(-z));
         s += nocc * nvir;
       }
-      return std::max(2.0 * beta[i] * s, 1e-12);
+      return std::max(c->gdeg * beta[i] * s, 1e-12);
     };
     std::vector<int> fst(B), lst(B);
     std::vector<double> dmu(B);

@@ -92,6 +92,7 @@ struct ThermalProblem {
   const double* h;     // n x n
   const double* eri;   // n^4, <pq|rs>
   double mu, beta, thr;
+  double g;            // electrons per orbital and occupation: 2 (spatial, restricted), 1 (spin orbitals)
   double* occ;         // n_p
   double* wo;          // sqrt(n_p) or 0 when dropped
   double* wv;          // sqrt(1 - n_p) or 0 when dropped
@@ -116,9 +117,11 @@ struct BlockSpec {
 };
 void launch_block(const BlockSpec& b, hipStream_t s);
 
-// u = f - diag(eps) and its derivative du = dh + J[dn] + dJ[n] (restricted Fock)
+// u = f - diag(eps) and its derivative du = dh + J[dn] + dJ[n], with the Fock
+// operator f_pq = h_pq + sum_r (g <pr|qr> - <pr|rq>) n_r (g = 2: spin-restricted
+// spatial orbitals, g = 1: spin orbitals)
 void launch_fock_deriv(int n, const double* eri, const double* deri, const double* dh, const double* occ,
-                       const double* docc, double* du, hipStream_t s);
+                       const double* docc, double g, double* du, hipStream_t s);
 void launch_u_from_fock(int n, const double* fock, const double* eps, double* u, hipStream_t s);
 
 // DIIS: coefficients for every instance from its Gram matrix (ld x ld, count entries

@@ -349,7 +349,7 @@ __global__ void fock_kernel(ThermalProblem P) {
   for (int r = 0; r < n; ++r) {
     const double d = P.eri[(((long)p * n + r) * n + q) * n + r];
     const double x = P.eri[(((long)p * n + r) * n + r) * n + q];
-    acc += (2.0 * d - x) * P.occ[r];
+    acc += (P.g * d - x) * P.occ[r];
   }
   P.fock[(long)p * n + q] = acc;
 }
@@ -361,7 +361,7 @@ void launch_thermal(const ThermalProblem& p, hipStream_t s) {
 
 // du_pq = dh_pq + sum_r (2 <pr|qr> - <pr|rq>) dn_r + sum_r (2 d<pr|qr> - d<pr|rq>) n_r
 __global__ void fock_deriv_kernel(int n, const double* eri, const double* deri, const double* dh,
-                                  const double* occ, const double* docc, double* du) {
+                                  const double* occ, const double* docc, double g, double* du) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int p = blockIdx.y;
   if (q >= n) return;
@@ -369,15 +369,15 @@ __global__ void fock_deriv_kernel(int n, const double* eri, const double* deri, 
   for (int r = 0; r < n; ++r) {
     const long id = (((long)p * n + r) * n + q) * n + r;
     const long ix = (((long)p * n + r) * n + r) * n + q;
-    if (docc) acc += (2.0 * eri[id] - eri[ix]) * docc[r];
-    if (deri) acc += (2.0 * deri[id] - deri[ix]) * occ[r];
+    if (docc) acc += (g * eri[id] - eri[ix]) * docc[r];
+    if (deri) acc += (g * deri[id] - deri[ix]) * occ[r];
   }
   du[(long)p * n + q] = acc;
 }
 
 void launch_fock_deriv(int n, const double* eri, const double* deri, const double* dh, const double* occ,
-                       const double* docc, double* du, hipStream_t s) {
-  hipLaunchKernelGGL(fock_deriv_kernel, dim3((n + 63) / 64, n), dim3(64), 0, s, n, eri, deri, dh, occ, docc, du);
+                       const double* docc, double g, double* du, hipStream_t s) {
+  hipLaunchKernelGGL(fock_deriv_kernel, dim3((n + 63) / 64, n), dim3(64), 0, s, n, eri, deri, dh, occ, docc, g, du);
 }
 
 __global__ void u_from_fock_kernel(int n, const double* fock, const double* eps, double* u) {

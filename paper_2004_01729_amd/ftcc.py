@@ -31,7 +31,8 @@ class FTCCError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("n_tau", ctypes.c_int), ("nodes_per_panel", ctypes.c_int), ("propagator", ctypes.c_int),
                 ("occ_thresh", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("checkpoint", ctypes.c_int), ("diis_depth", ctypes.c_int), ("mem_cap_bytes", ctypes.c_size_t)]
+                ("checkpoint", ctypes.c_int), ("diis_depth", ctypes.c_int), ("mem_cap_bytes", ctypes.c_size_t),
+                ("spin_orbital", ctypes.c_int)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -43,7 +43,7 @@ def test_binding_lists_match_header():
 
 def test_abi_version_and_error_string(lib):
     lib.ftcc_abi_version.restype = ctypes.c_int
-    assert lib.ftcc_abi_version() == 3
+    assert lib.ftcc_abi_version() == 4
     lib.ftcc_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.ftcc_last_error(), bytes)
 
@@ -52,4 +52,4 @@ def test_default_options(lib):
     from paper_2004_01729_amd import ftcc
     o = ftcc.default_options()
     assert (o.n_tau, o.nodes_per_panel, o.propagator, o.max_iter, o.checkpoint, o.diis_depth) == (16, 4, 0, 200, 0, 0)
-    assert o.tol == 1e-12 and o.occ_thresh == 0.0 and o.mem_cap_bytes == 0
+    assert o.tol == 1e-12 and o.occ_thresh == 0.0 and o.mem_cap_bytes == 0 and o.spin_orbital == 0
