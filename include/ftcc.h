@@ -181,6 +181,19 @@ int ftcc_get_lambda(ftcc_ctx* ctx, int inst, int node, double* lam1, double* lam
 int ftcc_response(ftcc_ctx* ctx, double* dO_dmu, double* dO_dbeta, double* dO_dh,
                   const double* const* deri_dtheta, const double* const* dh_dtheta, double* dO_dtheta);
 
+/* Two-body response density (Section II.D / Appendix B, the response of Omega
+ * to the two-electron integrals; the N-particle density Gamma_N): for every
+ * instance Gamma_pqrs = dOmega/d<pq|rs> at a frozen reference (orbitals, eps,
+ * dropped slots), taken within the integrals that keep <pq|rs> = <qp|sr> (the
+ * average of an element and its exchange partner), so that for any direction
+ * deri of that kind sum_pqrs Gamma_pqrs deri_pqrs = dOmega/dtheta of
+ * ftcc_response.  Includes the mean-field part and the dependence through the
+ * Fock operator.  gamma: n_i^4 row-major blocks one after the other in instance
+ * order (NaN for an instance whose march or adjoint failed).  Needs
+ * ftcc_lambda; builds a third executor on first use (gradient buffers for
+ * every integral block per executor slot, 12 n^4 accumulators per instance). */
+int ftcc_two_body_density(ftcc_ctx* ctx, double* gamma);
+
 /* Fixed electron number (Section III fixes <N> = 14 for the electron gas this
  * way; the appendix on the UEG basis-set error chooses mu_CC so that the
  * coupled-cluster system holds N electrons): for every instance, the chemical

@@ -264,6 +264,28 @@ def d_omega_dh(model, grid, sol, adj):
     return out
 
 
+def two_body_density(d_omega_along, n):
+    """Gamma_pqrs = dOmega/d<pq|rs> at a frozen reference, within the integrals
+    that keep <pq|rs> = <qp|sr> (Section II.D: the response of Omega to the
+    two-electron integrals), by its definition: for every element the derivative
+    along the direction that moves <pq|rs> and <qp|sr> by 1/2 each.
+    d_omega_along(deri) returns dOmega/dtheta for <pq|rs> + theta deri."""
+    out = np.zeros((n,) * 4)
+    seen = {}
+    for p in range(n):
+        for q in range(n):
+            for r in range(n):
+                for t in range(n):
+                    key = min((p, q, r, t), (q, p, t, r))
+                    if key not in seen:
+                        d = np.zeros((n,) * 4)
+                        d[p, q, r, t] += 0.5
+                        d[q, p, t, r] += 0.5
+                        seen[key] = d_omega_along(d)
+                    out[p, q, r, t] = seen[key]
+    return out
+
+
 def find_mu(make_model, grid, n_target, mu0, tol=1e-10, max_iter=40, solve_tol=1e-13):
     """Chemical potential at which the FT-CCSD electron number N = -dOmega/dmu
     (Section II.D) equals n_target, as the paper fixes <N> for the electron gas

@@ -162,6 +162,12 @@ class Executor {
              const std::vector<int>& const_grads, std::function<double*(size_t)> cache_alloc = nullptr,
              size_t cache_budget = 0);
 
+  // Evaluate the constant combinations (derived tensors) with every forward
+  // pass instead of once in the set-up, so that the reverse pass carries
+  // gradients through them to the raw constants (for the gradient with respect
+  // to the integrals).  Call before build().
+  void set_inline_setup(bool on) { inline_setup_ = on; }
+
   // time the candidate GEMM tile configurations of every large GEMM launch and keep the best
   void autotune(hipStream_t s);
   void run_setup(hipStream_t s) const { run(setup_, s); }
@@ -212,6 +218,7 @@ class Executor {
   const Program* prog_ = nullptr;
   std::vector<ProblemRef> probs_;
   Scratch* scratch_ = nullptr;
+  bool inline_setup_ = false;
   std::function<double*(int, size_t)> const_alloc_;
   std::map<std::pair<int, std::string>, PerProb> const_cache_;
   struct CacheEntry {

@@ -906,15 +906,17 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
   for (int k = 0; k < nt; ++k) {
     const TensorDecl& d = prog->t[k];
     for (int p = 0; p < np; ++p) fwd[k][p] = bind(k, p, false);
-    bool g = (d.kind == T_INPUT || d.kind == T_OUTPUT || (d.kind == T_INTER && !d.derived));
+    bool g = (d.kind == T_INPUT || d.kind == T_OUTPUT || (d.kind == T_INTER && (!d.derived || inline_setup_)));
     if (std::find(const_grads.begin(), const_grads.end(), k) != const_grads.end()) g = true;
     need_grad[k] = g && want_backward;
     if (need_grad[k])
       for (int p = 0; p < np; ++p) grd[k][p] = bind(k, p, true);
   }
-  auto cidx = [&](int k) { return (k >= 0 && (prog->t[k].kind == T_CONST || prog->t[k].derived)) ? k : -1; };
+  auto cidx = [&](int k) {
+    return (k >= 0 && (prog->t[k].kind == T_CONST || (prog->t[k].derived && !inline_setup_))) ? k : -1;
+  };
   // set-up ops first (constants only), once per instance
-  {
+  if (!inline_setup_) {
     std::vector<ProblemRef> firsts;
     std::vector<int> idx;
     std::vector<bool> seen_inst;
@@ -952,7 +954,7 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
   version_.assign(nt, 0);
   auto vidx = [&](int k) { return (k >= 0 && cidx(k) < 0) ? k : -1; };
   for (const SymOp& o : prog->ops) {
-    if (o.setup) continue;
+    if (o.setup && !inline_setup_) continue;
     contract(fwd_, fwd[o.out], o.oi, o.alpha, fwd[o.a], o.ai, cidx(o.a), o.b >= 0 ? &fwd[o.b] : nullptr, o.bi,
              cidx(o.b), o.accumulate, prog->t[o.out].name, vidx(o.a), vidx(o.b), o.out, o.a, o.b);
     version_[o.out]++;
@@ -967,7 +969,7 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
       fill(bwd_, grd[k], prog->t[k].rank, "zero:" + prog->t[k].name, k);
   for (int i = (int)prog->ops.size() - 1; i >= 0; --i) {
     const SymOp& o = prog->ops[i];
-    if (o.setup) continue;
+    if (o.setup && !inline_setup_) continue;
     const std::string tag = "bwd:" + prog->t[o.out].name;
     if (o.b < 0) {
       if (need_grad[o.a])

@@ -73,6 +73,7 @@ def library():
         "ftcc_stats": (ctypes.c_int, [ctypes.c_void_p, _L, _L, _D, _D]),
         "ftcc_find_mu": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, ctypes.c_double, ctypes.c_int, _D, _I, _I]),
         "ftcc_kernel_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D, _L]),
+        "ftcc_two_body_density": (ctypes.c_int, [ctypes.c_void_p, _D]),
         "ftcc_last_error": (ctypes.c_char_p, []),
         "ftcc_abi_version": (ctypes.c_int, []),
     }
@@ -91,7 +92,7 @@ def exported_symbols():
             "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
             "ftcc_get_lambda", "ftcc_response", "ftcc_find_mu", "ftcc_eval_residual", "ftcc_time_residual",
             "ftcc_stats",
-            "ftcc_kernel_profile",
+            "ftcc_kernel_profile", "ftcc_two_body_density",
             "ftcc_last_error", "ftcc_abi_version"]
 
 
@@ -267,6 +268,17 @@ class Context:
                 dh.append(dh_flat[off:off + k * k].reshape(k, k))
                 off += k * k
         return dict(mu=dmu, beta=dbeta, h=dh, theta=dth)
+
+    def two_body_density(self):
+        """Gamma_pqrs = dOmega/d<pq|rs> of every instance (list of n_i^4 arrays)."""
+        sizes = [self.sizes[i] for i in range(self.B)]
+        flat = np.zeros(sum(k ** 4 for k in sizes))
+        _check(self.lib.ftcc_two_body_density(self._h, _ptr(flat)))
+        out, off = [], 0
+        for k in sizes:
+            out.append(flat[off:off + k ** 4].reshape(k, k, k, k))
+            off += k ** 4
+        return out
 
     def find_mu(self, n_target, mu0, beta, tol=1e-10, max_iter=40, raise_on_status=True):
         """mu of every instance with -dOmega/dmu = n_target; returns (mu, N, iters, status)."""
