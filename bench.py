@@ -20,6 +20,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|ueg
                        [--per-instance] [--momentum]
        python bench.py --mode numerr [--dense]
        python bench.py --mode afm
+       python bench.py --mode exc
 
 --mode residual times R back-to-back residual evaluations of every node of the
 last panel at the converged amplitudes (kernel throughput alone); --mode copy
@@ -36,7 +37,9 @@ RK1 / RK2 / RK4 with Simpson's rule, Table tab:numerr) on the 14-electron gas
 in 33 plane waves at r_s = 4, Theta = 0.125 (momentum-blocked unless --dense).
 --mode afm runs the 32-site half-filled ring with Neel and UHF references in
 spin orbitals (U = 2, 4, 8; T = 0.25 .. 2): Omega, E, S and the staggered
-magnetisation per site.
+magnetisation per site.  --mode exc computes the exchange-correlation energy
+E_xc(N, M) of the 66-electron unpolarised gas in 123 plane waves at Theta = 0.5
+(r_s = 1, 2, 4) with mu fixed at the coupled-cluster level.
 """
 from __future__ import annotations
 
@@ -305,6 +308,54 @@ def afm_bench(L=32, Us=(2.0, 4.0, 8.0), Ts=(0.25, 0.5, 1.0, 2.0), n_tau=24):
                 n_tau=n_tau, rows=rows)
 
 
+def exc_bench(n_el=66, n_pw=123, rss=(1.0, 2.0, 4.0), theta=0.5):
+    """Exchange-correlation energy of the unpolarised gas at fixed N (the
+    appendix on the UEG basis-set error):
+        E_xc(N, M) = E_CC(mu_CC) + E_0(mu_CC) - E_0(mu_0) = E(mu_CC) - E_0(mu_0),
+    E(mu) = Omega + beta dOmega/dbeta + mu N the FT-CCSD internal energy (thermal
+    HF reference, frozen), mu_CC from ftcc_find_mu so that -dOmega/dmu = N, and
+    E_0 the ideal-gas kinetic energy in the same M plane waves at the mu_0 that
+    holds N electrons.  Momentum-blocked, 16 tau points, occupation threshold 1e-6."""
+    import numpy as np
+    import ftcc_inputs as fi
+    from paper_2004_01729_amd import ftcc as F
+    rows = []
+    for rs in rss:
+        s = fi.ueg_config(n_pw, n_el, rs, theta)
+        t0 = time.perf_counter()
+        ctx = F.Context(1, n_tau=16, nodes_per_panel=4, tol=1e-11, occ_thresh=1e-6, checkpoint=1)
+        ctx.set_momentum(0, *s.momentum)
+        ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+        mu, n_cc, its, st = ctx.find_mu(n_el, s.mu, s.beta, tol=1e-8, max_iter=20, raise_on_status=False)
+        row = dict(rs=rs, theta=theta, beta=s.beta, mu_hf=s.mu, status=int(st[0]), find_mu_evaluations=int(its[0]))
+        if st[0] == 0:
+            ctx.solve(mu[0], s.beta)
+            om, _ = ctx.grand_potential()
+            ctx.lam()
+            r = ctx.response(want_mu=True, want_beta=True, want_h=False)
+            n_e = -r["mu"][0]
+            e_cc = float(om[0] + s.beta * r["beta"][0] + mu[0] * n_e)
+            # ideal gas in the same basis: kinetic energies k^2/2 (the diagonal of h)
+            ek = np.diag(s.h)
+            def n_of(m):
+                return 2.0 * float(np.sum(1.0 / (1.0 + np.exp(np.clip(s.beta * (ek - m), -700, 700)))))
+            lo, hi = ek.min() - 50.0 / s.beta, ek.max() + 50.0 / s.beta
+            for _ in range(200):
+                mid = 0.5 * (lo + hi)
+                lo, hi = (mid, hi) if n_of(mid) < n_el else (lo, mid)
+            mu0 = 0.5 * (lo + hi)
+            occ0 = 1.0 / (1.0 + np.exp(np.clip(s.beta * (ek - mu0), -700, 700)))
+            e0 = float(2.0 * np.sum(ek * occ0))
+            row.update(mu_cc=float(mu[0]), N=float(n_e), E=e_cc, mu_0=mu0, E_0=e0,
+                       E_xc_per_electron=(e_cc - e0) / n_el, rs_E_xc_per_electron=rs * (e_cc - e0) / n_el)
+        ctx.close()
+        row["seconds"] = time.perf_counter() - t0
+        rows.append(row)
+        print(f"[exc] rs={rs:g} theta={theta:g} status={row['status']} {row['seconds']:.1f} s", file=sys.stderr,
+              flush=True)
+    return dict(mode="exc", workload=f"ueg_N{n_el}_{n_pw}pw_theta{theta:g}_thr1e-6", rows=rows)
+
+
 def cpu_baseline(s, budget_s=20.0):
     """The oracle as it stands (spin-summed restricted kernels, numpy/BLAS on
     the host) on a bounded sample: the einsum items of one residual evaluation
@@ -355,7 +406,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="ueg57")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch", "numerr", "afm"))
+    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch", "numerr", "afm", "exc"))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
     ap.add_argument("--group", type=int, default=32)
@@ -375,6 +426,9 @@ def main():
         raise SystemExit("no GPU visible")
     if args.mode == "copy":
         print(json.dumps(copy_calibration(args.reps)), flush=True)
+        return
+    if args.mode == "exc":
+        print(json.dumps(exc_bench()), flush=True)
         return
     if args.mode == "afm":
         print(json.dumps(afm_bench()), flush=True)
