@@ -92,6 +92,9 @@ struct Launch {
   int n_tasks = 0;
   void* d_red = nullptr;            // SGEMM: reductions of split inner ranges
   int n_red = 0;
+  bool zero_fill = false;           // ELEM with alpha = beta = 0 (host copies kept for merging)
+  std::vector<ElemProblem> eprobs;
+  std::vector<ElemTask> etasks;
   long long n_elem = 0;             // ELEM: allowed elements
   int dot_blocks = 0;
   void* d_desc = nullptr;
@@ -219,6 +222,8 @@ class Executor {
   std::vector<ProblemRef> probs_;
   Scratch* scratch_ = nullptr;
   bool inline_setup_ = false;
+  // consecutive zero fills write disjoint buffers: one launch serves them all
+  void merge_fills(std::vector<Launch>& L);
   std::function<double*(int, size_t)> const_alloc_;
   std::map<std::pair<int, std::string>, PerProb> const_cache_;
   struct CacheEntry {

@@ -813,6 +813,11 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
   L.n_tasks = (int)tasks.size();
   L.d_tasks = upload(tasks.data(), sizeof(ElemTask) * std::max<size_t>(tasks.size(), 1));
   L.n_elem = total;
+  if (alpha == 0.0 && beta == 0.0) {
+    L.zero_fill = true;
+    L.eprobs = ps;
+    L.etasks = tasks;
+  }
   L.total = (int)std::min<long long>((total + 255) / 256, 1 << 30);
   L.tag = tag + "(blocked)";
   dst.push_back(L);
@@ -877,6 +882,40 @@ bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std
   L.tag = tag + "(blocked dot)";
   dst.push_back(L);
   return true;
+}
+
+void Executor::merge_fills(std::vector<Launch>& L) {
+  std::vector<Launch> out;
+  std::vector<bool> merged;
+  for (Launch& l : L) {
+    if (l.kind == Launch::ELEM && l.zero_fill && !out.empty() && out.back().kind == Launch::ELEM &&
+        out.back().zero_fill) {
+      Launch& m = out.back();
+      const int po = (int)m.eprobs.size();
+      m.eprobs.insert(m.eprobs.end(), l.eprobs.begin(), l.eprobs.end());
+      for (ElemTask t : l.etasks) {
+        t.prob += po;
+        t.first += m.n_elem;
+        m.etasks.push_back(t);
+      }
+      m.n_elem += l.n_elem;
+      m.tag += "+" + l.tag;
+      merged.back() = true;
+      continue;
+    }
+    out.push_back(std::move(l));
+    merged.push_back(false);
+  }
+  for (size_t k = 0; k < out.size(); ++k) {
+    if (!merged[k]) continue;
+    Launch& m = out[k];
+    m.n_prob = (int)m.eprobs.size();
+    m.d_desc = upload(m.eprobs.data(), sizeof(ElemProblem) * m.eprobs.size());
+    m.n_tasks = (int)m.etasks.size();
+    m.d_tasks = upload(m.etasks.data(), sizeof(ElemTask) * std::max<size_t>(m.etasks.size(), 1));
+    m.total = (int)std::min<long long>((m.n_elem + 255) / 256, 1 << 30);
+  }
+  L = std::move(out);
 }
 
 double Executor::sgemm_flops_forward() const {
@@ -984,6 +1023,7 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
       contract(bwd_, grd[o.b], o.bi, o.alpha, fwd[o.a], o.ai, cidx(o.a), &grd[o.out], o.oi, -1, true, tag + ":dB",
                vidx(o.a), -1, o.b, o.a, o.out);
   }
+  merge_fills(bwd_);
   dump_plan();
 }
 
