@@ -128,7 +128,8 @@ using Binder = std::function<double*(int tensor, int prob, bool grad)>;
 struct Scratch {
   std::vector<double*> a, b, c, part;   // per problem: n^4 doubles each
   double* dot_partial = nullptr;        // >= n_prob * 64 doubles
-  double* tail_ws = nullptr;            // kTailWorkspaceDoubles: GEMM tail-split partial tiles
+  double* tail_ws = nullptr;            // partial tiles of split GEMM tails, blocked GEMM chunks, blocked dots
+  size_t tail_ws_doubles = 0;           // its size (at most kTailWorkspaceDoubles)
 };
 
 // HIP-event timing of the dominant kernel (the FP64-MFMA GEMM with 128x128
@@ -258,7 +259,7 @@ class Executor {
   double run_flops(const Launch& l) const;
   GemmTail tail_of(const Launch& l, int cfg) const {
     return plan_gemm_tail(cfg, l.total, l.min_k, l.splitk_blocks > 0, scratch_ ? scratch_->tail_ws : nullptr,
-                          kTailWorkspaceDoubles);
+                          scratch_ ? scratch_->tail_ws_doubles : 0);
   }
   const int* gate_for(const std::vector<Launch>& dst, int p) const {
     return (gate_ && &dst != &setup_) ? gate_ + probs_[p].inst : nullptr;

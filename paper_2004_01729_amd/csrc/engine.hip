@@ -710,7 +710,7 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
   // dependent gathers: its range is cut into chunks whose partial tiles a
   // second kernel adds in order.  The chunk grows (powers of two) until every
   // partial tile fits the workspace.
-  const long ws_tiles = scratch_ && scratch_->tail_ws ? (long)(kTailWorkspaceDoubles / 256) : 0;
+  const long ws_tiles = scratch_ && scratch_->tail_ws ? (long)(scratch_->tail_ws_doubles / 256) : 0;
   int chunk = kSgemmChunk;
   auto parts_needed = [&](int ch) {
     long n = 0;
@@ -870,7 +870,7 @@ bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std
     P.first_block = (int)(start / 256);
     P.n_blocks = (int)((total - start + 255) / 256);
   }
-  if ((total + 255) / 256 > (long long)kTailWorkspaceDoubles) return false;
+  if ((total + 255) / 256 > (long long)scratch_->tail_ws_doubles) return false;
   Launch L;
   L.kind = Launch::DOTB;
   L.n_prob = np;

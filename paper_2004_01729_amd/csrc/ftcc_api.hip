@@ -805,7 +805,13 @@ void build(ftcc_ctx* c) {
       c->scratch.part[q] = c->dalloc(n4);
     }
   c->scratch.dot_partial = c->dalloc((size_t)nn * 64 + 64);
-  c->scratch.tail_ws = c->dalloc(kTailWorkspaceDoubles);
+  {
+    // workspace for partial tiles: 128 MiB, or an eighth of a memory cap below 1 GiB
+    size_t ws = kTailWorkspaceDoubles;
+    if (c->opt.mem_cap_bytes) ws = std::min(ws, std::max<size_t>(c->opt.mem_cap_bytes / 64, 64 * 256));
+    c->scratch.tail_ws = c->dalloc(ws);
+    c->scratch.tail_ws_doubles = ws;
+  }
   c->d_maxbits = (unsigned long long*)c->dalloc(2 * B);
   c->d_active = (int*)c->dalloc(B);
   c->d_run = (int*)c->dalloc(B);
