@@ -1,0 +1,49 @@
+"""The largest workload shape, the 123-plane-wave gas (n = 123, N = 14,
+r_s = 4, Theta = 1; t2 is 1.83 GB), where no oracle evaluation fits a test:
+properties that hold at any size.  One residual evaluation at momentum-
+conserving random amplitudes by the dense FP64-MFMA path and by the momentum-
+blocked path (two different algorithms for the same equations) agree element
+by element; the dense residual has the structure the equations fix (momentum-
+forbidden elements zero, S2[ijab] = S2[jiba])."""
+import numpy as np
+import pytest
+
+import ftcc_inputs as fi
+
+pytestmark = pytest.mark.gpu
+
+
+def test_residual_n123_dense_equals_blocked():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_01729_amd import ftcc as F
+    s = fi.ueg_config(123, 14, 4.0, 1.0)
+    n = s.n
+    lab = np.asarray(s.momentum[0])
+    base = 4 * int(np.abs(lab).max()) + 1
+    code = lambda v: (v[..., 0] * base + v[..., 1]) * base + v[..., 2]
+    pair = code(lab[:, None, :] + lab[None, :, :])                 # k_i + k_j
+    allowed2 = pair[:, :, None, None] == pair[None, None, :, :]
+    allowed1 = code(lab)[:, None] == code(lab)[None, :]
+    rng = np.random.default_rng(11)
+    t1 = rng.standard_normal((n, n)) * 0.02 * allowed1
+    t2 = rng.standard_normal((n,) * 4) * 0.02
+    t2 = 0.5 * (t2 + t2.transpose(1, 0, 3, 2))
+    t2 *= allowed2
+    out = []
+    for blocked in (False, True):
+        print(f"[fullsize123] residual n=123 seed=11 blocked={blocked}", flush=True)
+        ctx = F.Context(1, n_tau=4, nodes_per_panel=4, occ_thresh=1e-6)
+        if blocked:
+            ctx.set_momentum(0, *s.momentum)
+        ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+        out.append(ctx.eval_residual(0, s.mu, s.beta, t1, t2))
+        ctx.close()
+    (d1, d2, de), (b1, b2, be) = out
+    scale2 = max(1.0, np.abs(d2).max())
+    assert np.abs(d1 - b1).max() < 1e-12 * max(1.0, np.abs(d1).max())
+    assert np.abs(d2 - b2).max() < 1e-12 * scale2
+    assert abs(de - be) < 1e-12 * max(1.0, abs(de))
+    assert np.abs(d2[~allowed2]).max() < 1e-14 * scale2 and np.all(b2[~allowed2] == 0.0)
+    assert np.abs(d2 - d2.transpose(1, 0, 3, 2)).max() < 1e-13 * scale2
