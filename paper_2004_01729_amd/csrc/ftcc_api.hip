@@ -2271,7 +2271,17 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
     const bool want_theta = dO_dtheta && (deri_dtheta || dh_dtheta);
     // device copies of the theta directions
     std::vector<double*> d_deri(B, nullptr), d_dh(B, nullptr);
-    std::vector<void*> tmp;
+    // freed when the call ends, also when it ends with an error
+    struct DeviceTemps {
+      hipStream_t s;
+      std::vector<void*> p;
+      void push_back(void* x) { p.push_back(x); }
+      ~DeviceTemps() {
+        if (p.empty()) return;
+        (void)hipStreamSynchronize(s);
+        for (void* x : p) (void)hipFree(x);
+      }
+    } tmp{c->stream, {}};
     if (want_theta) {
       for (int i = 0; i < B; ++i) {
         const long n = c->inst[i].n, n2 = n * n, n4 = n2 * n2;
@@ -2440,7 +2450,6 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
       }
     }
     sync(c);
-    for (void* t : tmp) (void)hipFree(t);
     for (int i = 0; i < B; ++i) {
       if (dO_dmu) dO_dmu[i] = mfv[5 * i + 2] + accs[8 * i + 0];
       if (dO_dbeta) dO_dbeta[i] = mfv[5 * i + 3] + accs[8 * i + 1] + accs[8 * i + 3];
