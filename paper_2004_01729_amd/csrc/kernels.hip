@@ -15,6 +15,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
+#include "gmem.h"
 #include "kernels.h"
 
 namespace ftcc {
@@ -89,7 +92,7 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   }
   const int pi = find_problem(prefix, n_prob, tile);
   const GemmProblem& P = probs[pi];
-  if (P.active && *P.active == 0) return;   // the whole block leaves before any barrier
+  if (P.active && *gview(P.active) == 0) return;   // the whole block leaves before any barrier
   int local = tile - prefix[pi];
   const int tiles_mn = P.tiles_m * P.tiles_n;
   const int ks = local / tiles_mn;
@@ -119,33 +122,44 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   const int ca = tid % RA, r0a = tid / RA;
   const int cb = tid % RB, r0b = tid / RB;
   constexpr int DRA = 256 / RA, DRB = 256 / RB;
-  const double* __restrict__ A = P.A;
-  const double* __restrict__ B = P.B;
+  const gptr<const double> __restrict__ A = gview(P.A);
+  const gptr<const double> __restrict__ B = gview(P.B);
   const int lda = (int)P.lda, ldb = (int)P.ldb;
 
   double ra[LA], rb[LB];
-  // k0: first k of the tile
+  // Branch-free operand loads of the K step starting at k0: the element index is
+  // clamped into the operand (a valid address also past the step's K range) and
+  // the elements outside the range are zeroed on their way into LDS, so that a
+  // whole K step is one basic block that the scheduler can interleave.
   auto load_tiles = [&](int k0) {
 #pragma unroll
     for (int j = 0; j < LA; ++j) {
       const int r = r0a + DRA * j;
-      int gm, gk;
-      if (TA) { gk = k0 + r; gm = m0 + ca; } else { gm = m0 + r; gk = k0 + ca; }
-      ra[j] = (gm < M && gk < kend) ? A[TA ? (unsigned)(gk * lda + gm) : (unsigned)(gm * lda + gk)] : 0.0;
+      const unsigned off = TA ? (unsigned)(min(k0 + r, kend - 1) * lda + min(m0 + ca, M - 1))
+                              : (unsigned)(min(m0 + r, M - 1) * lda + min(k0 + ca, kend - 1));
+      ra[j] = A[off];
     }
 #pragma unroll
     for (int j = 0; j < LB; ++j) {
       const int r = r0b + DRB * j;
-      int gn, gk;
-      if (TB) { gn = n0 + r; gk = k0 + cb; } else { gk = k0 + r; gn = n0 + cb; }
-      rb[j] = (gn < N && gk < kend) ? B[TB ? (unsigned)(gn * ldb + gk) : (unsigned)(gk * ldb + gn)] : 0.0;
+      const unsigned off = TB ? (unsigned)(min(n0 + r, N - 1) * ldb + min(k0 + cb, kend - 1))
+                              : (unsigned)(min(k0 + r, kend - 1) * ldb + min(n0 + cb, N - 1));
+      rb[j] = B[off];
     }
   };
-  auto store_tiles = [&](int buf) {
+  auto store_tiles = [&](double* as, double* bs, int k0) {
 #pragma unroll
-    for (int j = 0; j < LA; ++j) As[buf][(r0a + DRA * j) * PA + ca] = ra[j];
+    for (int j = 0; j < LA; ++j) {
+      const int r = r0a + DRA * j;
+      const bool ok = TA ? (k0 + r < kend && m0 + ca < M) : (m0 + r < M && k0 + ca < kend);
+      as[r * PA + ca] = ok ? ra[j] : 0.0;
+    }
 #pragma unroll
-    for (int j = 0; j < LB; ++j) Bs[buf][(r0b + DRB * j) * PB + cb] = rb[j];
+    for (int j = 0; j < LB; ++j) {
+      const int r = r0b + DRB * j;
+      const bool ok = TB ? (n0 + r < N && k0 + cb < kend) : (k0 + r < kend && n0 + cb < N);
+      bs[r * PB + cb] = ok ? rb[j] : 0.0;
+    }
   };
 
   double4_t acc[FM][FN];
@@ -155,11 +169,6 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     for (int j = 0; j < FN; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
   const int nk = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
-  if (nk > 0) {
-    load_tiles(kbeg);
-    store_tiles(0);
-    __syncthreads();
-  }
   const int fr = lane & 15, fk = lane >> 4;
   const int abase = TA ? fk * PA + wm * WM + fr : (wm * WM + fr) * PA + fk;
   const int bbase = TB ? (wn * WN + fr) * PB + fk : fk * PB + wn * WN + fr;
@@ -167,22 +176,30 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   constexpr int ASTEP_K = TA ? 4 * PA : 4;      // next k group
   constexpr int BSTEP_J = TB ? 16 * PB : 16;
   constexpr int BSTEP_K = TB ? 4 : 4 * PB;
-  for (int it = 0; it < nk; ++it) {
-    const int cur = it & 1;
-    const bool more = (it + 1) < nk;
-    if (more) load_tiles(kbeg + (it + 1) * BK);
-    const double* as = As[cur] + abase;
-    const double* bs = Bs[cur] + bbase;
+  constexpr int KG = BK / 4;                    // k groups of one K step
+  // One K step on LDS buffer CUR (a compile-time index, so that the compiler sees
+  // that the stores into the other buffer never alias this step's fragment reads):
+  // the global loads of the next step, the MFMAs of this one, the next step's
+  // operands into the other buffer, a barrier.  The two waves that share a SIMD
+  // run this same code and would otherwise fall into step: both in their MFMA
+  // section together and then both in their loads and stores with the matrix
+  // pipe idle.  The scheduling groups below spread the memory instructions
+  // between the MFMAs instead.
+  auto kstep = [&](auto cur_c, int it) {
+    constexpr int CUR = decltype(cur_c)::value;
+    const int kn = kbeg + (it + 1) * BK;
+    load_tiles(kn);
+    const double* as = As[CUR] + abase;
+    const double* bs = Bs[CUR] + bbase;
     double af[2][FM], bf[2][FN];
 #pragma unroll
     for (int i = 0; i < FM; ++i) af[0][i] = as[i * ASTEP_I];
 #pragma unroll
     for (int j = 0; j < FN; ++j) bf[0][j] = bs[j * BSTEP_J];
-    __builtin_amdgcn_s_setprio(1);   // MFMA section: issue priority over waves in their load phase
 #pragma unroll
-    for (int kq = 0; kq < BK / 4; ++kq) {
+    for (int kq = 0; kq < KG; ++kq) {
       const int c = kq & 1;
-      if (kq + 1 < BK / 4) {   // fetch the next k group while this one multiplies
+      if (kq + 1 < KG) {   // fetch the next k group while this one multiplies
 #pragma unroll
         for (int i = 0; i < FM; ++i) af[c ^ 1][i] = as[(kq + 1) * ASTEP_K + i * ASTEP_I];
 #pragma unroll
@@ -194,14 +211,41 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
         for (int j = 0; j < FN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[c][i], bf[c][j], acc[i][j], 0, 0, 0);
     }
-    __builtin_amdgcn_s_setprio(0);
-    if (more) store_tiles(cur ^ 1);
+    store_tiles(As[CUR ^ 1], Bs[CUR ^ 1], kn);
+    // Instruction order (MFMA slot u = 0 .. T-1): the first k group's fragment
+    // reads, then after each MFMA at most one global load of the next step (first
+    // slots), one fragment read of the next k group (second half of each group),
+    // one LDS store of the next step's operands (last group only, long after
+    // their loads were issued).  Masks: 0x008 MFMA, 0x020 VMEM read, 0x100 DS
+    // read, 0x200 DS write.
+    {
+      constexpr int MG = FM * FN, T = MG * KG, NV = LA + LB, NW = LA + LB;
+      __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
+#pragma unroll
+      for (int u = 0; u < T; ++u) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (u < NV) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        if (u < T - MG && (u % MG) >= MG - (FM + FN)) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        if (u >= T - NW) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+      }
+    }
     __syncthreads();
+  };
+  if (nk > 0) {
+    load_tiles(kbeg);
+    store_tiles(As[0], Bs[0], kbeg);
+    __syncthreads();
+  }
+  // The last step's loads read clamped (valid) addresses and its stores fill the
+  // buffer that is no longer read.
+  for (int it = 0; it < nk; it += 2) {
+    kstep(std::integral_constant<int, 0>{}, it);
+    if (it + 1 < nk) kstep(std::integral_constant<int, 1>{}, it + 1);
   }
 
   // epilogue
   if (kseg >= 0) {   // partial tile of a tail segment, summed by gemm_tail_reduce
-    double* W = ws + (long)(b - dp_tiles) * (BM * BN);
+    const gptr<double> W = gview(ws) + (long)(b - dp_tiles) * (BM * BN);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -211,16 +255,16 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
           W[(wm * WM + i * 16 + 4 * r + fk) * BN + wn * WN + j * 16 + fr] = acc[i][j][r];
     return;
   }
-  double* C;
+  gptr<double> C;
   long ldc;
   double alpha, beta;
   if (P.ksplit > 1) {
-    C = P.partial + (long)ks * M * N;
+    C = gview(P.partial) + (long)ks * M * N;
     ldc = N;
     alpha = 1.0;
     beta = 0.0;
   } else {
-    C = P.C;
+    C = gview(P.C);
     ldc = P.ldc;
     alpha = P.alpha;
     beta = P.beta;
@@ -234,7 +278,7 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm * WM + i * 16 + 4 * r + fk;
         if (gm < M && gn < N) {
-          double* c = C + (long)gm * ldc + gn;
+          const gptr<double> c = C + (long)gm * ldc + gn;
           double v = alpha * acc[i][j][r];
           if (beta != 0.0) v += beta * (*c);
           *c = v;
@@ -253,10 +297,10 @@ __global__ void __launch_bounds__(256) gemm_tail_reduce_kernel(const GemmProblem
   const int t = dp_tiles + blockIdx.y;
   const int pi = find_problem(prefix, n_prob, t);
   const GemmProblem& P = probs[pi];
-  if (P.active && *P.active == 0) return;
+  if (P.active && *gview(P.active) == 0) return;
   int tm, tn;
   tile_coords(t - prefix[pi], P.tiles_m, P.tiles_n, tm, tn);   // tail launches have no split-K problems
-  const double* W = ws + (long)blockIdx.y * splits * (BM * BN);
+  const gptr<const double> W = gview(ws) + (long)blockIdx.y * splits * (BM * BN);
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = blockIdx.x * 1024 + u * 256 + threadIdx.x;
@@ -265,7 +309,7 @@ __global__ void __launch_bounds__(256) gemm_tail_reduce_kernel(const GemmProblem
     if (gm >= P.M || gn >= P.N) continue;
     double s = 0.0;
     for (int k = 0; k < splits; ++k) s += W[(long)k * (BM * BN) + e];
-    double* c = P.C + (long)gm * P.ldc + gn;
+    const gptr<double> c = gview(P.C) + (long)gm * P.ldc + gn;
     double v = P.alpha * s;
     if (P.beta != 0.0) v += P.beta * (*c);
     *c = v;
@@ -287,15 +331,15 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
   if (ti >= n_tasks) return;
   const SgemmTask T = tasks[ti];
   const SgemmProblem& P = probs[T.prob];
-  if (P.active && *P.active == 0) return;
-  const double* __restrict__ A = P.A;
-  const double* __restrict__ B = P.B;
-  const unsigned* __restrict__ offAK = P.offAK + T.kb;
-  const unsigned* __restrict__ offBK = P.offBK + T.kb;
+  if (P.active && *gview(P.active) == 0) return;
+  const gptr<const double> __restrict__ A = gview(P.A);
+  const gptr<const double> __restrict__ B = gview(P.B);
+  const gptr<const unsigned> __restrict__ offAK = gview(P.offAK) + T.kb;
+  const gptr<const unsigned> __restrict__ offBK = gview(P.offBK) + T.kb;
   const int r = lane & 15, q = lane >> 4;
   const bool row_ok = r < T.mlen, col_ok = r < T.nlen;
-  const unsigned am = row_ok ? P.offAM[T.mb + r] : 0u;
-  const unsigned bn = col_ok ? P.offBN[T.nb + r] : 0u;
+  const unsigned am = row_ok ? gview(P.offAM)[T.mb + r] : 0u;
+  const unsigned bn = col_ok ? gview(P.offBN)[T.nb + r] : 0u;
   double4_t acc = (double4_t){0.0, 0.0, 0.0, 0.0};
   // G groups of 4 inner indices per step: the offset loads of all groups are
   // issued together, then all operand gathers, then the MFMAs, so one step
@@ -324,7 +368,7 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
     for (int u = 0; u < G; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
   }
   if (T.part >= 0) {   // one chunk of a split inner range: the whole tile, lane-major
-    double* w = ws + (size_t)T.part * 256;
+    const gptr<double> w = gview(ws) + (size_t)T.part * 256;
 #pragma unroll
     for (int i = 0; i < 4; ++i) w[i * 64 + lane] = acc[i];
     return;
@@ -333,7 +377,7 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
   for (int i = 0; i < 4; ++i) {
     const int row = 4 * i + q, col = r;
     if (row < T.mlen && col < T.nlen) {
-      double* c = P.C + P.offCM[T.mb + row] + P.offCN[T.nb + col];
+      const gptr<double> c = gview(P.C) + gview(P.offCM)[T.mb + row] + gview(P.offCN)[T.nb + col];
       double v = P.alpha * acc[i];
       if (P.beta != 0.0) v += P.beta * (*c);
       *c = v;
@@ -350,15 +394,15 @@ __global__ void __launch_bounds__(256) sgemm_reduce_kernel(const SgemmProblem* _
   if (ti >= n_red) return;
   const SgemmReduce R = red[ti];
   const SgemmProblem& P = probs[R.prob];
-  if (P.active && *P.active == 0) return;
+  if (P.active && *gview(P.active) == 0) return;
   const int r = lane & 15, q = lane >> 4;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int row = 4 * i + q, col = r;
     if (row < R.mlen && col < R.nlen) {
       double acc = 0.0;
-      for (int c = 0; c < R.count; ++c) acc += ws[(size_t)(R.first + c) * 256 + i * 64 + lane];
-      double* out = P.C + P.offCM[R.mb + row] + P.offCN[R.nb + col];
+      for (int c = 0; c < R.count; ++c) acc += gview(ws)[(size_t)(R.first + c) * 256 + i * 64 + lane];
+      const gptr<double> out = gview(P.C) + gview(P.offCM)[R.mb + row] + gview(P.offCN)[R.nb + col];
       double v = P.alpha * acc;
       if (P.beta != 0.0) v += P.beta * (*out);
       *out = v;
@@ -380,12 +424,12 @@ __global__ void __launch_bounds__(256) elem_kernel(const ElemProblem* __restrict
   }
   const ElemTask& T = tasks[lo];
   const ElemProblem& P = probs[T.prob];
-  if (P.active && *P.active == 0) return;
+  if (P.active && *gview(P.active) == 0) return;
   const int r = (int)(e - T.first);
   const int u = T.u0 + r / T.vlen, v = T.v0 + r % T.vlen;
-  double* y = P.Y + P.oy1[u] + P.oy2[v];
+  const gptr<double> y = gview(P.Y) + gview(P.oy1)[u] + gview(P.oy2)[v];
   double val = 0.0;
-  if (P.alpha != 0.0) val = P.alpha * P.X[P.ox1[u] + P.ox2[v]];
+  if (P.alpha != 0.0) val = P.alpha * gview(P.X)[gview(P.ox1)[u] + gview(P.ox2)[v]];
   if (P.beta != 0.0) val += P.beta * (*y);
   *y = val;
 }
@@ -408,7 +452,7 @@ __global__ void __launch_bounds__(256) dotb_partial_kernel(const DotbProblem* __
     const long long r = e - T.first;
     if (r >= 0 && r < (long long)T.ulen * T.vlen) {
       const int u = T.u0 + (int)(r / T.vlen), w = T.v0 + (int)(r % T.vlen);
-      v = P.X[P.ox1[u] + P.ox2[w]] * P.Y[P.oy1[u] + P.oy2[w]];
+      v = gview(P.X)[gview(P.ox1)[u] + gview(P.ox2)[w]] * gview(P.Y)[gview(P.oy1)[u] + gview(P.oy2)[w]];
     }
   }
   __shared__ double red[256];
@@ -425,12 +469,13 @@ __global__ void dotb_final_kernel(const DotbProblem* __restrict__ probs, int n_p
   const int pi = blockIdx.x * blockDim.x + threadIdx.x;
   if (pi >= n_prob) return;
   const DotbProblem& P = probs[pi];
-  if (P.active && *P.active == 0) return;
+  if (P.active && *gview(P.active) == 0) return;
   double s = 0.0;
   for (int b = 0; b < P.n_blocks; ++b) s += partial[P.first_block + b];
   double v = P.alpha * s;
-  if (P.beta != 0.0) v += P.beta * (*P.out);
-  *P.out = v;
+  const gptr<double> out = gview(P.out);
+  if (P.beta != 0.0) v += P.beta * (*out);
+  *out = v;
 }
 
 // C = alpha * sum_s partial[s] + beta * C for split-K problems
@@ -438,16 +483,16 @@ __global__ void splitk_reduce_kernel(const GemmProblem* __restrict__ probs, cons
                                      int n_prob, int total) {
   const int pi = find_problem(prefix, n_prob, blockIdx.x);
   const GemmProblem P = probs[pi];
-  if (P.ksplit <= 1 || (P.active && *P.active == 0)) return;
+  if (P.ksplit <= 1 || (P.active && *gview(P.active) == 0)) return;
   const long mn = (long)P.M * P.N;
   const long chunk = (long)(blockIdx.x - prefix[pi]) * 256 * 4;
   for (int u = 0; u < 4; ++u) {
     long e = chunk + u * 256 + threadIdx.x;
     if (e >= mn) return;
     double s = 0.0;
-    for (int k = 0; k < P.ksplit; ++k) s += P.partial[k * mn + e];
+    for (int k = 0; k < P.ksplit; ++k) s += gview(P.partial)[k * mn + e];
     long gm = e / P.N, gn = e % P.N;
-    double* c = P.C + gm * P.ldc + gn;
+    const gptr<double> c = gview(P.C) + gm * P.ldc + gn;
     double v = P.alpha * s;
     if (P.beta != 0.0) v += P.beta * (*c);
     *c = v;
@@ -483,12 +528,12 @@ __global__ void __launch_bounds__(256) permute4_kernel(const PermProblem* __rest
                                                        const int* __restrict__ prefix, int n_prob) {
   const int pi = find_problem(prefix, n_prob, blockIdx.x);
   const PermProblem& P = probs[pi];
-  if (P.active && *P.active == 0) return;   // uniform per block, before the barrier
+  if (P.active && *gview(P.active) == 0) return;   // uniform per block, before the barrier
   const unsigned int local = blockIdx.x - prefix[pi];
-  const double alpha = P.scale ? P.alpha * (*P.scale) : P.alpha;
+  const double alpha = P.scale ? P.alpha * (*gview(P.scale)) : P.alpha;
   const double beta = P.beta;
-  const double* __restrict__ X = P.X;
-  double* __restrict__ Y = P.Y;
+  const gptr<const double> __restrict__ X = gview(P.X);
+  const gptr<double> __restrict__ Y = gview(P.Y);
   __shared__ double tileb[32][33];
   if (P.tb < 0) {
     const unsigned int total = (unsigned int)P.d[0] * P.d[1] * P.d[2] * P.d[3];
@@ -547,9 +592,9 @@ __global__ void dot_partial_kernel(const DotProblem* __restrict__ probs, int blo
   const int pi = blockIdx.x / blocks_per;
   const int bi = blockIdx.x % blocks_per;
   const DotProblem P = probs[pi];
-  if (P.active && *P.active == 0) return;
+  if (P.active && *gview(P.active) == 0) return;
   double s = 0.0;
-  for (long e = (long)bi * 256 + threadIdx.x; e < P.len; e += (long)blocks_per * 256) s += P.X[e] * P.Y[e];
+  for (long e = (long)bi * 256 + threadIdx.x; e < P.len; e += (long)blocks_per * 256) s += gview(P.X)[e] * gview(P.Y)[e];
   __shared__ double red[256];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -565,12 +610,13 @@ __global__ void dot_final_kernel(const DotProblem* __restrict__ probs, int n_pro
   const int pi = blockIdx.x * blockDim.x + threadIdx.x;
   if (pi >= n_prob) return;
   const DotProblem P = probs[pi];
-  if (P.active && *P.active == 0) return;
+  if (P.active && *gview(P.active) == 0) return;
   double s = 0.0;
   for (int b = 0; b < blocks_per; ++b) s += partial[pi * blocks_per + b];
   double v = P.alpha * s;
-  if (P.beta != 0.0) v += P.beta * (*P.out);
-  *P.out = v;
+  const gptr<double> out = gview(P.out);
+  if (P.beta != 0.0) v += P.beta * (*out);
+  *out = v;
 }
 
 // ------------------------------------------------------------------ launchers

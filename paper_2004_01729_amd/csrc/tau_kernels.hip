@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "gmem.h"
 #include "tau_kernels.h"
 
 namespace ftcc {
@@ -94,7 +95,8 @@ __device__ void weights(const PanelRule& R, double D, double h, Weights<M>& w, b
 
 // orbital-energy difference of element e of a t1 (rank 2, [i][a]) or t2
 // (rank 4, [i][j][a][b]) segment
-__device__ __forceinline__ double seg_delta(const double* eps, int n, int rank, long e) {
+__device__ __forceinline__ double seg_delta(const double* eps_ptr, int n, int rank, long e) {
+  const gptr<const double> eps = gview(eps_ptr);
   if (rank == 2) {
     const int a = (int)(e % n), i = (int)(e / n);
     return eps[a] - eps[i];
@@ -132,7 +134,7 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
     if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
   }
   const TauProblem& P = probs[lo];
-  if (P.active && *P.active == 0) return;   // converged instance of a batch: left unchanged
+  if (P.active && *gview(P.active) == 0) return;   // converged instance of a batch: left unchanged
   const PanelRule& R = *rule;
   constexpr int m = M;
   const long base = (long)(b - prefix[lo]) * 1024;
@@ -140,28 +142,28 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
   for (int u = 0; u < 4; ++u) {
     const long ei = base + u * 256 + threadIdx.x;
     if (ei >= P.len) break;
-    const long e = P.idx ? (long)P.idx[ei] : ei;   // element offset in the segment
-    const double sb = P.sb ? P.sb[e] : 0.0;
+    const long e = P.idx ? (long)gview(P.idx)[ei] : ei;   // element offset in the segment
+    const double sb = P.sb ? gview(P.sb)[e] : 0.0;
     double Sv[M];
     bool any = (sb != 0.0);
     for (int y = 0; y < m; ++y) {
-      Sv[y] = P.S[y] ? P.S[y][e] : 0.0;
+      Sv[y] = P.S[y] ? gview(P.S[y])[e] : 0.0;
       any = any || (Sv[y] != 0.0);
     }
     if (mode == TAU_LSTEP) {
       for (int x = 0; x < m; ++x) {
-        const double nv = -P.R[x][e];
-        mchg = nan_max(mchg, fabs(nv - P.s[x][e]));
+        const double nv = -gview(P.R[x])[e];
+        mchg = nan_max(mchg, fabs(nv - gview(P.s[x])[e]));
         mval = nan_max(mval, fabs(nv));
-        P.s[x][e] = nv;
+        gview(P.s[x])[e] = nv;
       }
       continue;
     }
     if (mode == TAU_BETA) {
       double Rv[M];
-      bool anyb = any || (P.lam_a && P.lam_a[e] != 0.0);
+      bool anyb = any || (P.lam_a && gview(P.lam_a)[e] != 0.0);
       for (int y = 0; y < m; ++y) {
-        Rv[y] = P.R[y][e];
+        Rv[y] = gview(P.R[y])[e];
         anyb = anyb || (Rv[y] != 0.0);
       }
       if (!anyb) continue;
@@ -177,54 +179,54 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
         double f = (sb != 0.0) ? -w.Ee * sb : 0.0;
         for (int y = 0; y < m; ++y)
           if (Rv[y] != 0.0) f += w.We[y] * Rv[y];
-        acc += P.lam_a[e] * f;
+        acc += gview(P.lam_a)[e] * f;
       }
       continue;
     }
     if (!any) {
       // structurally zero (dropped slots, or zero start): outputs stay zero
       if (mode == TAU_INIT || mode == TAU_LAMT) {
-        for (int x = 0; x < m; ++x) P.s[x][e] = 0.0;
+        for (int x = 0; x < m; ++x) gview(P.s[x])[e] = 0.0;
       } else if (mode == TAU_STEP) {
         for (int x = 0; x < m; ++x) {
-          mchg = nan_max(mchg, fabs(P.s[x][e]));
-          P.s[x][e] = 0.0;
+          mchg = nan_max(mchg, fabs(gview(P.s[x])[e]));
+          gview(P.s[x])[e] = 0.0;
         }
       } else {
-        P.out[e] = 0.0;
+        gview(P.out)[e] = 0.0;
       }
       continue;
     }
     Weights<M> w;
     weights<M>(R, delta_of(P, e), P.h, w, false, mode != TAU_INIT && mode != TAU_STEP);
     if (mode == TAU_INIT) {
-      for (int x = 0; x < m; ++x) P.s[x][e] = (sb != 0.0) ? w.E[x] * sb : 0.0;
+      for (int x = 0; x < m; ++x) gview(P.s[x])[e] = (sb != 0.0) ? w.E[x] * sb : 0.0;
     } else if (mode == TAU_STEP) {
       for (int x = 0; x < m; ++x) {
         double v = (sb != 0.0) ? w.E[x] * sb : 0.0;
         for (int y = 0; y < m; ++y)
           if (Sv[y] != 0.0) v -= w.W[x][y] * Sv[y];
-        mchg = nan_max(mchg, fabs(v - P.s[x][e]));
+        mchg = nan_max(mchg, fabs(v - gview(P.s[x])[e]));
         mval = nan_max(mval, fabs(v));
-        P.s[x][e] = v;
+        gview(P.s[x])[e] = v;
       }
     } else if (mode == TAU_END) {
       double v = (sb != 0.0) ? w.Ee * sb : 0.0;
       for (int y = 0; y < m; ++y)
         if (Sv[y] != 0.0) v -= w.We[y] * Sv[y];
-      P.out[e] = v;
+      gview(P.out)[e] = v;
     } else if (mode == TAU_LAMT) {
       for (int x = 0; x < m; ++x) {
         double v = (sb != 0.0) ? w.We[x] * sb : 0.0;
         for (int y = 0; y < m; ++y)
           if (Sv[y] != 0.0) v += w.W[y][x] * Sv[y];
-        P.s[x][e] = v;
+        gview(P.s[x])[e] = v;
       }
     } else if (mode == TAU_APREV) {
       double v = (sb != 0.0) ? w.Ee * sb : 0.0;
       for (int x = 0; x < m; ++x)
         if (Sv[x] != 0.0) v += w.E[x] * Sv[x];
-      P.out[e] = v;
+      gview(P.out)[e] = v;
     }
   }
   // block reductions
@@ -251,7 +253,7 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
       if (threadIdx.x < s) r0[threadIdx.x] += r0[threadIdx.x + s];
       __syncthreads();
     }
-    if (threadIdx.x == 0) P.partial[b - prefix[lo]] = r0[0];
+    if (threadIdx.x == 0) gview(P.partial)[b - prefix[lo]] = r0[0];
   }
 }
 
@@ -285,21 +287,21 @@ __global__ void __launch_bounds__(256) rk_combine_kernel(const RKProblem* __rest
     if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
   }
   const RKProblem& P = probs[lo];
-  if (P.active && *P.active == 0) return;   // uniform per block, before the barrier
+  if (P.active && *gview(P.active) == 0) return;   // uniform per block, before the barrier
   const long first = (long)(b - prefix[lo]) * 1024;
   double vmax = 0.0;
   for (int u = 0; u < 4; ++u) {
     const long ei = first + u * 256 + threadIdx.x;
     if (ei >= P.len) break;
-    const long e = P.idx ? (long)P.idx[ei] : ei;
+    const long e = P.idx ? (long)gview(P.idx)[ei] : ei;
     const double d = seg_delta(P.eps, P.n, P.rank, e);
-    double v = P.base ? P.x0 * P.base[e] : 0.0;
+    double v = P.base ? P.x0 * gview(P.base)[e] : 0.0;
     for (int l = 0; l < P.nst; ++l) {
-      const double y = P.Y[l] ? P.Y[l][e] : 0.0;
-      const double sv = P.S[l] ? P.S[l][e] : 0.0;
+      const double y = P.Y[l] ? gview(P.Y[l])[e] : 0.0;
+      const double sv = P.S[l] ? gview(P.S[l])[e] : 0.0;
       v += P.coef[l] * (-d * y + P.sigma * sv);
     }
-    P.out[e] = v;
+    gview(P.out)[e] = v;
     vmax = nan_max(vmax, fabs(v));
   }
   if (!P.maxbits) return;   // uniform per launch problem
