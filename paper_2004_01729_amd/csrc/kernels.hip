@@ -185,10 +185,15 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
   // section together and then both in their loads and stores with the matrix
   // pipe idle.  The scheduling groups below spread the memory instructions
   // between the MFMAs instead.
-  auto kstep = [&](auto cur_c, int it) {
+  auto kstep = [&](auto cur_c, auto live_c, int it) {
     constexpr int CUR = decltype(cur_c)::value;
     const int kn = kbeg + (it + 1) * BK;
     load_tiles(kn);
+    if constexpr (!decltype(live_c)::value) {   // a wave with no output in the tile: loads, stores, barrier
+      store_tiles(As[CUR ^ 1], Bs[CUR ^ 1], kn);
+      __syncthreads();
+      return;
+    }
     const double* as = As[CUR] + abase;
     const double* bs = Bs[CUR] + bbase;
     double af[2][FM], bf[2][FN];
@@ -213,18 +218,20 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     }
     store_tiles(As[CUR ^ 1], Bs[CUR ^ 1], kn);
     // Instruction order (MFMA slot u = 0 .. T-1): the first k group's fragment
-    // reads, then after each MFMA at most one global load of the next step (first
-    // slots), one fragment read of the next k group (second half of each group),
-    // one LDS store of the next step's operands (last group only, long after
-    // their loads were issued).  Masks: 0x008 MFMA, 0x020 VMEM read, 0x100 DS
-    // read, 0x200 DS write.
+    // reads, then after each MFMA at most one global load of the next step (every
+    // other slot of the first 2 (LA + LB) when the step has room for that before
+    // its stores, else the first LA + LB slots), one fragment read of the next k
+    // group (second half of each group), one LDS store of the next step's operands
+    // (last group only, long after their loads were issued).  Masks: 0x008 MFMA,
+    // 0x020 VMEM read, 0x100 DS read, 0x200 DS write.
     {
       constexpr int MG = FM * FN, T = MG * KG, NV = LA + LB, NW = LA + LB;
+      constexpr bool spread = T >= 2 * NV + NW;
       __builtin_amdgcn_sched_group_barrier(0x100, FM + FN, 0);
 #pragma unroll
       for (int u = 0; u < T; ++u) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        if (u < NV) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        if (spread ? (u < 2 * NV && (u % 2) == 0) : (u < NV)) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
         if (u < T - MG && (u % MG) >= MG - (FM + FN)) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
         if (u >= T - NW) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
       }
@@ -237,11 +244,23 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     __syncthreads();
   }
   // The last step's loads read clamped (valid) addresses and its stores fill the
-  // buffer that is no longer read.
-  for (int it = 0; it < nk; it += 2) {
-    kstep(std::integral_constant<int, 0>{}, it);
-    if (it + 1 < nk) kstep(std::integral_constant<int, 1>{}, it + 1);
-  }
+  // buffer that is no longer read.  A wave whose 64x64 part of the tile lies
+  // wholly outside C (edge tiles of a matrix that is not a multiple of the tile)
+  // takes its share of the loads, stores and barriers but issues no MFMAs, which
+  // leaves the matrix pipe to the other wave on its SIMD.  Both marches pass the
+  // same barriers; the flag is made wave-uniform (a scalar branch), so a wave runs
+  // exactly one of them.
+  const int live = __builtin_amdgcn_readfirstlane((m0 + wm * WM < M && n0 + wn * WN < N) ? 1 : 0);
+  auto march = [&](auto live_c) {
+    for (int it = 0; it < nk; it += 2) {
+      kstep(std::integral_constant<int, 0>{}, live_c, it);
+      if (it + 1 < nk) kstep(std::integral_constant<int, 1>{}, live_c, it + 1);
+    }
+  };
+  if (live)
+    march(std::true_type{});
+  else
+    march(std::false_type{});
 
   // epilogue
   if (kseg >= 0) {   // partial tile of a tail segment, summed by gemm_tail_reduce
