@@ -214,7 +214,8 @@ int ftcc_find_mu(ftcc_ctx* ctx, const double* n_target, double* mu_inout, const 
 
 /* One evaluation of the kernels E, S1, S2 (eqn:E, eqn:ccS1, eqn:ccS2) of instance
  * `inst` at the given amplitudes and the thermal integrals of (mu, beta):
- * t1, S1 n*n; t2, S2 n^4; E scalar. */
+ * t1, S1 n*n; t2, S2 n^4; E scalar.  With momentum labels, amplitudes with
+ * nonzero elements that the labels forbid are rejected (FTCC_EINVAL). */
 int ftcc_eval_residual(ftcc_ctx* ctx, int inst, double mu, double beta, const double* t1, const double* t2,
                        double* S1, double* S2, double* E);
 

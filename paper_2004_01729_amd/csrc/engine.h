@@ -160,7 +160,8 @@ class Executor {
   // permuted copy of a constant.  const_grads lists constants whose gradients
   // the backward list must produce.
   // cache_alloc(count) (may be empty) provides buffers for reused permuted copies of
-  // value operands, up to cache_budget bytes in total.
+  // value operands, up to cache_budget bytes in total; it may return nullptr (no
+  // room), and the operand is then permuted into scratch at each use instead.
   void build(const Program* prog, const std::vector<ProblemRef>& probs, Binder bind, Scratch* scratch,
              std::function<double*(int inst, size_t count)> const_alloc, bool want_backward,
              const std::vector<int>& const_grads, std::function<double*(size_t)> cache_alloc = nullptr,
@@ -195,6 +196,10 @@ class Executor {
   double gemm_flops_forward() const;
   double gemm_flops_backward() const;
   int n_launches_forward() const { return (int)fwd_.size(); }
+  // device bytes taken by the cached permuted copies of value operands and by the
+  // permuted copies of constants
+  size_t cache_bytes() const { return cache_bytes_; }
+  size_t const_copy_bytes() const { return const_bytes_; }
 
  private:
   using PerProb = std::vector<double*>;
@@ -234,7 +239,7 @@ class Executor {
   std::map<std::pair<int, std::string>, CacheEntry> value_cache_;
   std::vector<int> version_;
   std::function<double*(size_t)> cache_alloc_;
-  size_t cache_budget_ = 0, cache_bytes_ = 0;
+  size_t cache_budget_ = 0, cache_bytes_ = 0, const_bytes_ = 0;
   std::vector<Launch> setup_, fwd_, bwd_;
   std::vector<void*> owned_;
   KernelProfiler* prof_ = nullptr;

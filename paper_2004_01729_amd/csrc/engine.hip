@@ -222,7 +222,10 @@ Executor::PerProb Executor::const_permuted(int tensor, const PerProb& X, const s
   std::map<int, double*> per_inst;
   for (int p = 0; p < np; ++p) {
     const int inst = probs_[p].inst;
-    if (!per_inst.count(inst)) per_inst[inst] = const_alloc_(inst, (size_t)ipow(probs_[p].n, (int)xi.size()));
+    if (!per_inst.count(inst)) {
+      per_inst[inst] = const_alloc_(inst, (size_t)ipow(probs_[p].n, (int)xi.size()));
+      const_bytes_ += sizeof(double) * (size_t)ipow(probs_[p].n, (int)xi.size());
+    }
     Y[p] = per_inst[inst];
   }
   // one permute per instance: restrict to the first problem of each instance
@@ -270,8 +273,15 @@ Executor::PerProb Executor::value_permuted(std::vector<Launch>& dst, int tensor,
       perm(dst, X, xi, scratch, yi, 1.0, 0.0, nullptr, tag);
       return scratch;
     }
-    cache_bytes_ += bytes;
-    for (int p = 0; p < np; ++p) Y.push_back(cache_alloc_((size_t)ipow(probs_[p].n, (int)xi.size())));
+    for (int p = 0; p < np; ++p) {
+      double* q = cache_alloc_((size_t)ipow(probs_[p].n, (int)xi.size()));
+      if (!q) {   // no room: uncached (buffers taken for earlier problems stay unused)
+        perm(dst, X, xi, scratch, yi, 1.0, 0.0, nullptr, tag);
+        return scratch;
+      }
+      cache_bytes_ += sizeof(double) * (size_t)ipow(probs_[p].n, (int)xi.size());
+      Y.push_back(q);
+    }
   }
   perm(dst, X, xi, Y, yi, 1.0, 0.0, nullptr, tag + "(cached)");
   value_cache_[k] = CacheEntry{Y, version_[tensor]};

@@ -453,6 +453,13 @@ void trace_mem(ftcc_ctx* c, const char* stage) {
   std::fflush(stderr);
 }
 
+void trace_executor(ftcc_ctx* c, const char* which, const Executor& ex) {
+  if (!trace_on()) return;
+  std::fprintf(stderr, "[ftcc] %s executor built: %.2f GiB held (cached operand copies %.2f GiB, permuted constants %.2f GiB)\n",
+               which, c->bytes / 1073741824.0, ex.cache_bytes() / 1073741824.0, ex.const_copy_bytes() / 1073741824.0);
+  std::fflush(stderr);
+}
+
 void sync(ftcc_ctx* c) {
   FTCC_HIP(hipStreamSynchronize(c->stream));
   if (c->prof.enabled) c->prof.harvest();
@@ -502,6 +509,8 @@ void thermal_setup(ftcc_ctx* c, int i) {
     b.wv = I.wv;
     b.dwo = b.dwv = nullptr;
     b.out = I.blk[kG[k]];
+    b.idx = I.d_allowed[1];   // with momentum labels: the allowed elements (the law of t2)
+    b.count = I.n_allowed[1];
     launch_block(b, c->stream);
   }
   hipLaunchKernelGGL(meanfield_kernel, dim3(1), dim3(256), 0, c->stream, n, I.eps, I.h, I.eri, I.occ, I.fock, I.mu,
@@ -547,6 +556,8 @@ void deriv_setup(ftcc_ctx* c, int i, int which, const double* d_dh, const double
     b.dwo = (which < 2) ? I.dwo : nullptr;
     b.dwv = (which < 2) ? I.dwv : nullptr;
     b.out = I.dblk[kG[k]];
+    b.idx = I.d_allowed[1];
+    b.count = I.n_allowed[1];
     launch_block(b, c->stream);
   }
   FTCC_HIP(hipGetLastError());
@@ -910,7 +921,21 @@ void build(ftcc_ctx* c) {
     fail(FTCC_EINVAL, "unbound tensor " + d.name);
   };
   auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
-  auto vcache = [c](size_t count) { return c->dalloc(count); };
+  // Reused permuted copies of value operands are optional: one is taken only while
+  // it leaves a reserve for what the executors must still allocate (the second
+  // executor's intermediates and permuted constants: 16 n^4 doubles per instance,
+  // plus 1 GiB), and an allocation that fails leaves the operand uncached.
+  double reserve = 1073741824.0;
+  for (int i = 0; i < B; ++i) reserve += 16.0 * std::pow((double)c->inst[i].n, 4) * sizeof(double);
+  auto vcache = [c, reserve](size_t count) -> double* {
+    if (c->available() < reserve + (double)count * sizeof(double)) return nullptr;
+    try {
+      return c->dalloc(count);
+    } catch (const Fail& f) {
+      if (f.code != FTCC_ENOMEM) throw;
+      return nullptr;
+    }
+  };
   // reuse budget for permuted operand copies: a quarter of the memory still available
   // (the blocked contractions address their operands in place: no permuted copies)
   const size_t budget = mom ? 0 : (size_t)(c->available() / 4);
@@ -922,10 +947,12 @@ void build(ftcc_ctx* c) {
   if (mom) c->ex_main->set_momentum(by_inst);
   c->ex_main->build(&prog, probs, bind_main, &c->scratch, calloc_, true, ugrads, vcache, budget);
   c->ex_main->set_profiler(&c->prof);
+  trace_executor(c, "main", *c->ex_main);
   c->ex_d.reset(new Executor());
   if (mom) c->ex_d->set_momentum(by_inst);
   c->ex_d->build(&prog, probs, bind_d, &c->scratch, calloc_, false, {}, vcache, budget / 2);
   c->ex_d->set_profiler(&c->prof);
+  trace_executor(c, "derivative", *c->ex_d);
   trace_mem(c, "executors");
   // no kernel-profiler events inside the autotuner or a graph capture
   const bool prof_on = c->prof.enabled;
@@ -980,6 +1007,21 @@ void dcopy(ftcc_ctx* c, double* dst, const double* src, long count) {
   FTCC_HIP(hipMemcpyAsync(dst, src, sizeof(double) * count, hipMemcpyDeviceToDevice, c->stream));
 }
 
+// Copy of one node state of instance i (t1 block, then t2 block).  With momentum
+// labels only the allowed elements move: every state buffer keeps its forbidden
+// elements at zero (buffers start zeroed and no kernel of the blocked path
+// writes them), so the rest of the copy would move zeros onto zeros.
+void node_copy(ftcc_ctx* c, int i, double* dst, const double* src) {
+  const Instance& I = c->inst[i];
+  if (!I.d_allowed[0] || !I.d_allowed[1]) {
+    dcopy(c, dst, src, node_len(c, i));
+    return;
+  }
+  launch_copy_listed(I.d_allowed[0], I.n_allowed[0], I.d_allowed[1], I.n_allowed[1], (long)I.n * I.n, src, dst,
+                     c->stream);
+  FTCC_HIP(hipGetLastError());
+}
+
 // forward residuals of every node of the panel slots (node amplitudes -> S, E)
 void forward(ftcc_ctx* c) {
   if (c->slots == c->m) {
@@ -988,11 +1030,11 @@ void forward(ftcc_ctx* c) {
   }
   for (int x = 0; x < c->m; ++x) {
     for (int i = 0; i < c->B; ++i)
-      if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+      if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
     run_fwd_slots(c);
     for (int i = 0; i < c->B; ++i) {
       if (!c->run_host[i]) continue;
-      dcopy(c, c->S[i * c->m + x], c->s_S[i], node_len(c, i));
+      node_copy(c, i, c->S[i * c->m + x], c->s_S[i]);
       dcopy(c, c->e[i * c->m + x], c->s_e[i], 1);
     }
   }
@@ -1007,13 +1049,13 @@ void backward(ftcc_ctx* c) {
   }
   for (int x = 0; x < c->m; ++x) {
     for (int i = 0; i < c->B; ++i)
-      if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+      if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
     run_fwd_slots(c);
     c->resid_evals += n_running(c);
     for (int i = 0; i < c->B; ++i) {
       if (!c->run_host[i]) continue;
       const int p = i * c->m + x;
-      dcopy(c, c->s_cot[i], c->cot[p], node_len(c, i));
+      node_copy(c, i, c->s_cot[i], c->cot[p]);
       dcopy(c, c->s_ebar[i], c->ebar[p], 1);
     }
     run_bwd_slots(c);
@@ -1021,7 +1063,7 @@ void backward(ftcc_ctx* c) {
       if (!c->run_host[i]) continue;
       const int p = i * c->m + x;
       const long n = c->inst[i].n;
-      dcopy(c, c->gr[p], c->s_gr[i], node_len(c, i));
+      node_copy(c, i, c->gr[p], c->s_gr[i]);
       for (int k = 0; k < 4; ++k) dcopy(c, c->ugrad[p][k], c->s_ugrad[i][k], n * n);
     }
   }
@@ -1034,10 +1076,10 @@ void d_forward(ftcc_ctx* c) {
     return;
   }
   for (int x = 0; x < c->m; ++x) {
-    for (int i = 0; i < c->B; ++i) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    for (int i = 0; i < c->B; ++i) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
     c->ex_d->run_forward(c->stream);
     for (int i = 0; i < c->B; ++i) {
-      dcopy(c, c->dS[i * c->m + x], c->s_dS[i], node_len(c, i));
+      node_copy(c, i, c->dS[i * c->m + x], c->s_dS[i]);
       dcopy(c, c->de[i * c->m + x], c->s_de[i], 1);
     }
   }
@@ -1332,12 +1374,12 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
 // stage x of every running instance: amp[x] -> S[x], e[x]
 void forward_one(ftcc_ctx* c, int x) {
   for (int i = 0; i < c->B; ++i)
-    if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
   run_fwd_slots(c);
   c->resid_evals += n_running(c);
   for (int i = 0; i < c->B; ++i) {
     if (!c->run_host[i]) continue;
-    dcopy(c, c->S[i * c->m + x], c->s_S[i], node_len(c, i));
+    node_copy(c, i, c->S[i * c->m + x], c->s_S[i]);
     dcopy(c, c->e[i * c->m + x], c->s_e[i], 1);
   }
 }
@@ -1345,14 +1387,14 @@ void forward_one(ftcc_ctx* c, int x) {
 // reverse pass of stage x (tape recomputed first): cot[x], ebar[x] -> gr[x], ugrad[x]; also S[x]
 void backward_one(ftcc_ctx* c, int x) {
   for (int i = 0; i < c->B; ++i)
-    if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
   run_fwd_slots(c);
   c->resid_evals += n_running(c);
   for (int i = 0; i < c->B; ++i) {
     if (!c->run_host[i]) continue;
     const int q = i * c->m + x;
-    dcopy(c, c->S[q], c->s_S[i], node_len(c, i));
-    dcopy(c, c->s_cot[i], c->cot[q], node_len(c, i));
+    node_copy(c, i, c->S[q], c->s_S[i]);
+    node_copy(c, i, c->s_cot[i], c->cot[q]);
     dcopy(c, c->s_ebar[i], c->ebar[q], 1);
   }
   run_bwd_slots(c);
@@ -1361,7 +1403,7 @@ void backward_one(ftcc_ctx* c, int x) {
     if (!c->run_host[i]) continue;
     const int q = i * c->m + x;
     const long n = c->inst[i].n;
-    dcopy(c, c->gr[q], c->s_gr[i], node_len(c, i));
+    node_copy(c, i, c->gr[q], c->s_gr[i]);
     for (int k = 0; k < 4; ++k) dcopy(c, c->ugrad[q][k], c->s_ugrad[i][k], n * n);
   }
 }
@@ -1369,11 +1411,11 @@ void backward_one(ftcc_ctx* c, int x) {
 // derivative-integral residual of stage x: amp[x] -> dS[x], de[x]
 void d_forward_one(ftcc_ctx* c, int x) {
   for (int i = 0; i < c->B; ++i)
-    if (c->run_host[i]) dcopy(c, c->s_amp[i], c->amp[i * c->m + x], node_len(c, i));
+    if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
   c->ex_d->run_forward(c->stream);
   for (int i = 0; i < c->B; ++i) {
     if (!c->run_host[i]) continue;
-    dcopy(c, c->dS[i * c->m + x], c->s_dS[i], node_len(c, i));
+    node_copy(c, i, c->dS[i * c->m + x], c->s_dS[i]);
     dcopy(c, c->de[i * c->m + x], c->s_de[i], 1);
   }
 }
@@ -1473,7 +1515,7 @@ double rk_a(const ftcc_ctx* c, int j, int l) { return c->rk_a[j * c->m + l]; }
 void rk_stage_state(ftcc_ctx* c, int p, int x) {
   if (x == 0) {
     for (int i = 0; i < c->B; ++i)
-      if (c->run_host[i]) dcopy(c, c->amp[i * c->m], c->inst[i].sb[p], node_len(c, i));
+      if (c->run_host[i]) node_copy(c, i, c->amp[i * c->m], c->inst[i].sb[p]);
     return;
   }
   rk_combine(c, 0, p, x, -1.0, false, [c, p, x](int i) {
@@ -1586,7 +1628,7 @@ void rk_lambda(ftcc_ctx* c, std::vector<int>& status) {
   set_ebar(c, 0, P);
   backward_one(c, 0);
   for (int i = 0; i < B; ++i)
-    if (ok[i]) dcopy(c, c->inst[i].abuf[P], c->gr[i * m], node_len(c, i));
+    if (ok[i]) node_copy(c, i, c->inst[i].abuf[P], c->gr[i * m]);
   for (int p = P - 1; p >= 0; --p) {
     rk_recompute_stages(c, p);
     for (int x = m - 1; x >= 0; --x) {
@@ -1782,8 +1824,8 @@ void gamma_node(ftcc_ctx* c, int x) {
   for (int i = 0; i < c->B; ++i) {
     if (!c->run_host[i]) continue;
     const int q = i * c->m + x;
-    dcopy(c, c->s_amp[i], c->amp[q], node_len(c, i));
-    dcopy(c, c->s_cot[i], c->cot[q], node_len(c, i));
+    node_copy(c, i, c->s_amp[i], c->amp[q]);
+    node_copy(c, i, c->s_cot[i], c->cot[q]);
     dcopy(c, c->s_ebar[i], c->ebar[q], 1);
   }
   gamma_pass(c);
@@ -2316,6 +2358,13 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
           d.Y = c->dS[q];
           d.out = c->inst[i].acc + slot;
           d.len = n * n + n * n * n * n;
+          if (c->inst[i].d_allowed[0]) {   // momentum labels: the allowed elements only
+            d.ia = c->inst[i].d_allowed[0];
+            d.na = c->inst[i].n_allowed[0];
+            d.ib = c->inst[i].d_allowed[1];
+            d.nb = c->inst[i].n_allowed[1];
+            d.second = n * n;
+          }
           d.alpha = 1.0;
           d.beta = 1.0;
           ds.push_back(d);
@@ -2561,6 +2610,10 @@ int ftcc_eval_residual(ftcc_ctx* c, int i, double mu, double beta, const double*
       FTCC_HIP(hipMemcpyAsync(c->amp[i * c->m + x], t1, sizeof(double) * n2, hipMemcpyHostToDevice, c->stream));
       FTCC_HIP(
           hipMemcpyAsync(c->amp[i * c->m + x] + n2, t2, sizeof(double) * n4, hipMemcpyHostToDevice, c->stream));
+    }
+    if (I.d_allowed[0]) {   // the blocked path keeps every forbidden element of a state at zero
+      check_momentum(c, i, c->amp[i * c->m], 2, "t1");
+      check_momentum(c, i, c->amp[i * c->m] + n2, 4, "t2");
     }
     forward(c);
     const int q = i * c->m;

@@ -54,6 +54,12 @@ struct DotProblem {
   long len;
   double alpha, beta;
   const int* active;     // optional run flag (0: skip, *out keeps its value)
+  // optional element lists: with ia set the sum runs over the offsets ia[0..na)
+  // and second + ib[0..nb) (the other elements are zero in X or Y) instead of [0, len)
+  const unsigned* ia;
+  long na;
+  const unsigned* ib;
+  long nb, second;
 };
 
 // Tail split of a grouped GEMM launch.  The tiles of a launch run in waves of

@@ -484,14 +484,23 @@ __global__ void __launch_bounds__(256) dotb_partial_kernel(const DotbProblem* __
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
-__global__ void dotb_final_kernel(const DotbProblem* __restrict__ probs, int n_prob, const double* partial) {
-  const int pi = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pi >= n_prob) return;
-  const DotbProblem& P = probs[pi];
-  if (P.active && *gview(P.active) == 0) return;
+// One block per problem: strided sums of its block partials, then a tree in LDS
+// (a fixed order: deterministic).
+__global__ void __launch_bounds__(256) dotb_final_kernel(const DotbProblem* __restrict__ probs, int n_prob,
+                                                         const double* partial) {
+  const DotbProblem& P = probs[blockIdx.x];
+  if (P.active && *gview(P.active) == 0) return;   // uniform per block, before the barriers
   double s = 0.0;
-  for (int b = 0; b < P.n_blocks; ++b) s += partial[P.first_block + b];
-  double v = P.alpha * s;
+  for (int b = threadIdx.x; b < P.n_blocks; b += 256) s += gview(partial)[P.first_block + b];
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  double v = P.alpha * red[0];
   const gptr<double> out = gview(P.out);
   if (P.beta != 0.0) v += P.beta * (*out);
   *out = v;
@@ -613,7 +622,16 @@ __global__ void dot_partial_kernel(const DotProblem* __restrict__ probs, int blo
   const DotProblem P = probs[pi];
   if (P.active && *gview(P.active) == 0) return;
   double s = 0.0;
-  for (long e = (long)bi * 256 + threadIdx.x; e < P.len; e += (long)blocks_per * 256) s += gview(P.X)[e] * gview(P.Y)[e];
+  if (P.ia) {
+    const long cnt = P.na + P.nb;
+    for (long t = (long)bi * 256 + threadIdx.x; t < cnt; t += (long)blocks_per * 256) {
+      const long e = t < P.na ? (long)gview(P.ia)[t] : P.second + (long)gview(P.ib)[t - P.na];
+      s += gview(P.X)[e] * gview(P.Y)[e];
+    }
+  } else {
+    for (long e = (long)bi * 256 + threadIdx.x; e < P.len; e += (long)blocks_per * 256)
+      s += gview(P.X)[e] * gview(P.Y)[e];
+  }
   __shared__ double red[256];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -748,8 +766,7 @@ void launch_dotb(const DotbProblem* d_probs, int n_prob, const ElemTask* d_tasks
   if (blocks > 0 && n_tasks > 0)
     hipLaunchKernelGGL(dotb_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_probs, d_tasks, n_tasks, total,
                        partial);
-  hipLaunchKernelGGL(dotb_final_kernel, dim3((n_prob + 63) / 64), dim3(64), 0, s, d_probs, n_prob,
-                     (const double*)partial);
+  hipLaunchKernelGGL(dotb_final_kernel, dim3(n_prob), dim3(256), 0, s, d_probs, n_prob, (const double*)partial);
 }
 
 void launch_permute(const PermProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,

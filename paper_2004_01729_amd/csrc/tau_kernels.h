@@ -85,6 +85,12 @@ struct RKProblem {
 // blocks: 1024 elements each, per problem
 void launch_rk_combine(const RKProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks, hipStream_t s);
 
+// dst[o] = src[o] for the element offsets o of a node state listed in a (the t1
+// block, na entries) and, shifted by `second`, in b (the t2 block, nb entries):
+// the copy of a node state whose other elements are zero in both buffers.
+void launch_copy_listed(const unsigned* a, long na, const unsigned* b, long nb, long second, const double* src,
+                        double* dst, hipStream_t s);
+
 // Thermal quantities of one instance.
 struct ThermalProblem {
   int n;
@@ -114,6 +120,10 @@ struct BlockSpec {
   const double* dwo;   // may be nullptr
   const double* dwv;
   double* out;
+  // optional list of the elements to compute (the others stay as they are: zero);
+  // rank 4 only
+  const unsigned* idx = nullptr;
+  long count = 0;
 };
 void launch_block(const BlockSpec& b, hipStream_t s);
 

@@ -320,6 +320,23 @@ void launch_rk_combine(const RKProblem* d_probs, const int* d_prefix, int n_prob
   hipLaunchKernelGGL(rk_combine_kernel, dim3(total_blocks), dim3(256), 0, s, d_probs, d_prefix, n_prob);
 }
 
+__global__ void __launch_bounds__(256) copy_listed_kernel(const unsigned* __restrict__ a, long na,
+                                                          const unsigned* __restrict__ b, long nb, long second,
+                                                          const double* __restrict__ src, double* __restrict__ dst) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= na + nb) return;
+  const long off = e < na ? (long)gview(a)[e] : second + (long)gview(b)[e - na];
+  gview(dst)[off] = gview(src)[off];
+}
+
+void launch_copy_listed(const unsigned* a, long na, const unsigned* b, long nb, long second, const double* src,
+                        double* dst, hipStream_t s) {
+  const long total = na + nb;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(copy_listed_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, a, na, b, nb,
+                     second, src, dst);
+}
+
 // ------------------------------------------------------------------ thermal quantities
 __global__ void occ_kernel(ThermalProblem P) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -397,8 +414,9 @@ void launch_u_from_fock(int n, const double* fock, const double* eps, double* u,
 // ------------------------------------------------------------------ weighted blocks
 __global__ void block_kernel(BlockSpec B) {
   const long len = (B.rank == 4) ? (long)B.n * B.n * B.n * B.n : (long)B.n * B.n;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= len) return;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (B.idx ? B.count : len)) return;
+  const long e = B.idx ? (long)gview(B.idx)[t] : t;
   int idx[4];
   long r = e;
   for (int k = B.rank - 1; k >= 0; --k) {
@@ -428,7 +446,8 @@ __global__ void block_kernel(BlockSpec B) {
 }
 
 void launch_block(const BlockSpec& b, hipStream_t s) {
-  const long len = (b.rank == 4) ? (long)b.n * b.n * b.n * b.n : (long)b.n * b.n;
+  const long len = b.idx ? b.count : (b.rank == 4) ? (long)b.n * b.n * b.n * b.n : (long)b.n * b.n;
+  if (len <= 0) return;
   hipLaunchKernelGGL(block_kernel, dim3((len + 255) / 256), dim3(256), 0, s, b);
 }
 

@@ -113,3 +113,43 @@ def test_labels_that_break_the_integrals_are_refused(F):
     with pytest.raises(F.FTCCError, match="forbid"):
         ctx.solve(s.mu, s.beta)
     ctx.close()
+
+
+def test_amplitudes_that_break_the_labels_are_refused(F):
+    """The blocked path keeps every momentum-forbidden element of a state at zero;
+    caller amplitudes with a forbidden nonzero are rejected, not silently kept."""
+    s = fi.hubbard_config(L=6, U=4.0, T=1.0)
+    a1, a2 = _allowed(s)
+    t1, t2 = fi.random_amplitudes(s.n, seed=7, scale=0.1)
+    t1, t2 = t1 * a1, t2 * a2
+    print("[momentum] forbidden amplitude elements are refused", flush=True)
+    ctx = _ctx(F, [s], n_tau=4, nodes_per_panel=4)
+    ctx.eval_residual(0, s.mu, s.beta, t1, t2)
+    bad = t2.copy()
+    bad[tuple(np.argwhere(~a2)[0])] = 0.01
+    with pytest.raises(F.FTCCError, match="forbid") as e:
+        ctx.eval_residual(0, s.mu, s.beta, t1, bad)
+    assert e.value.code == F.EINVAL
+    ctx.close()
+
+
+def test_one_slot_schedule_blocked(F, monkeypatch):
+    """The one-slot schedule moves node states in and out of the executor's slot
+    over the momentum-allowed elements only; Omega and the mu, beta and h
+    gradients equal those of the schedule with one slot per node."""
+    s = fi.hubbard_config(L=6, U=4.0, T=1.0)
+    out = []
+    for slots in ("all", "1"):
+        monkeypatch.setenv("FTCC_NODE_SLOTS", slots)
+        print(f"[momentum] hubbard L=6 schedule slots={slots}", flush=True)
+        ctx = _ctx(F, [s], n_tau=8, nodes_per_panel=4, tol=1e-14)
+        ctx.solve(s.mu, s.beta)
+        om, _ = ctx.grand_potential()
+        ctx.lam()
+        r = ctx.response(want_mu=True, want_beta=True, want_h=True)
+        ctx.close()
+        out.append((om[0], r["mu"][0], r["beta"][0], r["h"][0]))
+    (o0, m0, b0, h0), (o1, m1, b1, h1) = out
+    assert abs(o0 - o1) < 1e-12 * abs(o0)
+    assert abs(m0 - m1) < 1e-10 * max(1.0, abs(m0)) and abs(b0 - b1) < 1e-10 * max(1.0, abs(b0))
+    assert np.abs(h0 - h1).max() < 1e-10
