@@ -1,7 +1,8 @@
 // C ABI of the FT-CCSD hot path: context, thermal set-up, forward march,
-// Lambda adjoint and response derivatives.  All arithmetic runs in the HIP
-// kernels of this directory; the host only sequences launches and tests the
-// convergence flags.
+// Lambda adjoint and response derivatives (the differential form's march is in
+// rk_march.hip, the two-body response density in density.hip; the shared state
+// and helpers in api_internal.h).  All arithmetic runs in the HIP kernels of this
+// directory; the host only sequences launches and tests the convergence flags.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,101 +24,11 @@
 #include "kernels.h"
 #include "tau_kernels.h"
 #include "util.h"
-
-using namespace ftcc;
+#include "api_internal.h"
 
 namespace {
 
 thread_local std::string g_err;
-
-struct Fail {
-  int code;
-  std::string msg;
-};
-
-[[noreturn]] void fail(int code, const std::string& msg) { throw Fail{code, msg}; }
-
-const char* kU[4] = {"u_oo", "u_ov", "u_vo", "u_vv"};
-const char* kG[12] = {"g_oooo", "g_ooov", "g_oovo", "g_oovv", "g_ovov", "g_ovvo",
-                      "g_ovvv", "g_vovv", "g_vvvv", "g_vvvo", "g_ovoo", "g_vvoo"};
-
-// Gauss-Legendre nodes and weights on [0, 1] (Newton on P_m)
-void gauss_legendre(int m, double* c, double* b) {
-  for (int i = 0; i < m; ++i) {
-    double x = std::cos(M_PI * (i + 0.75) / (m + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1.0, p1 = x;
-      for (int k = 2; k <= m; ++k) {
-        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      double pm = (m == 1) ? x : p1;
-      double pm1 = (m == 1) ? 1.0 : p0;
-      double dp = m * (x * pm - pm1) / (x * x - 1.0);
-      double dx = pm / dp;
-      x -= dx;
-      if (std::fabs(dx) < 1e-17) break;
-    }
-    double p0 = 1.0, p1 = x;
-    for (int k = 2; k <= m; ++k) {
-      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-      p0 = p1;
-      p1 = p2;
-    }
-    double pm = (m == 1) ? x : p1, pm1 = (m == 1) ? 1.0 : p0;
-    double dp = m * (x * pm - pm1) / (x * x - 1.0);
-    c[m - 1 - i] = 0.5 * (x + 1.0);
-    b[m - 1 - i] = 1.0 / ((1.0 - x * x) * dp * dp);   // 2/((1-x^2)P'^2) on [-1,1], halved
-  }
-}
-
-PanelRule make_rule(int m, int lawson) {
-  PanelRule R;
-  std::memset(&R, 0, sizeof(R));
-  R.m = m;
-  R.lawson = lawson;
-  gauss_legendre(m, R.c, R.b);
-  for (int y = 0; y < m; ++y) {
-    // l_y(u) = prod_{j != y} (u - c_j) / (c_y - c_j) as monomial coefficients
-    double poly[kMaxNodes + 1] = {0};
-    poly[0] = 1.0;
-    int deg = 0;
-    for (int j = 0; j < m; ++j) {
-      if (j == y) continue;
-      const double den = R.c[y] - R.c[j];
-      double nw[kMaxNodes + 1] = {0};
-      for (int k = 0; k <= deg; ++k) {
-        nw[k + 1] += poly[k] / den;
-        nw[k] -= poly[k] * R.c[j] / den;
-      }
-      ++deg;
-      std::memcpy(poly, nw, sizeof(nw));
-    }
-    for (int k = 0; k < m; ++k) R.lc[y][k] = poly[k];
-  }
-  for (int x = 0; x < m; ++x)
-    for (int y = 0; y < m; ++y) {
-      double a = 0.0, p = R.c[x];
-      for (int k = 0; k < m; ++k) {
-        a += R.lc[y][k] * p / (k + 1);
-        p *= R.c[x];
-      }
-      R.A[x][y] = a;
-    }
-  for (int x = 0; x <= m; ++x) {
-    const double cx = (x < m) ? R.c[x] : 1.0;
-    for (int y = 0; y < m; ++y) {
-      double p = cx, f = 1.0;   // c_x^(k+1), k!
-      for (int k = 0; k < m; ++k) {
-        R.gc[x][y][k] = R.lc[y][k] * p * f;
-        p *= cx;
-        f *= (k + 1);
-      }
-    }
-  }
-  return R;
-}
 
 // ------------------------------------------------------------------ mean-field kernel
 // out[0] Omega_0, out[1] Omega_1, out[2] d(Omega_0+Omega_1)/dmu, out[3] .../dbeta,
@@ -203,51 +114,6 @@ __global__ void dh_assemble_kernel(int n, const double* occ, const double* wo, c
   out[e] = v;
 }
 
-// Two-body response density Gamma_abcd = dOmega/d<ab|cd> at a frozen reference:
-//   sum over the 12 weighted blocks of w_a w_b w_c w_d G^XYZW_abcd
-//   + g gc_ac n_b delta_bd - gc_ad n_b delta_bc          (through the Fock operator in u)
-//   + (g/2) (g delta_ac delta_bd - delta_ad delta_bc) n_a n_b   (Omega_1)
-// with gc_pq = sum_XY w^X_p w^Y_q U^XY_pq, projected on the integrals with
-// <ab|cd> = <ba|dc> (the average of the element and its exchange partner).
-struct GammaBlocks {
-  const double* G[12];
-  char pat[12][4];
-  const double* U[4];
-  char upat[4][2];
-};
-__device__ double gamma_raw(const GammaBlocks& B, int n, const double* occ, const double* wo, const double* wv,
-                            double g, int a, int b, int c, int d) {
-  const long e = (((long)a * n + b) * n + c) * n + d;
-  const int idx[4] = {a, b, c, d};
-  double v = 0.0;
-  for (int k = 0; k < 12; ++k) {
-    double w = 1.0;
-    for (int s = 0; s < 4; ++s) w *= (B.pat[k][s] == 'o') ? wo[idx[s]] : wv[idx[s]];
-    if (w != 0.0) v += w * B.G[k][e];
-  }
-  auto gc = [&](int p, int q) {
-    double x = 0.0;
-    for (int k = 0; k < 4; ++k) {
-      const double w = ((B.upat[k][0] == 'o') ? wo[p] : wv[p]) * ((B.upat[k][1] == 'o') ? wo[q] : wv[q]);
-      if (w != 0.0) x += w * B.U[k][(long)p * n + q];
-    }
-    return x;
-  };
-  if (b == d) v += g * gc(a, c) * occ[b];
-  if (b == c) v -= gc(a, d) * occ[b];
-  if (a == c && b == d) v += 0.5 * g * g * occ[a] * occ[b];
-  if (a == d && b == c) v -= 0.5 * g * occ[a] * occ[b];
-  return v;
-}
-__global__ void gamma_assemble_kernel(GammaBlocks B, int n, const double* occ, const double* wo, const double* wv,
-                                      double g, double* out) {
-  const long total = (long)n * n * n * n;
-  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
-    const int d = (int)(e % n), c = (int)((e / n) % n), b = (int)((e / n / n) % n), a = (int)(e / n / n / n);
-    out[e] = 0.5 * (gamma_raw(B, n, occ, wo, wv, g, a, b, c, d) + gamma_raw(B, n, occ, wo, wv, g, b, a, d, c));
-  }
-}
-
 // Elements of a one-body (rank 2, law k_p = k_q) or two-body (rank 4,
 // k_p + k_q = k_r + k_s) array that are nonzero although momentum forbids them;
 // any such element sets *bad (plain stores of the same value).
@@ -281,128 +147,92 @@ __global__ void zero_u64_kernel(unsigned long long* p, int count) {
 
 }  // namespace
 
-// ------------------------------------------------------------------ context
-struct Instance {
-  int n = 0;
-  bool has_ham = false;
-  double mu = 0.0, beta = 1.0;
-  double *h = nullptr, *eri = nullptr, *eps = nullptr;
-  std::vector<double> eps_host;
-  InstMomentum mom;                // dims == 0: no momentum labels
-  unsigned* d_allowed[2] = {nullptr, nullptr};   // momentum-allowed elements of the t1 / t2 segments
-  long n_allowed[2] = {0, 0};
-  int* d_labels = nullptr;         // device copies for the conservation checks
-  int* d_modulus = nullptr;
-  double *occ = nullptr, *wo = nullptr, *wv = nullptr, *fock = nullptr;
-  double *dn = nullptr, *dwo = nullptr, *dwv = nullptr, *du_raw = nullptr, *u_raw = nullptr;
-  std::map<std::string, double*> blk, dblk;
-  std::vector<double*> grid, resid, sb, lam, abuf;
-  double* mf = nullptr;          // meanfield outputs (5)
-  double* acc = nullptr;         // response accumulators: [0] mu, [1] beta, [2] theta, [3] beta grid
-  std::vector<double> energies;  // per node
-  double omega0 = 0, omega1 = 0, omega_cc = 0;
-  int iters = 0, status = 0, lam_iters = 0, lam_status = 0;
-  double* ugrad_acc[4] = {nullptr, nullptr, nullptr, nullptr};
-  double* rk_tmp[2] = {nullptr, nullptr};   // differential form: reverse-pass temporaries
-  double* gacc[12] = {};                    // two-body density: accumulated gradients of the 12 weighted blocks
-  double* rk_hbar = nullptr;                // d Omega_CC / d(step) at fixed integrals
-};
+namespace ftcc {
+namespace host {
 
-struct ftcc_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  hipStream_t own_stream = nullptr;
-  ftcc_options opt;
-  int B = 0, m = 4, P = 4;
-  PanelRule rule;
-  PanelRule* d_rule = nullptr;
-  std::vector<Instance> inst;
-  std::vector<void*> allocs;
-  Program prog;
-  std::unique_ptr<Executor> ex_main, ex_d, ex_g;   // ex_g: integral gradients (built on first use)
-  std::map<std::pair<int, int>, double*> g_derived, g_cgrad;   // (tensor, problem) buffers of ex_g
-  bool built = false, solved = false, have_lambda = false;
-  // per node (instance * m + x): amplitudes, residuals, energies, gradients, cotangents
-  std::vector<double*> amp, S, e, gr, cot, ebar, dS, de;
-  // per executor slot (instance * slots + slot); the same pointers as the node
-  // buffers when every node of a panel has its own slot (slots == m)
-  int slots = 0;
-  std::vector<double*> s_amp, s_S, s_e, s_gr, s_cot, s_ebar, s_dS, s_de;
-  std::vector<std::array<double*, 4>> s_ugrad;
-  std::map<std::pair<int, int>, double*> inter, inter_grad, dderived;   // (tensor, problem) / (tensor, inst)
-  std::map<std::pair<int, int>, double*> derived;
-  std::vector<std::array<double*, 4>> ugrad;
-  Scratch scratch;
-  unsigned long long* d_maxbits = nullptr;    // [B][2]
-  double* d_partial = nullptr;                // TAU_BETA partial sums
-  std::vector<int> tau_prefix_host;
-  int* d_active = nullptr;                    // [B] propagator step flags
-  int* d_run = nullptr;                       // [B] residual-program run flags (executor gate)
-  std::vector<int> run_host;                  // host copy of d_run
-  KernelProfiler prof;
-  hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
-  std::vector<int> beta_part_off;             // first TAU_BETA partial of each instance
-  std::vector<int> active_host;               // per-instance "still iterating" flags
-  std::map<std::pair<int, int>, std::pair<TauProblem*, int*>> tau_cache;
-  std::map<std::pair<int, int>, std::pair<int, int>> tau_shape;   // (n_prob, blocks)
-  // DIIS state: per instance `depth` stored iterates X and residuals R (m * len each)
-  std::vector<std::vector<double*>> diis_X, diis_R;
-  std::vector<int> diis_count, diis_next;
-  double* d_gram = nullptr;     // [B][D][D]
-  double* d_coef = nullptr;     // [B][D]
-  int* d_dcount = nullptr;      // [B]
-  int* d_dnewest = nullptr;     // [B]
-  long resid_evals = 0, vjp_evals = 0;
-  double t_solve = 0.0, t_lambda = 0.0;
-  size_t bytes = 0;
-  // differential form (propagator >= 2): explicit Runge-Kutta with m = stages,
-  // P = n_tau steps; tableau a (row-major m x m, strictly lower) and b
-  bool rk = false;
-  double gdeg = 2.0;                          // electrons per orbital and occupation: 2 restricted, 1 spin orbitals
-  std::vector<double> rk_a, rk_b;
-  double* d_rkw = nullptr;                    // [P + 1] Simpson weight / beta of each grid point
-  int* d_bad = nullptr;                       // flag of the conservation-law checks
-  std::map<std::tuple<int, int, int>, std::pair<RKProblem*, int*>> rk_cache;
-  std::map<std::tuple<int, int, int>, int> rk_blocks;
-  std::map<std::tuple<int, int, int>, DotProblem*> rk_dots;
-  ftcc_alloc_fn ualloc = nullptr;   // caller's device memory supplier (or hipMalloc)
-  ftcc_free_fn ufree = nullptr;
-  void* uuser = nullptr;
+[[noreturn]] void fail(int code, const std::string& msg) { throw Fail{code, msg}; }
 
-  double* dalloc(size_t count) {
-    void* p = nullptr;
-    // 256-byte granules keep every buffer aligned for 16-byte vector loads
-    const size_t nb = (std::max<size_t>(count, 1) * sizeof(double) + 255) / 256 * 256;
-    if (opt.mem_cap_bytes && bytes + nb > opt.mem_cap_bytes)
-      fail(FTCC_ENOMEM, "allocation of " + std::to_string(nb) + " bytes would exceed mem_cap_bytes (" +
-                            std::to_string(bytes) + " bytes already held)");
-    if (ualloc) {
-      p = ualloc(nb, uuser);
-      if (!p) fail(FTCC_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(nb) + " bytes");
-    } else if (hipMalloc(&p, nb) != hipSuccess) {
-      (void)hipGetLastError();
-      fail(FTCC_ENOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed (" + std::to_string(bytes) +
-                            " bytes already held)");
+const char* kU[4] = {"u_oo", "u_ov", "u_vo", "u_vv"};
+const char* kG[12] = {"g_oooo", "g_ooov", "g_oovo", "g_oovv", "g_ovov", "g_ovvo",
+                      "g_ovvv", "g_vovv", "g_vvvv", "g_vvvo", "g_ovoo", "g_vvoo"};
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton on P_m)
+void gauss_legendre(int m, double* c, double* b) {
+  for (int i = 0; i < m; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (m + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= m; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pm = (m == 1) ? x : p1;
+      double pm1 = (m == 1) ? 1.0 : p0;
+      double dp = m * (x * pm - pm1) / (x * x - 1.0);
+      double dx = pm / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-17) break;
     }
-    // every buffer starts zeroed: momentum-blocked contractions write only the
-    // allowed blocks of their outputs and rely on the forbidden elements being 0
-    if (hipMemset(p, 0, nb) != hipSuccess) fail(FTCC_EDEVICE, "hipMemset of a new buffer failed");
-    bytes += nb;
-    allocs.push_back(p);
-    return (double*)p;
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= m; ++k) {
+      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double pm = (m == 1) ? x : p1, pm1 = (m == 1) ? 1.0 : p0;
+    double dp = m * (x * pm - pm1) / (x * x - 1.0);
+    c[m - 1 - i] = 0.5 * (x + 1.0);
+    b[m - 1 - i] = 1.0 / ((1.0 - x * x) * dp * dp);   // 2/((1-x^2)P'^2) on [-1,1], halved
   }
+}
 
-  // device memory this context may still take: free memory, bounded by the cap
-  double available() {
-    size_t free_b = 0, total_b = 0;
-    FTCC_HIP(hipMemGetInfo(&free_b, &total_b));
-    double a = (double)free_b;
-    if (opt.mem_cap_bytes) a = std::min(a, (double)opt.mem_cap_bytes - (double)bytes);
-    return std::max(a, 0.0);
+PanelRule make_rule(int m, int lawson) {
+  PanelRule R;
+  std::memset(&R, 0, sizeof(R));
+  R.m = m;
+  R.lawson = lawson;
+  gauss_legendre(m, R.c, R.b);
+  for (int y = 0; y < m; ++y) {
+    // l_y(u) = prod_{j != y} (u - c_j) / (c_y - c_j) as monomial coefficients
+    double poly[kMaxNodes + 1] = {0};
+    poly[0] = 1.0;
+    int deg = 0;
+    for (int j = 0; j < m; ++j) {
+      if (j == y) continue;
+      const double den = R.c[y] - R.c[j];
+      double nw[kMaxNodes + 1] = {0};
+      for (int k = 0; k <= deg; ++k) {
+        nw[k + 1] += poly[k] / den;
+        nw[k] -= poly[k] * R.c[j] / den;
+      }
+      ++deg;
+      std::memcpy(poly, nw, sizeof(nw));
+    }
+    for (int k = 0; k < m; ++k) R.lc[y][k] = poly[k];
   }
-};
-
-namespace {
+  for (int x = 0; x < m; ++x)
+    for (int y = 0; y < m; ++y) {
+      double a = 0.0, p = R.c[x];
+      for (int k = 0; k < m; ++k) {
+        a += R.lc[y][k] * p / (k + 1);
+        p *= R.c[x];
+      }
+      R.A[x][y] = a;
+    }
+  for (int x = 0; x <= m; ++x) {
+    const double cx = (x < m) ? R.c[x] : 1.0;
+    for (int y = 0; y < m; ++y) {
+      double p = cx, f = 1.0;   // c_x^(k+1), k!
+      for (int k = 0; k < m; ++k) {
+        R.gc[x][y][k] = R.lc[y][k] * p * f;
+        p *= cx;
+        f *= (k + 1);
+      }
+    }
+  }
+  return R;
+}
 
 long ipow(long n, int r) {
   long v = 1;
@@ -1234,7 +1064,6 @@ void diis_reset(ftcc_ctx* c) {
   for (int i = 0; i < c->B; ++i) c->diis_count[i] = c->diis_next[i] = 0;
 }
 
-using NodeBufs = std::function<double*(int inst, int x)>;
 
 void diis_before(ftcc_ctx* c, const NodeBufs& it, const std::vector<bool>& active) {
   for (int i = 0; i < c->B; ++i) {
@@ -1361,476 +1190,8 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
   return its;
 }
 
-
-// ------------------------------------------------------------------ differential form
-// Algorithm alg:diff: ds/dtau = -(Delta s + S[s]) (eqn:smud) stepped across the
-// uniform grid tau_k = k h, h = beta / n_g, by an explicit Runge-Kutta method
-// (Section III: RK1, RK2, RK4 with Simpson's rule for Omega_CC).  The executor
-// has one slot per instance; "node" x of the node buffers is stage x of the
-// current step: amp[x] its state Y_x, S[x] its residual, gr[x] its reverse-pass
-// gradient.  Grid states s_k live in sb[k] (k = 0..n_g), their cotangents in
-// abuf[k], and the slope cotangents kbar of step p, stage x in lam[p m + x].
-
-// stage x of every running instance: amp[x] -> S[x], e[x]
-void forward_one(ftcc_ctx* c, int x) {
-  for (int i = 0; i < c->B; ++i)
-    if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
-  run_fwd_slots(c);
-  c->resid_evals += n_running(c);
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    node_copy(c, i, c->S[i * c->m + x], c->s_S[i]);
-    dcopy(c, c->e[i * c->m + x], c->s_e[i], 1);
-  }
-}
-
-// reverse pass of stage x (tape recomputed first): cot[x], ebar[x] -> gr[x], ugrad[x]; also S[x]
-void backward_one(ftcc_ctx* c, int x) {
-  for (int i = 0; i < c->B; ++i)
-    if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
-  run_fwd_slots(c);
-  c->resid_evals += n_running(c);
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    const int q = i * c->m + x;
-    node_copy(c, i, c->S[q], c->s_S[i]);
-    node_copy(c, i, c->s_cot[i], c->cot[q]);
-    dcopy(c, c->s_ebar[i], c->ebar[q], 1);
-  }
-  run_bwd_slots(c);
-  c->vjp_evals += n_running(c);
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    const int q = i * c->m + x;
-    const long n = c->inst[i].n;
-    node_copy(c, i, c->gr[q], c->s_gr[i]);
-    for (int k = 0; k < 4; ++k) dcopy(c, c->ugrad[q][k], c->s_ugrad[i][k], n * n);
-  }
-}
-
-// derivative-integral residual of stage x: amp[x] -> dS[x], de[x]
-void d_forward_one(ftcc_ctx* c, int x) {
-  for (int i = 0; i < c->B; ++i)
-    if (c->run_host[i]) node_copy(c, i, c->s_amp[i], c->amp[i * c->m + x]);
-  c->ex_d->run_forward(c->stream);
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    node_copy(c, i, c->dS[i * c->m + x], c->s_dS[i]);
-    dcopy(c, c->de[i * c->m + x], c->s_de[i], 1);
-  }
-}
-
-struct RKSpec {
-  const double* base = nullptr;
-  double x0 = 0.0;
-  int nst = 0;
-  double coef[kMaxStages] = {0.0, 0.0, 0.0, 0.0};
-  const double* Y[kMaxStages] = {nullptr, nullptr, nullptr, nullptr};
-  const double* S[kMaxStages] = {nullptr, nullptr, nullptr, nullptr};
-  double* out = nullptr;
-};
-
-// out = x0 base + sum_l coef_l (-Delta Y_l + sigma S_l) for every instance (both
-// amplitude segments); descriptors cached under (kind, step, stage) until the
-// next solve.  track: max |out| into maxbits[2 i + 1].
-void rk_combine(ftcc_ctx* c, int kind, int p, int x, double sigma, bool track,
-                const std::function<RKSpec(int)>& spec) {
-  const auto key = std::make_tuple(kind, p, x);
-  auto it = c->rk_cache.find(key);
-  if (it == c->rk_cache.end()) {
-    std::vector<RKProblem> ps;
-    std::vector<int> prefix;
-    int total = 0;
-    for (int i = 0; i < c->B; ++i) {
-      const RKSpec sp = spec(i);
-      const Instance& I = c->inst[i];
-      const long n2 = (long)I.n * I.n;
-      for (int seg = 0; seg < 2; ++seg) {
-        RKProblem r;
-        std::memset(&r, 0, sizeof(r));
-        const long off = seg ? n2 : 0;
-        r.eps = I.eps;
-        r.n = I.n;
-        r.rank = seg ? 4 : 2;
-        r.len = seg_len(c, i, seg);
-        r.idx = I.d_allowed[seg];
-        r.base = sp.base ? sp.base + off : nullptr;
-        r.x0 = sp.x0;
-        r.nst = sp.nst;
-        for (int l = 0; l < sp.nst; ++l) {
-          r.coef[l] = sp.coef[l];
-          r.Y[l] = sp.Y[l] ? sp.Y[l] + off : nullptr;
-          r.S[l] = sp.S[l] ? sp.S[l] + off : nullptr;
-        }
-        r.sigma = sigma;
-        r.out = sp.out + off;
-        r.maxbits = track ? c->d_maxbits + 2 * i + 1 : nullptr;
-        r.active = c->d_run + i;
-        prefix.push_back(total);
-        total += (int)((r.len + 1023) / 1024);
-        ps.push_back(r);
-      }
-    }
-    RKProblem* d_ps = nullptr;
-    int* d_pre = nullptr;
-    FTCC_HIP(hipMalloc((void**)&d_ps, sizeof(RKProblem) * ps.size()));
-    FTCC_HIP(hipMalloc((void**)&d_pre, sizeof(int) * prefix.size()));
-    FTCC_HIP(hipMemcpy(d_ps, ps.data(), sizeof(RKProblem) * ps.size(), hipMemcpyHostToDevice));
-    FTCC_HIP(hipMemcpy(d_pre, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice));
-    it = c->rk_cache.emplace(key, std::make_pair(d_ps, d_pre)).first;
-    c->rk_blocks[key] = total;
-  }
-  launch_rk_combine(it->second.first, it->second.second, 2 * c->B, c->rk_blocks[key], c->stream);
-  FTCC_HIP(hipGetLastError());
-}
-
-// acc_i += <X_i, Y_i> over whole amplitude vectors, one deterministic dot per instance
-void rk_dot(ftcc_ctx* c, int kind, int p, int x, const std::function<std::array<const double*, 3>(int)>& xyz) {
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    const auto key = std::make_tuple(kind * 65536 + i, p, x);
-    auto it = c->rk_dots.find(key);
-    if (it == c->rk_dots.end()) {
-      const auto v = xyz(i);
-      DotProblem d{};
-      d.X = v[0];
-      d.Y = v[1];
-      d.out = const_cast<double*>(v[2]);
-      d.len = node_len(c, i);
-      d.alpha = 1.0;
-      d.beta = 1.0;
-      DotProblem* dd = nullptr;
-      FTCC_HIP(hipMalloc((void**)&dd, sizeof(DotProblem)));
-      FTCC_HIP(hipMemcpy(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice));
-      it = c->rk_dots.emplace(key, dd).first;
-    }
-    launch_dot(it->second, 1, 64, c->scratch.dot_partial, c->stream);
-  }
-}
-
-double rk_h(const ftcc_ctx* c, int i) { return c->inst[i].beta / c->P; }
-double rk_a(const ftcc_ctx* c, int j, int l) { return c->rk_a[j * c->m + l]; }
-
-// stage state Y_x of step p: sb[p] + h sum_{l<x} a_xl k_l, k_l = -(Delta Y_l + S_l)
-void rk_stage_state(ftcc_ctx* c, int p, int x) {
-  if (x == 0) {
-    for (int i = 0; i < c->B; ++i)
-      if (c->run_host[i]) node_copy(c, i, c->amp[i * c->m], c->inst[i].sb[p]);
-    return;
-  }
-  rk_combine(c, 0, p, x, -1.0, false, [c, p, x](int i) {
-    RKSpec sp;
-    sp.base = c->inst[i].sb[p];
-    sp.x0 = 1.0;
-    for (int l = 0; l < x; ++l) {
-      sp.coef[sp.nst] = rk_h(c, i) * rk_a(c, x, l);
-      sp.Y[sp.nst] = c->amp[i * c->m + l];
-      sp.S[sp.nst] = c->S[i * c->m + l];
-      ++sp.nst;
-    }
-    sp.out = c->amp[i * c->m + x];
-    return sp;
-  });
-}
-
-// every stage state of step p with the residuals of stages 0..m-2 (the last
-// stage's residual comes from the tape of its reverse pass, or is evaluated by
-// the caller)
-void rk_recompute_stages(ftcc_ctx* c, int p) {
-  for (int x = 0; x < c->m; ++x) {
-    rk_stage_state(c, p, x);
-    if (x < c->m - 1) forward_one(c, x);
-  }
-}
-
-void set_ebar(ftcc_ctx* c, int x, int grid_point) {
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    double* e = c->ebar[i * c->m + x];
-    if (grid_point >= 0) dcopy(c, e, c->d_rkw + grid_point, 1);
-    else zero_d(c, e, 1);
-  }
-}
-
-void rk_solve(ftcc_ctx* c, std::vector<int>& status) {
-  const int B = c->B, m = c->m, P = c->P;
-  std::vector<double> ebuf((size_t)B * (P + 1), 0.0);
-  std::vector<bool> ok(B);
-  const auto wall0 = std::chrono::steady_clock::now();
-  auto energy_to_host = [&](int k) {
-    for (int i = 0; i < B; ++i)
-      if (c->run_host[i])
-        FTCC_HIP(hipMemcpyAsync(&ebuf[(size_t)i * (P + 1) + k], c->e[i * m], sizeof(double), hipMemcpyDeviceToHost,
-                                c->stream));
-  };
-  for (int p = 0; p < P; ++p) {
-    for (int i = 0; i < B; ++i) ok[i] = status[i] == 0;
-    set_run(c, ok);
-    for (int x = 0; x < m; ++x) {
-      rk_stage_state(c, p, x);
-      forward_one(c, x);
-      if (x == 0) energy_to_host(p);     // E at the grid point s_p = Y_0
-    }
-    reset_maxbits(c);
-    rk_combine(c, 1, p, 0, -1.0, true, [c, p](int i) {
-      RKSpec sp;
-      sp.base = c->inst[i].sb[p];
-      sp.x0 = 1.0;
-      for (int l = 0; l < c->m; ++l) {
-        sp.coef[sp.nst] = rk_h(c, i) * c->rk_b[l];
-        sp.Y[sp.nst] = c->amp[i * c->m + l];
-        sp.S[sp.nst] = c->S[i * c->m + l];
-        ++sp.nst;
-      }
-      sp.out = c->inst[i].sb[p + 1];
-      return sp;
-    });
-    const std::vector<double> mb = read_maxbits(c);
-    for (int i = 0; i < B; ++i)
-      if (status[i] == 0 && !std::isfinite(mb[2 * i + 1])) status[i] = FTCC_ENONFINITE;
-    trace(c, "forward (Runge-Kutta)", p + 1, P, std::vector<int>(1, m), wall0);
-  }
-  for (int i = 0; i < B; ++i) ok[i] = status[i] == 0;
-  set_run(c, ok);
-  rk_stage_state(c, P, 0);
-  forward_one(c, 0);
-  energy_to_host(P);
-  run_all(c);
-  sync(c);
-  for (int i = 0; i < B; ++i) {
-    Instance& I = c->inst[i];
-    double om = 0.0;
-    for (int k = 0; k <= P; ++k) {
-      I.energies[k] = ebuf[(size_t)i * (P + 1) + k];
-      om += ((k == 0 || k == P) ? 1.0 : (k % 2 ? 4.0 : 2.0)) / (3.0 * P) * I.energies[k];
-    }
-    I.omega_cc = status[i] == 0 ? om : std::nan("");
-    I.iters = P;
-  }
-}
-
-// Reverse-mode sweep: sbar_{n_g} = (g/beta) dE/ds(s_{n_g}); per step p (last first)
-//   kbar_x = h b_x sbar_{p+1} + h sum_{y>x} a_yx Z_y,  Z_y = -Delta kbar_y + J_S(Y_y)^T (-kbar_y)
-//   sbar_p = sbar_{p+1} + sum_x Z_x   (Z_0 carries (g_p/beta) dE/ds(s_p) as well)
-// and the explicit step-length term
-//   hbar += <sbar_{p+1}, sum_x b_x k_x> + sum_{x>0} <Z_x, sum_{l<x} a_xl k_l>.
-void rk_lambda(ftcc_ctx* c, std::vector<int>& status) {
-  const int B = c->B, m = c->m, P = c->P;
-  std::vector<bool> ok(B);
-  for (int i = 0; i < B; ++i) ok[i] = status[i] == 0;
-  set_run(c, ok);
-  for (int i = 0; i < B; ++i) zero_d(c, c->inst[i].rk_hbar, 1);
-  const auto wall0 = std::chrono::steady_clock::now();
-  // final grid point: only the energy term
-  rk_stage_state(c, P, 0);
-  for (int i = 0; i < B; ++i)
-    if (ok[i]) zero_d(c, c->cot[i * m], node_len(c, i));
-  set_ebar(c, 0, P);
-  backward_one(c, 0);
-  for (int i = 0; i < B; ++i)
-    if (ok[i]) node_copy(c, i, c->inst[i].abuf[P], c->gr[i * m]);
-  for (int p = P - 1; p >= 0; --p) {
-    rk_recompute_stages(c, p);
-    for (int x = m - 1; x >= 0; --x) {
-      rk_combine(c, 2, p, x, +1.0, false, [c, p, x](int i) {
-        RKSpec sp;
-        const Instance& I = c->inst[i];
-        const double h = rk_h(c, i);
-        sp.base = I.abuf[p + 1];
-        sp.x0 = h * c->rk_b[x];
-        for (int y = x + 1; y < c->m; ++y) {
-          if (rk_a(c, y, x) == 0.0) continue;
-          sp.coef[sp.nst] = h * rk_a(c, y, x);
-          sp.Y[sp.nst] = I.lam[p * c->m + y];
-          sp.S[sp.nst] = c->gr[i * c->m + y];
-          ++sp.nst;
-        }
-        sp.out = I.lam[p * c->m + x];
-        return sp;
-      });
-      rk_combine(c, 7, p, x, 0.0, false, [c, p, x](int i) {   // cotangent of S at the stage: -kbar
-        RKSpec sp;
-        sp.base = c->inst[i].lam[p * c->m + x];
-        sp.x0 = -1.0;
-        sp.out = c->cot[i * c->m + x];
-        return sp;
-      });
-      set_ebar(c, x, x == 0 ? p : -1);
-      backward_one(c, x);
-    }
-    rk_combine(c, 3, p, 0, +1.0, false, [c, p](int i) {
-      RKSpec sp;
-      const Instance& I = c->inst[i];
-      sp.base = I.abuf[p + 1];
-      sp.x0 = 1.0;
-      for (int x = 0; x < c->m; ++x) {
-        sp.coef[sp.nst] = 1.0;
-        sp.Y[sp.nst] = I.lam[p * c->m + x];
-        sp.S[sp.nst] = c->gr[i * c->m + x];
-        ++sp.nst;
-      }
-      sp.out = I.abuf[p];
-      return sp;
-    });
-    // explicit dependence on the step length
-    rk_combine(c, 4, p, 0, -1.0, false, [c](int i) {
-      RKSpec sp;
-      for (int l = 0; l < c->m; ++l) {
-        sp.coef[sp.nst] = c->rk_b[l];
-        sp.Y[sp.nst] = c->amp[i * c->m + l];
-        sp.S[sp.nst] = c->S[i * c->m + l];
-        ++sp.nst;
-      }
-      sp.out = c->inst[i].rk_tmp[0];
-      return sp;
-    });
-    rk_dot(c, 0, p, 0, [c, p](int i) {
-      const Instance& I = c->inst[i];
-      return std::array<const double*, 3>{I.abuf[p + 1], I.rk_tmp[0], I.rk_hbar};
-    });
-    for (int x = 1; x < m; ++x) {
-      rk_combine(c, 5, p, x, -1.0, false, [c, x](int i) {
-        RKSpec sp;
-        for (int l = 0; l < x; ++l) {
-          if (rk_a(c, x, l) == 0.0) continue;
-          sp.coef[sp.nst] = rk_a(c, x, l);
-          sp.Y[sp.nst] = c->amp[i * c->m + l];
-          sp.S[sp.nst] = c->S[i * c->m + l];
-          ++sp.nst;
-        }
-        sp.out = c->inst[i].rk_tmp[0];
-        return sp;
-      });
-      rk_combine(c, 6, p, x, +1.0, false, [c, p, x](int i) {
-        RKSpec sp;
-        const Instance& I = c->inst[i];
-        sp.nst = 1;
-        sp.coef[0] = 1.0;
-        sp.Y[0] = I.lam[p * c->m + x];
-        sp.S[0] = c->gr[i * c->m + x];
-        sp.out = I.rk_tmp[1];
-        return sp;
-      });
-      rk_dot(c, 1, p, x, [c](int i) {
-        const Instance& I = c->inst[i];
-        return std::array<const double*, 3>{I.rk_tmp[1], I.rk_tmp[0], I.rk_hbar};
-      });
-    }
-    if (trace_on()) {
-      sync(c);
-      trace(c, "lambda (Runge-Kutta)", P - p, P, std::vector<int>(1, m), wall0);
-    }
-  }
-  // a reverse pass that produced non-finite cotangents
-  reset_maxbits(c);
-  rk_combine(c, 8, 0, 0, 0.0, true, [c](int i) {
-    RKSpec sp;
-    sp.base = c->inst[i].abuf[0];
-    sp.x0 = 1.0;
-    sp.out = c->inst[i].rk_tmp[1];
-    return sp;
-  });
-  const std::vector<double> mb = read_maxbits(c);
-  for (int i = 0; i < B; ++i) {
-    if (status[i] == 0 && !std::isfinite(mb[2 * i + 1])) status[i] = FTCC_ENONFINITE;
-    c->inst[i].lam_iters = P;
-  }
-  run_all(c);
-}
-
-// ------------------------------------------------------------------ two-body density
-// A third executor of the same program whose reverse pass also yields the
-// gradients with respect to every constant block (the u and g blocks): the
-// constant combinations are evaluated inside the forward pass so that their
-// gradients reach the raw blocks.  Built on first use; its intermediates share
-// the main executor's buffers (the two never run interleaved).
-void build_gamma_executor(ftcc_ctx* c) {
-  if (c->ex_g) return;
-  const Program& prog = c->prog;
-  const int SL = c->slots;
-  std::vector<ProblemRef> probs;
-  for (int i = 0; i < c->B; ++i)
-    for (int x = 0; x < SL; ++x) probs.push_back({i, x, c->inst[i].n});
-  const int id_t1 = prog.id("t1"), id_t2 = prog.id("t2"), id_S1 = prog.id("S1"), id_S2 = prog.id("S2"),
-            id_E = prog.id("E");
-  auto buf = [c](std::map<std::pair<int, int>, double*>& store, int t, int key, long count) {
-    auto k = std::make_pair(t, key);
-    auto it = store.find(k);
-    if (it != store.end()) return it->second;
-    double* p = c->dalloc(count);
-    store[k] = p;
-    return p;
-  };
-  Binder bind = [&, c](int t, int p, bool grad) -> double* {
-    const TensorDecl& d = prog.t[t];
-    const int i = probs[p].inst;
-    const long n = probs[p].n, n2 = n * n, cnt = ipow(n, d.rank);
-    if (t == id_t1) return grad ? c->s_gr[p] : c->s_amp[p];
-    if (t == id_t2) return grad ? c->s_gr[p] + n2 : c->s_amp[p] + n2;
-    if (t == id_S1) return grad ? c->s_cot[p] : c->s_S[p];
-    if (t == id_S2) return grad ? c->s_cot[p] + n2 : c->s_S[p] + n2;
-    if (t == id_E) return grad ? c->s_ebar[p] : c->s_e[p];
-    if (d.kind == T_CONST) return grad ? buf(c->g_cgrad, t, p, cnt) : c->inst[i].blk[d.name];
-    if (d.derived) return buf(grad ? c->g_cgrad : c->g_derived, t, p, cnt);
-    return buf(grad ? c->inter_grad : c->inter, t, p, cnt);
-  };
-  std::vector<int> cgrads;
-  for (int k = 0; k < (int)prog.t.size(); ++k)
-    if (prog.t[k].kind == T_CONST) cgrads.push_back(k);
-  auto calloc_ = [c](int, size_t count) { return c->dalloc(count); };
-  auto vcache = [c](size_t count) { return c->dalloc(count); };
-  std::unique_ptr<Executor> ex(new Executor());
-  ex->set_inline_setup(true);
-  ex->set_gate(c->d_run, c->run_host.data());
-  if (momentum_on(c)) {
-    std::vector<const InstMomentum*> by_inst;
-    for (const Instance& I : c->inst) by_inst.push_back(&I.mom);
-    ex->set_momentum(by_inst);
-  }
-  ex->build(&prog, probs, bind, &c->scratch, calloc_, true, cgrads, vcache, 0);
-  c->ex_g = std::move(ex);
-  for (int i = 0; i < c->B; ++i) {
-    Instance& I = c->inst[i];
-    const long n2 = (long)I.n * I.n;
-    for (int k = 0; k < 12; ++k)
-      if (!I.gacc[k]) I.gacc[k] = c->dalloc(n2 * n2);
-  }
-}
-
-// forward + reverse pass of ex_g over the slots, then add the constant-block
-// gradients of every running slot to the instance accumulators (u blocks into
-// ugrad_acc, g blocks into gacc)
-void gamma_pass(ftcc_ctx* c) {
-  const Program& prog = c->prog;
-  c->ex_g->run_forward(c->stream);
-  c->ex_g->run_backward(c->stream);
-  const int SL = c->slots;
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    Instance& I = c->inst[i];
-    const long n2 = (long)I.n * I.n;
-    for (int x = 0; x < SL; ++x) {
-      const int q = i * SL + x;
-      for (int k = 0; k < 4; ++k)
-        launch_axpby(n2, 1.0, c->g_cgrad.at(std::make_pair(prog.id(kU[k]), q)), 1.0, I.ugrad_acc[k], c->stream);
-      for (int k = 0; k < 12; ++k)
-        launch_axpby(n2 * n2, 1.0, c->g_cgrad.at(std::make_pair(prog.id(kG[k]), q)), 1.0, I.gacc[k], c->stream);
-    }
-  }
-}
-
-// one node (or RK stage) x through the single slot
-void gamma_node(ftcc_ctx* c, int x) {
-  for (int i = 0; i < c->B; ++i) {
-    if (!c->run_host[i]) continue;
-    const int q = i * c->m + x;
-    node_copy(c, i, c->s_amp[i], c->amp[q]);
-    node_copy(c, i, c->s_cot[i], c->cot[q]);
-    dcopy(c, c->s_ebar[i], c->ebar[q], 1);
-  }
-  gamma_pass(c);
-}
-}  // namespace
+}  // namespace host
+}  // namespace ftcc
 
 // ------------------------------------------------------------------ ABI
 extern "C" {
@@ -2136,7 +1497,8 @@ int ftcc_get_amplitudes(ftcc_ctx* c, int i, int k, double* t1, double* t2) {
 
 }  // extern "C"
 
-namespace {
+namespace ftcc {
+namespace host {
 
 // Bring the converged amplitudes of panel p into the slots and evaluate the
 // forward program there (tape for the backward, residuals in S).
@@ -2162,7 +1524,8 @@ void load_panel(ftcc_ctx* c, int p) {
   }
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace ftcc
 
 extern "C" {
 
@@ -2507,91 +1870,6 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
   });
 }
 
-int ftcc_two_body_density(ftcc_ctx* c, double* gamma) {
-  return run_guarded([&] {
-    if (!c || !gamma) fail(FTCC_EINVAL, "null argument");
-    if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
-    FTCC_HIP(hipSetDevice(c->device));
-    build_gamma_executor(c);
-    const int B = c->B, m = c->m, P = c->P;
-    std::vector<bool> ok(B);
-    for (int i = 0; i < B; ++i) {
-      Instance& I = c->inst[i];
-      const long n2 = (long)I.n * I.n;
-      ok[i] = I.status == 0 && I.lam_status == 0;
-      for (int k = 0; k < 4; ++k) zero_d(c, I.ugrad_acc[k], n2);
-      for (int k = 0; k < 12; ++k) zero_d(c, I.gacc[k], n2 * n2);
-    }
-    const auto wall0 = std::chrono::steady_clock::now();
-    if (!c->rk) {
-      // every node: (g_x/beta) dE/dI + <lambda-tilde_x, dS/dI> through the reverse pass
-      for (int p = 0; p < P; ++p) {
-        load_panel(c, p);
-        set_run(c, ok);
-        tau_run(c, TAU_LAMT, p);
-        if (c->slots == m) {
-          gamma_pass(c);
-        } else {
-          for (int x = 0; x < m; ++x) gamma_node(c, x);
-        }
-        trace(c, "two-body density", p + 1, P, std::vector<int>(1, 0), wall0);
-      }
-    } else {
-      // every grid point (energy weight) and every stage (cotangent -kbar of its residual)
-      set_run(c, ok);
-      for (int k = 0; k <= P; ++k) {
-        const int ns = k < P ? m : 1;
-        if (k < P) rk_recompute_stages(c, k);
-        else rk_stage_state(c, P, 0);
-        for (int x = 0; x < ns; ++x) {
-          if (k < P) {
-            rk_combine(c, 7, k, x, 0.0, false, [c, k, x](int i) {
-              RKSpec sp;
-              sp.base = c->inst[i].lam[k * c->m + x];
-              sp.x0 = -1.0;
-              sp.out = c->cot[i * c->m + x];
-              return sp;
-            });
-          } else {
-            for (int i = 0; i < B; ++i)
-              if (ok[i]) zero_d(c, c->cot[i * m], node_len(c, i));
-          }
-          set_ebar(c, x, x == 0 ? k : -1);
-          gamma_node(c, x);
-        }
-      }
-    }
-    run_all(c);
-    long off = 0;
-    for (int i = 0; i < B; ++i) {
-      Instance& I = c->inst[i];
-      const long n = I.n, n4 = n * n * n * n;
-      if (!ok[i]) {
-        for (long e = 0; e < n4; ++e) gamma[off + e] = std::nan("");
-        off += n4;
-        continue;
-      }
-      GammaBlocks gb;
-      for (int k = 0; k < 12; ++k) {
-        gb.G[k] = I.gacc[k];
-        std::memcpy(gb.pat[k], kG[k] + 2, 4);
-      }
-      for (int k = 0; k < 4; ++k) {
-        gb.U[k] = I.ugrad_acc[k];
-        std::memcpy(gb.upat[k], kU[k] + 2, 2);
-      }
-      double* d = nullptr;
-      FTCC_HIP(hipMallocAsync((void**)&d, sizeof(double) * n4, c->stream));
-      hipLaunchKernelGGL(gamma_assemble_kernel, dim3((unsigned)std::min<long>((n4 + 255) / 256, 65536)), dim3(256), 0,
-                         c->stream, gb, (int)n, I.occ, I.wo, I.wv, c->gdeg, d);
-      FTCC_HIP(hipGetLastError());
-      FTCC_HIP(hipMemcpyAsync(gamma + off, d, sizeof(double) * n4, hipMemcpyDeviceToHost, c->stream));
-      FTCC_HIP(hipFreeAsync(d, c->stream));
-      off += n4;
-    }
-    sync(c);
-  });
-}
 
 int ftcc_eval_residual(ftcc_ctx* c, int i, double mu, double beta, const double* t1, const double* t2, double* S1,
                        double* S2, double* E) {
