@@ -90,6 +90,7 @@ struct Launch {
   int min_k = 0;                    // smallest K of the launch's GEMM problems
   void* d_tasks = nullptr;          // SGEMM / ELEM: task list
   int n_tasks = 0;
+  void* d_bfirst = nullptr;         // ELEM / DOTB: per 256-element block, the task of its first element
   void* d_red = nullptr;            // SGEMM: reductions of split inner ranges
   int n_red = 0;
   bool zero_fill = false;           // ELEM with alpha = beta = 0 (host copies kept for merging)

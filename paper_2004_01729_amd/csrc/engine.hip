@@ -107,6 +107,21 @@ void* Executor::upload(const void* host, size_t bytes) {
   return d;
 }
 
+// Task of the first element of every 256-element block of an element-task list
+// (the largest task index whose first element is at or before it), and the last
+// task after the final block: the kernels search only between two neighbours.
+static std::vector<int> block_first_tasks(const std::vector<ElemTask>& tasks, long long total) {
+  const long long nb = (total + 255) / 256;
+  std::vector<int> bf((size_t)nb + 1);
+  int t = 0;
+  for (long long b = 0; b < nb; ++b) {
+    while (t + 1 < (int)tasks.size() && tasks[t + 1].first <= b * 256) ++t;
+    bf[(size_t)b] = t;
+  }
+  bf[(size_t)nb] = tasks.empty() ? 0 : (int)tasks.size() - 1;
+  return bf;
+}
+
 // ------------------------------------------------------------------ lowering: permute / fill
 void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
                     const std::string& yi, double alpha, double beta, const std::vector<const double*>* scale,
@@ -822,6 +837,10 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
   L.d_desc = upload(ps.data(), sizeof(ElemProblem) * np);
   L.n_tasks = (int)tasks.size();
   L.d_tasks = upload(tasks.data(), sizeof(ElemTask) * std::max<size_t>(tasks.size(), 1));
+  {
+    const std::vector<int> bf = block_first_tasks(tasks, total);
+    L.d_bfirst = upload(bf.data(), sizeof(int) * bf.size());
+  }
   L.n_elem = total;
   if (alpha == 0.0 && beta == 0.0) {
     L.zero_fill = true;
@@ -887,6 +906,10 @@ bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std
   L.d_desc = upload(ps.data(), sizeof(DotbProblem) * np);
   L.n_tasks = (int)tasks.size();
   L.d_tasks = upload(tasks.data(), sizeof(ElemTask) * std::max<size_t>(tasks.size(), 1));
+  {
+    const std::vector<int> bf = block_first_tasks(tasks, total);
+    L.d_bfirst = upload(bf.data(), sizeof(int) * bf.size());
+  }
   L.n_elem = total;
   L.d_partial = scratch_->tail_ws;
   L.tag = tag + "(blocked dot)";
@@ -923,6 +946,8 @@ void Executor::merge_fills(std::vector<Launch>& L) {
     m.d_desc = upload(m.eprobs.data(), sizeof(ElemProblem) * m.eprobs.size());
     m.n_tasks = (int)m.etasks.size();
     m.d_tasks = upload(m.etasks.data(), sizeof(ElemTask) * std::max<size_t>(m.etasks.size(), 1));
+    const std::vector<int> bf = block_first_tasks(m.etasks, m.n_elem);
+    m.d_bfirst = upload(bf.data(), sizeof(int) * bf.size());
     m.total = (int)std::min<long long>((m.n_elem + 255) / 256, 1 << 30);
   }
   L = std::move(out);
@@ -1136,11 +1161,13 @@ void Executor::run(const std::vector<Launch>& L, hipStream_t s) const {
                      (const SgemmReduce*)l.d_red, l.n_red, s);
         break;
       case Launch::DOTB:
-        launch_dotb((const DotbProblem*)l.d_desc, l.n_prob, (const ElemTask*)l.d_tasks, l.n_tasks, l.n_elem,
+        launch_dotb((const DotbProblem*)l.d_desc, l.n_prob, (const ElemTask*)l.d_tasks, (const int*)l.d_bfirst,
+                    l.n_tasks, l.n_elem,
                     l.d_partial, s);
         break;
       case Launch::ELEM:
-        launch_elem((const ElemProblem*)l.d_desc, (const ElemTask*)l.d_tasks, l.n_tasks, l.n_elem, s);
+        launch_elem((const ElemProblem*)l.d_desc, (const ElemTask*)l.d_tasks, (const int*)l.d_bfirst, l.n_tasks,
+                    l.n_elem, s);
         break;
     }
   }

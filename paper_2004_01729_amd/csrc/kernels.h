@@ -137,7 +137,10 @@ struct ElemTask {
   int prob;
   int u0, ulen, v0, vlen;
 };
-void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, int n_tasks, long long total, hipStream_t s);
+// d_bfirst: per 256-element block the task of its first element, then the last
+// task (total / 256 rounded up, plus one entries)
+void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, const int* d_bfirst, int n_tasks,
+                 long long total, hipStream_t s);
 
 // Momentum-blocked full contraction: out = alpha * sum X[ox1[u] + ox2[v]] * Y[oy1[u] + oy2[v]]
 // + beta * out over the allowed elements (task list as for elem_kernel).  Each
@@ -156,8 +159,8 @@ struct DotbProblem {
   const int* active;
   int first_block, n_blocks;
 };
-void launch_dotb(const DotbProblem* d_probs, int n_prob, const ElemTask* d_tasks, int n_tasks, long long total,
-                 double* partial, hipStream_t s);
+void launch_dotb(const DotbProblem* d_probs, int n_prob, const ElemTask* d_tasks, const int* d_bfirst, int n_tasks,
+                 long long total, double* partial, hipStream_t s);
 
 void launch_splitk_reduce(const GemmProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks,
                           hipStream_t s);

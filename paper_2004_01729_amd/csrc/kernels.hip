@@ -430,13 +430,14 @@ __global__ void __launch_bounds__(256) sgemm_reduce_kernel(const SgemmProblem* _
 }
 
 // One thread per allowed element; the task is found by binary search over the
-// element prefix.
+// element prefix, between the tasks of this block's first element and of the
+// next block's (a few steps instead of a search of the whole list).
 __global__ void __launch_bounds__(256) elem_kernel(const ElemProblem* __restrict__ probs,
-                                                   const ElemTask* __restrict__ tasks, int n_tasks,
-                                                   long long total) {
+                                                   const ElemTask* __restrict__ tasks,
+                                                   const int* __restrict__ bfirst, long long total) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
-  int lo = 0, hi = n_tasks - 1;
+  int lo = gview(bfirst)[blockIdx.x], hi = gview(bfirst)[blockIdx.x + 1];
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (tasks[mid].first <= e) lo = mid; else hi = mid - 1;
@@ -456,12 +457,13 @@ __global__ void __launch_bounds__(256) elem_kernel(const ElemProblem* __restrict
 // Blocked dot: one thread per allowed element (padding threads add 0), then a
 // block sum per 256 elements; every thread reaches the barrier.
 __global__ void __launch_bounds__(256) dotb_partial_kernel(const DotbProblem* __restrict__ probs,
-                                                           const ElemTask* __restrict__ tasks, int n_tasks,
-                                                           long long total, double* __restrict__ partial) {
+                                                           const ElemTask* __restrict__ tasks,
+                                                           const int* __restrict__ bfirst, long long total,
+                                                           double* __restrict__ partial) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   double v = 0.0;
   if (e < total) {
-    int lo = 0, hi = n_tasks - 1;
+    int lo = gview(bfirst)[blockIdx.x], hi = gview(bfirst)[blockIdx.x + 1];
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (tasks[mid].first <= e) lo = mid; else hi = mid - 1;
@@ -753,19 +755,20 @@ void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_t
                        (const double*)ws);
 }
 
-void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, int n_tasks, long long total, hipStream_t s) {
+void launch_elem(const ElemProblem* d_probs, const ElemTask* d_tasks, const int* d_bfirst, int n_tasks,
+                 long long total, hipStream_t s) {
   if (n_tasks <= 0 || total <= 0) return;
-  hipLaunchKernelGGL(elem_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d_probs, d_tasks, n_tasks,
+  hipLaunchKernelGGL(elem_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d_probs, d_tasks, d_bfirst,
                      total);
 }
 
-void launch_dotb(const DotbProblem* d_probs, int n_prob, const ElemTask* d_tasks, int n_tasks, long long total,
-                 double* partial, hipStream_t s) {
+void launch_dotb(const DotbProblem* d_probs, int n_prob, const ElemTask* d_tasks, const int* d_bfirst, int n_tasks,
+                 long long total, double* partial, hipStream_t s) {
   if (n_prob <= 0) return;
   const long long blocks = (total + 255) / 256;
   if (blocks > 0 && n_tasks > 0)
-    hipLaunchKernelGGL(dotb_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_probs, d_tasks, n_tasks, total,
-                       partial);
+    hipLaunchKernelGGL(dotb_partial_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d_probs, d_tasks, d_bfirst,
+                       total, partial);
   hipLaunchKernelGGL(dotb_final_kernel, dim3(n_prob), dim3(256), 0, s, d_probs, n_prob, (const double*)partial);
 }
 
