@@ -47,3 +47,39 @@ def test_residual_n123_dense_equals_blocked():
     assert abs(de - be) < 1e-12 * max(1.0, abs(de))
     assert np.abs(d2[~allowed2]).max() < 1e-14 * scale2 and np.all(b2[~allowed2] == 0.0)
     assert np.abs(d2 - d2.transpose(1, 0, 3, 2)).max() < 1e-13 * scale2
+
+
+def test_full_configuration_context_fits():
+    """The 123-plane-wave context at the workload's full configuration (16 tau
+    nodes in 4 panels, checkpointing, occupation threshold 1e-6: about 278 GiB of
+    device memory, one executor slot, the permuted-operand caches stopped short
+    of a reserve) builds within HBM and evaluates the same residual as a
+    4-node context."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_01729_amd import ftcc as F
+    s = fi.ueg_config(123, 14, 4.0, 1.0)
+    n = s.n
+    lab = np.asarray(s.momentum[0])
+    base = 4 * int(np.abs(lab).max()) + 1
+    code = lambda v: (v[..., 0] * base + v[..., 1]) * base + v[..., 2]
+    pair = code(lab[:, None, :] + lab[None, :, :])
+    allowed2 = pair[:, :, None, None] == pair[None, None, :, :]
+    allowed1 = code(lab)[:, None] == code(lab)[None, :]
+    rng = np.random.default_rng(12)
+    t1 = rng.standard_normal((n, n)) * 0.02 * allowed1
+    t2 = rng.standard_normal((n,) * 4) * 0.02
+    t2 = 0.5 * (t2 + t2.transpose(1, 0, 3, 2))
+    t2 *= allowed2
+    out = []
+    for n_tau, extra in ((16, dict(checkpoint=1)), (4, {})):
+        print(f"[fullsize123] dense context n=123 n_tau={n_tau} {extra}", flush=True)
+        ctx = F.Context(1, n_tau=n_tau, nodes_per_panel=4, occ_thresh=1e-6, tol=1e-12, **extra)
+        ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+        out.append(ctx.eval_residual(0, s.mu, s.beta, t1, t2))
+        ctx.close()
+    (a1, a2, ae), (b1, b2, be) = out
+    assert np.abs(a1 - b1).max() < 1e-12 * max(1.0, np.abs(b1).max())
+    assert np.abs(a2 - b2).max() < 1e-12 * max(1.0, np.abs(b2).max())
+    assert abs(ae - be) < 1e-12 * max(1.0, abs(be))
