@@ -43,6 +43,8 @@ extern const char* kG[12];
 }  // namespace host
 }  // namespace ftcc
 
+// Included only by the three sources above, which name the kernels, the engine
+// and these helpers unqualified (never by a public header).
 using namespace ftcc;
 using namespace ftcc::host;
 
