@@ -256,6 +256,8 @@ class Executor {
     std::map<long long, std::pair<int, int>> blocks;   // packed momentum -> (first tuple, count)
   };
   std::map<std::string, GroupTable> group_cache_;
+  std::map<std::string, const unsigned*> out_tables_;   // output offset tables of GEMMs (device)
+  const unsigned* out_offsets(long n, const std::string& letters, const std::string& oi);
   void infer_laws();
   bool contract_blocked(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
                         const PerProb& A, const std::string& ai, const PerProb& B, const std::string& bi, bool acc,

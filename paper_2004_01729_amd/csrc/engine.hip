@@ -224,6 +224,30 @@ void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const 
   dst.push_back(L);
 }
 
+// Element offsets, in a tensor of layout `oi` (n per letter), of every index
+// tuple of `letters` (first letter most significant): the rows or columns of a
+// GEMM written straight into that tensor.  Built once per (n, letters, oi).
+const unsigned* Executor::out_offsets(long n, const std::string& letters, const std::string& oi) {
+  const std::string key = std::to_string(n) + ":" + letters + ":" + oi;
+  auto it = out_tables_.find(key);
+  if (it != out_tables_.end()) return it->second;
+  const int r = (int)letters.size(), ro = (int)oi.size();
+  std::vector<long> stride(r);
+  for (int k = 0; k < r; ++k) stride[k] = ipow(n, ro - 1 - (int)oi.find(letters[k]));
+  std::vector<unsigned> t((size_t)ipow(n, r));
+  for (size_t idx = 0; idx < t.size(); ++idx) {
+    long rem = (long)idx, off = 0;
+    for (int k = r - 1; k >= 0; --k) {
+      off += (rem % n) * stride[k];
+      rem /= n;
+    }
+    t[idx] = (unsigned)off;
+  }
+  const unsigned* d = (const unsigned*)upload(t.data(), sizeof(unsigned) * std::max<size_t>(t.size(), 1));
+  out_tables_[key] = d;
+  return d;
+}
+
 Executor::PerProb Executor::const_permuted(int tensor, const PerProb& X, const std::string& xi,
                                            const std::string& yi) {
   // canonical key: the permutation as positions
@@ -393,8 +417,13 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
         if (oi == M + N) {
         } else if (oi == N + M) {
           swap = true;
+        } else if (!N.empty() && N.back() == oi.back()) {
+          cost += 0.1 * sz(oi);   // written through output offset tables, columns contiguous
+        } else if (!M.empty() && M.back() == oi.back()) {
+          swap = true;            // the same with C transposed
+          cost += 0.1 * sz(oi);
         } else {
-          cost += 2.0 * sz(oi);
+          cost += 2.0 * sz(oi);   // GEMM layout, then a permute pass
         }
         if (cost < best.cost) best = {M, N, K, swap, cost};
       }
@@ -432,9 +461,19 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     std::swap(M, N);
   }
   const bool c_direct = (oi == M + N);
+  // Output in neither [M][N] nor [N][M] but with its fastest letter the GEMM's
+  // fastest column letter: the GEMM writes it through row and column offset
+  // tables (coalesced along that letter) instead of C plus a permute pass; not
+  // when the output aliases an operand, which the GEMM would overwrite while
+  // other tiles still read it.
+  bool c_table = !c_direct && !N.empty() && N.back() == oi.back();
+  for (int p = 0; p < np && c_table; ++p) {
+    if (out[p] == A[p] || out[p] == (*B)[p] || out[p] == Ap[p] || out[p] == Bp[p]) c_table = false;
+    if (ipow(probs_[p].n, (int)oi.size()) >= (1L << 32)) c_table = false;
+  }
   const double galpha = alpha;
-  const double gbeta = c_direct ? beta : 0.0;
-  const PerProb& Cp = c_direct ? out : scratch_->c;
+  const double gbeta = (c_direct || c_table) ? beta : 0.0;
+  const PerProb& Cp = (c_direct || c_table) ? out : scratch_->c;
 
   std::vector<GemmProblem> gs(np);
   std::vector<int> prefix(np), prefix2(np);
@@ -470,6 +509,10 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     g.active = gate_for(dst, p);
     g.tiles_m = (g.M + BM - 1) / BM;
     g.tiles_n = (g.N + BN - 1) / BN;
+    if (c_table) {
+      g.offM = out_offsets(n, M, oi);
+      g.offN = out_offsets(n, N, oi);
+    }
     int ks = 1;
     if (tiles_all < 512 && g.K >= 512) {
       ks = (int)std::min<long>((512 + tiles_all - 1) / tiles_all, g.K / 256);
@@ -520,7 +563,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
   L.flops = flops;
   L.tag = tag;
   dst.push_back(L);
-  if (!c_direct) perm(dst, scratch_->c, M + N, out, oi, 1.0, beta, nullptr, tag + ":permC");
+  if (!c_direct && !c_table) perm(dst, scratch_->c, M + N, out, oi, 1.0, beta, nullptr, tag + ":permC");
 }
 
 

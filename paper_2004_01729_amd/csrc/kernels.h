@@ -20,6 +20,11 @@ struct GemmProblem {
   int tiles_m, tiles_n, ksplit, kchunk;
   double alpha, beta;
   const int* active;     // optional run flag of the problem's instance (0: skip the problem)
+  // optional output offset tables: element (m, n) of C goes to C[offM[m] + offN[n]]
+  // instead of C[m * ldc + n] (a contraction whose output layout is neither
+  // [M][N] nor [N][M]: written in place of a separate permute pass)
+  const unsigned* offM;
+  const unsigned* offN;
 };
 
 // Unsigned 32-bit division by a runtime constant: q = umulhi(x, mul) >> shr

@@ -288,6 +288,7 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     alpha = P.alpha;
     beta = P.beta;
   }
+  const bool tab = P.ksplit <= 1 && P.offM;   // uniform per block
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -297,7 +298,8 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm * WM + i * 16 + 4 * r + fk;
         if (gm < M && gn < N) {
-          const gptr<double> c = C + (long)gm * ldc + gn;
+          const long off = tab ? (long)gview(P.offM)[gm] + gview(P.offN)[gn] : (long)gm * ldc + gn;
+          const gptr<double> c = C + off;
           double v = alpha * acc[i][j][r];
           if (beta != 0.0) v += beta * (*c);
           *c = v;
@@ -328,7 +330,8 @@ __global__ void __launch_bounds__(256) gemm_tail_reduce_kernel(const GemmProblem
     if (gm >= P.M || gn >= P.N) continue;
     double s = 0.0;
     for (int k = 0; k < splits; ++k) s += W[(long)k * (BM * BN) + e];
-    const gptr<double> c = gview(P.C) + (long)gm * P.ldc + gn;
+    const long off = P.offM ? (long)gview(P.offM)[gm] + gview(P.offN)[gn] : (long)gm * P.ldc + gn;
+    const gptr<double> c = gview(P.C) + off;
     double v = P.alpha * s;
     if (P.beta != 0.0) v += P.beta * (*c);
     *c = v;
@@ -522,7 +525,8 @@ __global__ void splitk_reduce_kernel(const GemmProblem* __restrict__ probs, cons
     double s = 0.0;
     for (int k = 0; k < P.ksplit; ++k) s += gview(P.partial)[k * mn + e];
     long gm = e / P.N, gn = e % P.N;
-    const gptr<double> c = gview(P.C) + gm * P.ldc + gn;
+    const long off = P.offM ? (long)gview(P.offM)[gm] + gview(P.offN)[gn] : gm * P.ldc + gn;
+    const gptr<double> c = gview(P.C) + off;
     double v = P.alpha * s;
     if (P.beta != 0.0) v += P.beta * (*c);
     *c = v;
