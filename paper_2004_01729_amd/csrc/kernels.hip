@@ -289,23 +289,47 @@ gemm_mfma_kernel(const GemmProblem* __restrict__ probs, const int* __restrict__ 
     beta = P.beta;
   }
   const bool tab = P.ksplit <= 1 && P.offM;   // uniform per block
+  // Column offsets once per tile; then per row group of MFMA tiles the element
+  // offsets (clamped into C for the elements outside it), all the target loads
+  // together, then the stores: one memory latency per group instead of one per
+  // element.
+  long coff[FN];
 #pragma unroll
-  for (int i = 0; i < FM; ++i)
+  for (int j = 0; j < FN; ++j) {
+    const int gn = min(n0 + wn * WN + j * 16 + fr, N - 1);
+    coff[j] = tab ? (long)gview(P.offN)[gn] : (long)gn;
+  }
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int gn = n0 + wn * WN + j * 16 + fr;
+  for (int i = 0; i < FM; ++i) {
+    long off[4][FN];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm * WM + i * 16 + 4 * r + fk;
+    for (int r = 0; r < 4; ++r) {
+      const int gm = min(m0 + wm * WM + i * 16 + 4 * r + fk, M - 1);
+      const long roff = tab ? (long)gview(P.offM)[gm] : (long)gm * ldc;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) off[r][j] = roff + coff[j];
+    }
+    double cv[4][FN];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) cv[r][j] = C[off[r][j]];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gm = m0 + wm * WM + i * 16 + 4 * r + fk;
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int gn = n0 + wn * WN + j * 16 + fr;
         if (gm < M && gn < N) {
-          const long off = tab ? (long)gview(P.offM)[gm] + gview(P.offN)[gn] : (long)gm * ldc + gn;
-          const gptr<double> c = C + off;
           double v = alpha * acc[i][j][r];
-          if (beta != 0.0) v += beta * (*c);
-          *c = v;
+          if (beta != 0.0) v += beta * cv[r][j];
+          C[off[r][j]] = v;
         }
       }
     }
+  }
 }
 
 // C = alpha * (sum of the K-segment partials, in segment order) + beta * C for the
