@@ -419,16 +419,22 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
     for (int i = 0; i < 4; ++i) w[i * 64 + lane] = acc[i];
     return;
   }
+  // the offsets of the lane's four elements (clamped into the tile), then the
+  // target loads together, then the stores: one memory latency per stage
+  // instead of a chain per element
+  const size_t cn = gview(P.offCN)[T.nb + max(min(r, T.nlen - 1), 0)];
+  size_t cm[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = 4 * i + q, col = r;
-    if (row < T.mlen && col < T.nlen) {
-      const gptr<double> c = gview(P.C) + gview(P.offCM)[T.mb + row] + gview(P.offCN)[T.nb + col];
-      double v = P.alpha * acc[i];
-      if (P.beta != 0.0) v += P.beta * (*c);
-      *c = v;
-    }
+  for (int i = 0; i < 4; ++i) cm[i] = gview(P.offCM)[T.mb + max(min(4 * i + q, T.mlen - 1), 0)];
+  const gptr<double> C = gview(P.C);
+  double cv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (P.beta != 0.0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cv[i] = C[cm[i] + cn];
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (4 * i + q < T.mlen && r < T.nlen) C[cm[i] + cn] = P.alpha * acc[i] + P.beta * cv[i];
 }
 
 // Sum of the partial tiles of a split inner range, in chunk order (deterministic).
@@ -442,18 +448,25 @@ __global__ void __launch_bounds__(256) sgemm_reduce_kernel(const SgemmProblem* _
   const SgemmProblem& P = probs[R.prob];
   if (P.active && *gview(P.active) == 0) return;
   const int r = lane & 15, q = lane >> 4;
+  // chunk partials added in chunk order per element (deterministic); offsets,
+  // target loads and stores batched over the lane's four elements
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c = 0; c < R.count; ++c)
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = 4 * i + q, col = r;
-    if (row < R.mlen && col < R.nlen) {
-      double acc = 0.0;
-      for (int c = 0; c < R.count; ++c) acc += gview(ws)[(size_t)(R.first + c) * 256 + i * 64 + lane];
-      const gptr<double> out = gview(P.C) + gview(P.offCM)[R.mb + row] + gview(P.offCN)[R.nb + col];
-      double v = P.alpha * acc;
-      if (P.beta != 0.0) v += P.beta * (*out);
-      *out = v;
-    }
+    for (int i = 0; i < 4; ++i) acc[i] += gview(ws)[(size_t)(R.first + c) * 256 + i * 64 + lane];
+  const size_t cn = gview(P.offCN)[R.nb + max(min(r, R.nlen - 1), 0)];
+  size_t cm[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cm[i] = gview(P.offCM)[R.mb + max(min(4 * i + q, R.mlen - 1), 0)];
+  const gptr<double> C = gview(P.C);
+  double cv[4] = {0.0, 0.0, 0.0, 0.0};
+  if (P.beta != 0.0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cv[i] = C[cm[i] + cn];
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (4 * i + q < R.mlen && r < R.nlen) C[cm[i] + cn] = P.alpha * acc[i] + P.beta * cv[i];
 }
 
 // One thread per allowed element; the task is found by binary search over the
