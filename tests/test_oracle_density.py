@@ -2,11 +2,13 @@
 the integrals keeping <pq|rs> = <qp|sr>) against central differences of the
 re-solved Omega (Richardson), for single elements and a random direction, on
 the integral form and on the differential form."""
+import math
+
 import numpy as np
 import pytest
 
 import ftcc_inputs as fi
-from oracle import grid as G, restricted as R, rk as K, solver as S
+from oracle import grid as G, restricted as R, rk as K, solver as S, spinorb as so
 
 
 def _richardson(f, d=1e-4):
@@ -61,3 +63,32 @@ def test_two_body_density_against_finite_differences(case, form):
     for d in dirs:
         fd = _richardson(lambda h: solve(eri + h * d)[1].omega)
         assert abs(np.sum(gam * d) - fd) < 1e-8 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("U,beta", [(4.0, 1.0), (2.0, 3.0)])
+def test_atomic_limit_density_is_double_occupancy(U, beta):
+    """One orbital (two spin orbitals), where FT-CCSD is exact: the grand
+    potential is -(1/beta) ln(1 + 2 e^{beta mu} + e^{beta(2 mu - U)}) for every U
+    at fixed mu and reference, so the density element dOmega/d<00|00> =
+    dOmega/dU is the thermal double occupancy <n_up n_down> =
+    e^{beta(2 mu - U)} / Z, a closed form independent of the method.  Restricted
+    model (the single element) and spin-orbital model (every integral scales
+    with U, so sum Gamma <pq|rs> / U is the same number)."""
+    mu = U / 2
+    h = np.zeros((1, 1))
+    eri = np.full((1, 1, 1, 1), U)
+    eps = np.array([U / 2])
+    z = 1 + 2 * math.exp(beta * mu) + math.exp(beta * (2 * mu - U))
+    docc = math.exp(beta * (2 * mu - U)) / z
+    gr = G.Grid(beta, 8, 4)
+    m = R.RestrictedModel(R.RestrictedIntegrals(h, eri, eps, mu, beta))
+    sol = S.solve(m, gr, tol=1e-14)
+    adj = S.adjoint(m, gr, sol, tol=1e-14)
+    gam = S.two_body_density(lambda d: S.d_omega(m, gr, sol, adj, "h", deri=d), 1)
+    assert abs(gam[0, 0, 0, 0] - docc) < 1e-8 * max(1.0, docc)
+    hs, es, epss = so.spin_orbital_from_spatial(h, eri, eps)
+    ms = so.SpinOrbitalModel(so.ThermalIntegrals(hs, es, epss, mu, beta))
+    sols = S.solve(ms, gr, tol=1e-14)
+    adjs = S.adjoint(ms, gr, sols, tol=1e-14)
+    gams = S.two_body_density(lambda d: S.d_omega(ms, gr, sols, adjs, "h", deri=d), 2)
+    assert abs(np.sum(gams * es) / U - docc) < 1e-8 * max(1.0, docc)
