@@ -2,10 +2,15 @@
 //
 //   gemm_mfma      grouped C = alpha * op(A) op(B) + beta * C on v_mfma_f64_16x16x4f64,
 //                  LDS double-buffered 128x128 (or 64x64) tiles, XCD-aware tile order,
-//                  optional split-K with a deterministic second-pass reduction
+//                  optional split-K with a deterministic second-pass reduction, C in
+//                  GEMM layout or written into a permuted layout through row and
+//                  column offset tables
 //   permute4       grouped 4-index transpose-accumulate Y[perm] = alpha X + beta Y,
 //                  LDS-tiled when the fastest index moves
 //   dot            grouped full contractions (two-pass, deterministic)
+//   sgemm, elem,   momentum-blocked contractions over element-offset lists (one wave
+//   dotb           per 16x16 MFMA tile), unary ops and full contractions over the
+//                  momentum-allowed elements
 //
 // The imaginary-time kernels (thermal blocks, propagator, adjoint) are in
 // tau_kernels.hip.
