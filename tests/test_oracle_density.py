@@ -92,3 +92,25 @@ def test_atomic_limit_density_is_double_occupancy(U, beta):
     adjs = S.adjoint(ms, gr, sols, tol=1e-14)
     gams = S.two_body_density(lambda d: S.d_omega(ms, gr, sols, adjs, "h", deri=d), 2)
     assert abs(np.sum(gams * es) / U - docc) < 1e-8 * max(1.0, docc)
+
+
+@pytest.mark.parametrize("U,beta", [(4.0, 1.0), (2.0, 3.0)])
+def test_atomic_limit_density_differential_form_converges_at_fourth_order(U, beta):
+    """The same closed form for the differential form: the RK4 march, its
+    reverse pass and the density approach <n_up n_down> with the method's
+    order (the error falls by about 2^4 when the grid is doubled)."""
+    mu = U / 2
+    h = np.zeros((1, 1))
+    eri = np.full((1, 1, 1, 1), U)
+    eps = np.array([U / 2])
+    z = 1 + 2 * math.exp(beta * mu) + math.exp(beta * (2 * mu - U))
+    docc = math.exp(beta * (2 * mu - U)) / z
+    m = R.RestrictedModel(R.RestrictedIntegrals(h, eri, eps, mu, beta))
+    errs = []
+    for n_g in (32, 64):
+        sol = K.solve(m, beta, n_g, "rk4")
+        adj = K.adjoint(m, sol)
+        gam = S.two_body_density(lambda d: K.d_omega(m, sol, adj, "h", deri=d), 1)
+        errs.append(abs(gam[0, 0, 0, 0] - docc))
+    assert errs[1] < 1e-8
+    assert 3.5 < math.log2(errs[0] / errs[1]) < 4.5
