@@ -1,45 +1,42 @@
 #!/usr/bin/env python3
 """Throughput of the FT-CCSD hot path on one MI355X.
 
-A step is one pass of the whole path over one instance: thermal integrals,
-the forward imaginary-time march to convergence (T1/T2 residuals + the
-exponential propagator + Omega), the Lambda adjoint swept backward in tau,
-and the response derivatives dOmega/dmu, dOmega/dbeta and dOmega/dh_pq.
+Default line (the metric's measurement M1 at the largest workload): the warm
+dense electron gas in 123 plane waves, N = 14, r_s = 4, Theta = 1, thermal HF
+reference, occupation threshold 1e-6, restricted, FP64, in the context of its
+full configuration (16 Gauss-Legendre tau points as 4 panels x 4 nodes,
+panel checkpointing; dense contractions on FP64 MFMA).  A step is the T1/T2
+residual evaluation (eqn:E, eqn:ccS1, eqn:ccS2) of the four nodes of a panel,
+i.e. the residual work of one Picard sweep, at the first-order amplitudes
+s(tau) = -S0 (1 - exp(-Delta tau)) / Delta at tau = beta / 2 (S0 the residual at
+zero amplitudes), on device-resident data through the replayed HIP graph.
+value = residual evaluations per second.  The dominant kernel's duration comes
+from a separate pass with per-launch HIP events after the timed steps.
+Secondary fields (config.secondary): the 57-plane-wave gas (r_s = 1,
+Theta = 0.5, 16 tau points) through the whole path -- forward march, Lambda
+adjoint, response dOmega/dmu, dOmega/dbeta, dOmega/dh -- and the adjoint
+gradient against measured central finite differences of Omega.
+Synthetic: every Hamiltonian is generated from these parameters.
 
-Workload (default): warm dense electron gas, restricted, 57 plane waves,
-N = 14, r_s = 1, Theta = 0.5, thermal HF reference, 16 Gauss-Legendre tau
-points (4 panels x 4), FP64.  Synthetic: the Hamiltonian is generated from
-these parameters (no data files).
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-secondary]
+       python bench.py --mode step [--workload ueg57|ueg123|hubbard6|hubbard10] [--momentum]
+       python bench.py --mode residual|copy|batch|numerr|exc|afm ...
 
-metric: tau-point T2 residual evaluations per second of whole-step wall time
-(forward residual evaluations of every node and sweep, including the forward
-re-evaluations inside the adjoint and response phases).
-
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload ueg57|ueg123|hubbard6|hubbard10]
-                       [--no-cpu-baseline] [--mode step|residual|copy|batch] [--reps R]
-                       [--per-instance] [--momentum]
-       python bench.py --mode numerr [--dense]
-       python bench.py --mode afm
-       python bench.py --mode exc
-
---mode residual times R back-to-back residual evaluations of every node of the
-last panel at the converged amplitudes (kernel throughput alone); --mode copy
-runs R device-to-device copies of 1 GiB (the byte-counter calibration for the
-traffic figures).  --mode batch runs one step of the 32-instance mixed batch
-(16 UEG 57-PW points over r_s x Theta, 16 Hubbard rings L = 6..14 with random U
-and T, 20 tau points, occupation threshold 1e-6) in one context, and with
---per-instance the same instances one context each; several minutes.  These
-print one JSON line of their own.  --momentum evaluates the contractions over
-their crystal-momentum-allowed blocks only (a different algorithm from the dense
-one the metric's FP64-MFMA share refers to; its line has no GEMM roofline).
---mode numerr measures the grid-error orders of the differential form (explicit
-RK1 / RK2 / RK4 with Simpson's rule, Table tab:numerr) on the 14-electron gas
-in 33 plane waves at r_s = 4, Theta = 0.125 (momentum-blocked unless --dense).
---mode afm runs the 32-site half-filled ring with Neel and UHF references in
-spin orbitals (U = 2, 4, 8; T = 0.25 .. 2): Omega, E, S and the staggered
-magnetisation per site.  --mode exc computes the exchange-correlation energy
-E_xc(N, M) of the 66-electron unpolarised gas in 123 plane waves at Theta = 0.5
-(r_s = 1, 2, 4) with mu fixed at the coupled-cluster level.
+--mode step times whole steps (thermal set-up + forward march + Lambda +
+response) of one workload.  --mode residual times R back-to-back residual
+evaluations of every node of the last panel at the converged amplitudes;
+--mode copy runs R device-to-device copies of 1 GiB (the byte-counter
+calibration for the traffic figures).  --mode batch runs one step of the
+32-instance mixed batch (16 UEG 57-PW points over r_s x Theta, 16 Hubbard rings
+L = 6..14 with random U and T, 20 tau points, occupation threshold 1e-6) in one
+context, and with --per-instance the same instances one context each.
+--momentum evaluates the contractions over their crystal-momentum-allowed
+blocks only.  --mode numerr measures the grid-error orders of the differential
+form and of the Simpson integral form (Table tab:numerr) on the 14-electron gas
+in 33 plane waves at r_s = 4, Theta = 0.125.  --mode afm runs the 32-site
+half-filled ring with Neel and UHF references; --mode exc the
+exchange-correlation energy E_xc(N, M) of the 66-electron gas in 123 plane
+waves with mu fixed at the coupled-cluster level.
 """
 from __future__ import annotations
 
@@ -54,7 +51,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix, flop/s
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm128_ueg57_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm128_ueg123_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_01729_amd", "csrc", "kernels.hip")
 
 
@@ -394,68 +391,30 @@ def cpu_baseline(s, budget_s=20.0):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.environ.get("OPENBLAS_NUM_THREADS", os.cpu_count() or 1)))
     threads = min(threads, os.cpu_count() or threads)
     return dict(value=1.0 / est, unit="tau-point residual evals/s", cores=threads, kind="oracle",
+                cpu_model=cpu_model(), blas="numpy einsum -> OpenBLAS dgemm (FP64)",
                 sample=f"first {k} of {len(items)} spatial einsum items of one residual evaluation at n={s.n} "
                        f"({100.0 * done / total:.1f}% of its flops) in {el:.1f} s; full-residual time "
                        f"extrapolated to {est:.1f} s")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="ueg57")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="step", choices=("step", "residual", "copy", "batch", "numerr", "afm", "exc"))
-    ap.add_argument("--reps", type=int, default=5)
-    ap.add_argument("--per-instance", action="store_true")
-    ap.add_argument("--group", type=int, default=32)
-    ap.add_argument("--subset", default="all", choices=("all", "rings"))
-    ap.add_argument("--momentum", action="store_true")
-    ap.add_argument("--dense", action="store_true", help="--mode numerr: dense contractions")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
-              file=sys.stderr)
-        sys.exit(2)
-
+def step_bench(args, measure_fd_beta=False):
+    """Whole steps (thermal set-up, forward march, Lambda, response for mu, beta,
+    h) of one workload; the GEMM roofline from per-launch events of the timed
+    steps (the profiler runs the launch lists eagerly).  The adjoint gradient is
+    set against central finite differences of Omega in mu (and beta), each
+    measured as two forward solves."""
     import torch
     from paper_2004_01729_amd import ftcc as F
-
-    if not torch.cuda.is_available():
-        raise SystemExit("no GPU visible")
-    if args.mode == "copy":
-        print(json.dumps(copy_calibration(args.reps)), flush=True)
-        return
-    if args.mode == "exc":
-        print(json.dumps(exc_bench()), flush=True)
-        return
-    if args.mode == "afm":
-        print(json.dumps(afm_bench()), flush=True)
-        return
-    if args.mode == "numerr":
-        print(json.dumps(numerr_bench(momentum=not args.dense)), flush=True)
-        return
-    if args.mode == "batch":
-        print(json.dumps(batch_bench(args.per_instance, args.group, args.momentum, args.subset)), flush=True)
-        return
     s, opts, cfg = workload(args.workload)
     ctx = F.Context(1, **opts)
     if args.momentum:
         ctx.set_momentum(0, *s.momentum)
         cfg = dict(cfg, momentum_blocked=True)
     ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
-    if args.mode == "residual":
-        ctx.solve(s.mu, s.beta)
-        r = residual_throughput(ctx, args.reps, opts["n_tau"])
-        ctx.close()
-        print(json.dumps(dict(mode="residual", workload=cfg["workload"], reps=args.reps, **r)), flush=True)
-        return
     for _ in range(args.warmup):
         step(ctx, s)
     torch.cuda.synchronize()
 
-    ctx.kernel_profile(1)            # start recording the dominant GEMM kernel
     evals = 0
     vjps = 0
     times = dict(forward=0.0, gradient=0.0)
@@ -466,6 +425,10 @@ def main():
         vjps += st1["vjp_evals"]
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    # the dominant GEMM family's launches, timed by per-launch HIP events in one
+    # further step (the recording runs the launch lists eagerly, not as graphs)
+    ctx.kernel_profile(1)
+    step(ctx, s)
     prof = ctx.kernel_profile(0)
     # forward re-evaluations inside the adjoint and response phases: one per node
     n_tau = opts["n_tau"]
@@ -494,13 +457,28 @@ def main():
     fd_mu_rich = (4.0 * (oph - omh) / d - fd_mu) / 3.0
     n_h = s.n * (s.n + 1) // 2
     gradient = dict(adjoint_s=t_grad, forward_s=t_fwd, fd_mu_measured_s=t_fd_mu,
-                    fd_mu_beta_s=2 * t_fd_mu, fd_all_params_s_extrapolated=(2 + n_h) * t_fd_mu,
-                    n_params=2 + n_h, adjoint_vs_fd_speedup_mu_beta=2 * t_fd_mu / t_grad,
-                    adjoint_vs_fd_speedup_all=(2 + n_h) * t_fd_mu / t_grad,
+                    n_params_all=2 + n_h,
                     dOmega_dmu_adjoint=float(resp["mu"][0]), dOmega_dmu_fd=float(fd_mu),
                     fd_rel_diff=abs(fd_mu - resp["mu"][0]) / max(1.0, abs(resp["mu"][0])),
                     dOmega_dmu_fd_richardson=float(fd_mu_rich),
                     fd_richardson_rel_diff=abs(fd_mu_rich - resp["mu"][0]) / max(1.0, abs(resp["mu"][0])))
+    if measure_fd_beta:
+        db = 1e-4 * s.beta
+        tb0 = time.perf_counter()
+        ctx.solve(s.mu, s.beta + db)
+        bp = ctx.grand_potential()[0][0]
+        ctx.solve(s.mu, s.beta - db)
+        bm = ctx.grand_potential()[0][0]
+        t_fd_beta = time.perf_counter() - tb0
+        fd_beta = (bp - bm) / (2 * db)
+        gradient.update(fd_beta_measured_s=t_fd_beta, fd_mu_beta_measured_s=t_fd_mu + t_fd_beta,
+                        adjoint_vs_fd_speedup_mu_beta=(t_fd_mu + t_fd_beta) / t_grad,
+                        dOmega_dbeta_adjoint=float(resp["beta"][0]), dOmega_dbeta_fd=float(fd_beta),
+                        fd_beta_rel_diff=abs(fd_beta - resp["beta"][0]) / max(1.0, abs(resp["beta"][0])),
+                        fd_all_params_s_extrapolated=(2 + n_h) * t_fd_mu,
+                        adjoint_vs_fd_speedup_all_extrapolated=(2 + n_h) * t_fd_mu / t_grad)
+    else:
+        gradient.update(adjoint_vs_fd_speedup_mu_beta_extrapolated=2 * t_fd_mu / t_grad)
     value = evals / el
     achieved = prof["flops"] / prof["seconds"] if prof["seconds"] > 0 else 0.0
     roofline = {
@@ -536,6 +514,183 @@ def main():
         "roofline": roofline,
     }
     ctx.close()
+    return line
+
+
+def cpu_model():
+    try:
+        for row in open("/proc/cpuinfo"):
+            if row.startswith("model name"):
+                return row.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def first_order_amplitudes(ctx, s):
+    """s(tau) = -S0 (1 - exp(-Delta tau)) / Delta at tau = beta / 2, S0 the residual
+    at zero amplitudes (the first-order solution of eqn:smu; -S0 tau where Delta = 0)."""
+    import numpy as np
+    n = s.n
+    S1, S2, _ = ctx.eval_residual(0, s.mu, s.beta, np.zeros((n, n)), np.zeros((n,) * 4))
+    tau = 0.5 * s.beta
+    e = s.eps
+
+    def prop(d):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(np.abs(d) > 1e-12, -np.expm1(-d * tau) / np.where(d == 0.0, 1.0, d), tau)
+
+    t1 = -S1 * prop(e[None, :] - e[:, None])
+    d2 = e[None, None, :, None] + e[None, None, None, :] - e[:, None, None, None] - e[None, :, None, None]
+    t2 = -S2 * prop(d2)
+    return t1, t2
+
+
+def m1_bench(args):
+    """The default line: residual evaluations per second at the 123-plane-wave
+    workload (see the module docstring)."""
+    import torch
+    from paper_2004_01729_amd import ftcc as F
+    s, opts, cfg = workload("ueg123")
+    t_setup = time.perf_counter()
+    ctx = F.Context(1, **opts)
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    t1, t2 = first_order_amplitudes(ctx, s)
+    S1, S2, E = ctx.eval_residual(0, s.mu, s.beta, t1, t2)     # puts t into every node slot
+    del S2
+    t_setup = time.perf_counter() - t_setup
+    m = opts["nodes_per_panel"]
+    for _ in range(args.warmup):
+        ctx.time_residual(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.time_residual(1)          # the m node residuals of a panel, replayed graph
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    _, flop_sweep = ctx.time_residual(1)
+    # per-launch HIP events on the dominant GEMM family (eager launches of the same lists)
+    ctx.kernel_profile(1)
+    prof_steps = 2
+    for _ in range(prof_steps):
+        ctx.time_residual(1)
+    prof = ctx.kernel_profile(0)
+    ctx.close()
+    evals = args.steps * m
+    achieved = prof["flops"] / prof["seconds"] if prof["seconds"] > 0 else 0.0
+    roofline = {
+        "bound": "mfma",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_FP64_MFMA / 1e12,
+        "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_MFMA,
+        "traffic": measured_traffic(),
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "kernel": "gemm_mfma_kernel<128,128,16,*,*> (FP64 MFMA 16x16x4)",
+        "launches": prof["launches"],
+        "avg_launch_ms": 1e3 * prof["seconds"] / max(prof["launches"], 1),
+        "flop_per_launch": prof["flops"] / max(prof["launches"], 1),
+        "timing": f"per-launch HIP events on the library stream over {prof_steps} further steps "
+                  "(eager launches of the timed graph's lists)",
+    } if prof["launches"] > 0 else None
+    line = {
+        "metric": "tau-point T2 residual evals/s",
+        "value": evals / el,
+        "unit": "residual evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": dict(cfg, phases="T1/T2 residual (M1)", residual_evals_per_step=m,
+                       amplitudes="first-order s(beta/2)", context_setup_s=t_setup,
+                       gemm_flop_per_eval=flop_sweep / m,
+                       step_gemm_tflops=flop_sweep * args.steps / el / 1e12,
+                       step_frac_fp64_mfma=flop_sweep * args.steps / el / PEAK_FP64_MFMA,
+                       E_first_order=float(E)),
+        "roofline": roofline,
+    }
+    return line, s
+
+
+def secondary_57(steps=1, warmup=1):
+    """The 57-plane-wave gas through the whole path and the adjoint gradient
+    against measured central differences (secondary fields of the default line)."""
+    ns = argparse.Namespace(workload="ueg57", momentum=False, steps=steps, warmup=warmup)
+    line = step_bench(ns, measure_fd_beta=True)
+    keep = ("value", "ms_per_step", "roofline")
+    out = {k: line[k] for k in keep}
+    out.update(line["config"])
+    out["value_unit"] = "residual evals/s of whole-step wall time"
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ueg57")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--mode", default="m1",
+                    choices=("m1", "step", "residual", "copy", "batch", "numerr", "afm", "exc"))
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--per-instance", action="store_true")
+    ap.add_argument("--group", type=int, default=32)
+    ap.add_argument("--subset", default="all", choices=("all", "rings"))
+    ap.add_argument("--momentum", action="store_true")
+    ap.add_argument("--dense", action="store_true", help="--mode numerr: dense contractions")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_01729_amd import ftcc as F
+
+    if not torch.cuda.is_available():
+        raise SystemExit("no GPU visible")
+    if args.mode == "copy":
+        print(json.dumps(copy_calibration(args.reps)), flush=True)
+        return
+    if args.mode == "exc":
+        print(json.dumps(exc_bench()), flush=True)
+        return
+    if args.mode == "afm":
+        print(json.dumps(afm_bench()), flush=True)
+        return
+    if args.mode == "numerr":
+        print(json.dumps(numerr_bench(momentum=not args.dense)), flush=True)
+        return
+    if args.mode == "batch":
+        print(json.dumps(batch_bench(args.per_instance, args.group, args.momentum, args.subset)), flush=True)
+        return
+    if args.mode == "residual":
+        s, opts, cfg = workload(args.workload)
+        ctx = F.Context(1, **opts)
+        if args.momentum:
+            ctx.set_momentum(0, *s.momentum)
+        ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+        ctx.solve(s.mu, s.beta)
+        r = residual_throughput(ctx, args.reps, opts["n_tau"])
+        ctx.close()
+        print(json.dumps(dict(mode="residual", workload=cfg["workload"], reps=args.reps, **r)), flush=True)
+        return
+    if args.mode == "step":
+        line = step_bench(args)
+        s = workload(args.workload)[0]
+    else:
+        line, s = m1_bench(args)
+        print(f"[bench] m1 done: {line['value']:.3f} residual evals/s", file=sys.stderr, flush=True)
+        if not args.no_secondary:
+            line["config"]["secondary"] = secondary_57()
+            print("[bench] secondary (57 PW whole path) done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(line), flush=True)

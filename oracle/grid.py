@@ -92,6 +92,45 @@ class Grid:
             out.append(arr[..., inv].reshape(lead + shape))
         return tuple(out)
 
+    def weights_ddelta(self, delta: np.ndarray, h: float | None = None):
+        """Derivatives (dE, dEe, dW, dWe) of the exponential weights with respect
+        to Delta at fixed h, by the same quadrature of their integral definitions:
+        d/dDelta exp(Delta h (u - c)) = h (u - c) exp(Delta h (u - c))."""
+        h = self.h if h is None else float(h)
+        delta = np.asarray(delta, dtype=np.float64)
+        uniq, inv = np.unique(delta.ravel(), return_inverse=True)
+        d = uniq
+        m, c, b = self.m, self.c, self.b
+        dE = -h * c[:, None] * np.exp(-np.outer(c, d) * h)
+        dEe = -h * np.exp(-d * h)
+        dW = np.zeros((m, m, d.size))
+        dWe = np.zeros((m, d.size))
+        v, om = panel_nodes(Q_SUB)
+        if self.kind == "etd":
+            for x in range(m):
+                for q in range(Q_SUB):
+                    u = c[x] * v[q]
+                    ex = np.exp(d * h * (u - c[x]))
+                    dW[x] += (h * c[x] * om[q]) * lagrange(c, u)[:, None] * (h * (u - c[x]) * ex)[None, :]
+            for q in range(Q_SUB):
+                u = v[q]
+                ex = np.exp(d * h * (u - 1.0))
+                dWe += (h * om[q]) * lagrange(c, u)[:, None] * (h * (u - 1.0) * ex)[None, :]
+        else:
+            A = np.zeros((m, m))
+            for x in range(m):
+                for q in range(Q_SUB):
+                    A[x] += c[x] * om[q] * lagrange(c, c[x] * v[q])
+            for x in range(m):
+                for y in range(m):
+                    dW[x, y] = h * A[x, y] * h * (c[y] - c[x]) * np.exp(d * h * (c[y] - c[x]))
+            for y in range(m):
+                dWe[y] = h * b[y] * h * (c[y] - 1.0) * np.exp(d * h * (c[y] - 1.0))
+        out = []
+        for arr in (dE, dEe, dW, dWe):
+            out.append(arr[..., inv].reshape(arr.shape[:-1] + delta.shape))
+        return tuple(out)
+
     def _weights_unique(self, d, h, deriv):
         m, c, b = self.m, self.c, self.b
         E = np.exp(-np.outer(c, d) * h)                        # (m, N)

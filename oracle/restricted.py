@@ -223,6 +223,38 @@ class RestrictedModel:
             acc = acc + c * _apply_axes(x, axes)
         return acc
 
+    def residual_rows(self, s, rows_i, rows_j):
+        """S1 whole and the rows S2[rows_i][:, rows_j] (shape (|I|, |J|, n, n)),
+        for sizes where S2 or the weighted integral blocks do not fit in memory.
+
+        The same items as residual(), each with its output restricted before it
+        is evaluated: an item whose result is transposed by `axes` lands its
+        axis axes[0] on output axis i and axes[1] on j, so the letters at those
+        axes take only the requested indices, in every factor that carries them.
+        Weighted integral blocks are formed per item and not kept."""
+        out = T.OUT["S2"]
+        res = []
+        for which, rows in (("S1", None), ("S2", (rows_i, rows_j))):
+            shape = (self.n, self.n) if rows is None else (len(rows_i), len(rows_j), self.n, self.n)
+            acc = np.zeros(shape)
+            for c, ops, axes in expanded(which):
+                restrict = {}
+                if rows is not None:
+                    ax = (0, 1, 2, 3) if axes is None else axes
+                    restrict = {out[ax[0]]: np.asarray(rows[0]), out[ax[1]]: np.asarray(rows[1])}
+                args = []
+                for op, sub in ops:
+                    a = self._operand(op, sub, s, self.ints)
+                    for k, ch in enumerate(sub):
+                        if ch in restrict:
+                            a = np.take(a, restrict[ch], axis=k)
+                    args.append(a)
+                self.ints._cache.clear()
+                x = _einsum(",".join(sub for _, sub in ops) + "->" + T.OUT[which], *args)
+                acc = acc + c * _apply_axes(x, axes)
+            res.append(acc)
+        return res[0], res[1]
+
     def energy(self, s, ints=None):
         return float(self._kernel("E", s, self.ints if ints is None else ints))
 
@@ -280,6 +312,10 @@ class RestrictedModel:
         if theta == "mu":
             return -2.0 * float(np.sum(b.n_occ))
         return -self.omega0() / b.beta + 2.0 * float(np.sum((b.eps - b.mu) * b.n_occ)) / b.beta
+
+    def domega0_deps(self):
+        """d Omega_0 / d eps_q = 2 n_q (both spins of spatial orbital q)."""
+        return 2.0 * self.ints.n_occ
 
     def dmf_dh(self):
         return 2.0 * np.diag(self.ints.n_occ)

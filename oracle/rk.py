@@ -217,3 +217,29 @@ def d_omega_dh(model, sol, adj):
         for Y, kb in zip(sol.stages[n], adj.kbar[n]):
             out = out + model.vjp_fock(Y, None, tuple(-x for x in kb))
     return out
+
+
+def d_omega_deps(model, sol, adj):
+    """dOmega/deps_q at a frozen reference for the differential form: the
+    occupation and explicit-u parts as in solver.d_omega_deps, and the slopes'
+    dependence on Delta, d k_j / d Delta = -Y_j, weighted by the slope
+    cotangents kbar_j."""
+    from .solver import _eps_from_delta
+    ints = model.ints
+    n = model.n
+    dn_mu, _ = model.occ_derivs()
+    d0 = model.domega0_deps()
+    out = np.zeros(n)
+    for q in range(n):
+        dn = np.zeros(n)
+        dn[q] = -dn_mu[q]
+        du = np.zeros((n, n))
+        du[q, q] = -1.0
+        out[q] = (d0[q] + model.domega_mf(dn, dh=du)
+                  + _integral_term(model, sol, adj, ints.derivative(dn=dn, dh=du)))
+    D1, D2 = model.zeros()
+    for n_step in range(sol.n_g):
+        for Y, kb in zip(sol.stages[n_step], adj.kbar[n_step]):
+            D1 = D1 - kb[0] * Y[0]
+            D2 = D2 - kb[1] * Y[1]
+    return out + _eps_from_delta(model, D1, D2)

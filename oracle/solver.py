@@ -150,7 +150,10 @@ class Adjoint:
     iters: list
 
 
-def adjoint(model, grid, sol: Solution, tol=1e-13, max_iter=400):
+def adjoint(model, grid, sol: Solution, tol=1e-13, max_iter=400, diis=0):
+    """Backward sweep over the panels.  The panel equations for lam are linear
+    and solved by fixed-point sweeps; diis > 1 extrapolates over that many
+    sweeps as in the forward march (the solution is unchanged)."""
     (E1, Ee1, W1, We1), (E2, Ee2, W2, We2) = _panel_weights(model, grid)
     m, P = grid.m, grid.P
     z = model.zeros()
@@ -167,6 +170,7 @@ def adjoint(model, grid, sol: Solution, tol=1e-13, max_iter=400):
             dE.append(g)
         l = [(-g[0], -g[1]) for g in dE]
         an = a[p + 1]
+        hist_s, hist_r = [], []
         for it in range(1, max_iter + 1):
             lt = []
             for x in range(m):
@@ -179,9 +183,15 @@ def adjoint(model, grid, sol: Solution, tol=1e-13, max_iter=400):
                 new.append((-dE[x][0] - j[0], -dE[x][1] - j[1]))
             change = max(_maxabs((new[x][0] - l[x][0], new[x][1] - l[x][1])) for x in range(m))
             scale = max(1e-300, max(_maxabs(v) for v in new))
-            l = new
             if change <= tol * max(scale, 1e-30) or change == 0.0:
+                l = new
                 break
+            if diis > 1:
+                hist_s.append(_flat(l))
+                hist_r.append(_flat(new) - hist_s[-1])
+                hist_s, hist_r = hist_s[-diis:], hist_r[-diis:]
+                new = _unflat(_diis_next(hist_s, hist_r), new) if len(hist_r) > 1 else new
+            l = new
         else:
             raise RuntimeError(f"panel {p}: adjoint iteration did not converge")
         iters[p] = it
@@ -262,6 +272,54 @@ def d_omega_dh(model, grid, sol, adj):
         x = k % m
         out = out + model.vjp_fock(s, grid.b[x] / P, adj.lamt[k])
     return out
+
+
+def _eps_from_delta(model, D1, D2):
+    """Chain a cotangent of the orbital-energy differences to the orbital
+    energies: Delta_i^a = eps_a - eps_i (t1[i, a]), Delta_ij^ab = eps_a + eps_b -
+    eps_i - eps_j (t2[i, j, a, b])."""
+    return (D1.sum(0) - D1.sum(1) + D2.sum((0, 1, 3)) + D2.sum((0, 1, 2))
+            - D2.sum((1, 2, 3)) - D2.sum((0, 2, 3)))
+
+
+def d_omega_deps(model, grid, sol, adj):
+    """dOmega/deps_q (vector) at frozen h, <pq|rs>, mu, beta, orbitals and
+    dropped slots: the response to the reference orbital energies of Section
+    II.D (type 2; Appendix B).  eps_q enters
+      * Omega_0 and Omega_1, and the occupation n_q (dn_q/deps_q = -beta n_q (1 - n_q)),
+        which moves the thermal integrals (weights and Fock operator) -- one
+        directional derivative per orbital, as for mu;
+      * u = f - diag(eps) explicitly (du = -e_q e_q^T);
+      * the propagator weights through Delta (dL/dDelta of the discrete
+        Lagrangian, chained to eps by Delta's definition).
+    The paper's relaxed diagonal is p^cc_qq = dOmega/deps_q + dOmega/dh_qq."""
+    ints = model.ints
+    n = model.n
+    dn_mu, _ = model.occ_derivs()
+    d0 = model.domega0_deps()
+    out = np.zeros(n)
+    for q in range(n):
+        dn = np.zeros(n)
+        dn[q] = -dn_mu[q]
+        du = np.zeros((n, n))
+        du[q, q] = -1.0
+        out[q] = (d0[q] + model.domega_mf(dn, dh=du)
+                  + _integral_term(model, grid, sol, adj, ints.derivative(dn=dn, dh=du)))
+    dE1, dEe1, dW1, dWe1 = grid.weights_ddelta(model.delta1)
+    dE2, dEe2, dW2, dWe2 = grid.weights_ddelta(model.delta2)
+    m, P = grid.m, grid.P
+    D1, D2 = model.zeros()
+    for p in range(P):
+        sb = sol.sb[p]
+        S = [sol.resid[p * m + y] for y in range(m)]
+        for x in range(m):
+            lam = adj.lam[p * m + x]
+            D1 = D1 + lam[0] * (-dE1[x] * sb[0] + sum(dW1[x, y] * S[y][0] for y in range(m)))
+            D2 = D2 + lam[1] * (-dE2[x] * sb[1] + sum(dW2[x, y] * S[y][1] for y in range(m)))
+        an = adj.a[p + 1]
+        D1 = D1 + an[0] * (-dEe1 * sb[0] + sum(dWe1[y] * S[y][0] for y in range(m)))
+        D2 = D2 + an[1] * (-dEe2 * sb[1] + sum(dWe2[y] * S[y][1] for y in range(m)))
+    return out + _eps_from_delta(model, D1, D2)
 
 
 def two_body_density(d_omega_along, n):

@@ -251,6 +251,10 @@ class SpinOrbitalModel:
             return -float(np.sum(b.n_occ))
         return -self.omega0() / b.beta + float(np.sum((b.eps - b.mu) * b.n_occ)) / b.beta
 
+    def domega0_deps(self):
+        """d Omega_0 / d eps_q = n_q (one electron per spin orbital)."""
+        return self.ints.n_occ.astype(float)
+
     def dmf_dh(self):
         """d Omega_1 / d h_pq = n_p delta_pq."""
         return np.diag(self.ints.n_occ).astype(float)

@@ -344,3 +344,19 @@ def test_find_mu_interacting_against_finite_differences():
     d2 = (om(mu + d / 2) - om(mu - d / 2)) / d
     n_fd = -(4 * d2 - d1) / 3
     assert abs(n_fd - 3.5) < 1e-8
+
+
+def test_adjoint_diis_same_solution(p10_case):
+    """Extrapolating the adjoint sweeps (DIIS) leaves the solution of the linear
+    panel equations unchanged: lambda, lambda-tilde and dOmega/dmu agree with the
+    plain sweeps (whose derivatives the central differences above pin)."""
+    c = p10_case
+    plain = c["adj"]
+    fast = S.adjoint(c["model"], c["gr"], c["sol"], diis=5)
+    for a, b in zip(plain.lam + plain.lamt, fast.lam + fast.lamt):
+        scale = max(1.0, np.abs(a[1]).max())
+        assert np.abs(a[0] - b[0]).max() < 1e-11 * scale and np.abs(a[1] - b[1]).max() < 1e-11 * scale
+    d0 = S.d_omega(c["model"], c["gr"], c["sol"], plain, "mu")
+    d1 = S.d_omega(c["model"], c["gr"], c["sol"], fast, "mu")
+    assert abs(d0 - d1) < 1e-11 * max(1.0, abs(d0))
+    assert sum(fast.iters) < sum(plain.iters)
