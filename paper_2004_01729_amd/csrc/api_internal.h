@@ -49,6 +49,14 @@ using namespace ftcc;
 using namespace ftcc::host;
 
 // ------------------------------------------------------------------ context
+// a cached exponential-sum launch of the Simpson integral form: problems, block
+// prefix and terms in one device buffer
+struct SpLaunch {
+  char* buf = nullptr;
+  int n_prob = 0;
+  int blocks = 0;
+};
+
 struct Instance {
   int n = 0;
   bool has_ham = false;
@@ -73,6 +81,10 @@ struct Instance {
   double* rk_tmp[2] = {nullptr, nullptr};   // differential form: reverse-pass temporaries
   double* gacc[12] = {};                    // two-body density: accumulated gradients of the 12 weighted blocks
   double* rk_hbar = nullptr;                // d Omega_CC / d(step) at fixed integrals
+  // orbital-energy response (allocated on first request): per-orbital accumulators of
+  // the thermal-integral part, dL/dDelta of every amplitude element, the direction
+  // du = -e_q e_q^T and the assembled vector
+  double *deps_acc = nullptr, *deps_delta = nullptr, *deps_dh = nullptr, *deps_out = nullptr;
 };
 
 struct ftcc_ctx {
@@ -125,6 +137,8 @@ struct ftcc_ctx {
   // differential form (propagator >= 2): explicit Runge-Kutta with m = stages,
   // P = n_tau steps; tableau a (row-major m x m, strictly lower) and b
   bool rk = false;
+  bool simpson = false;                       // propagator 5: the Simpson integral form (m = 1, P = n_tau)
+  std::map<long, SpLaunch> sp_cache;          // its exponential-sum descriptor sets (until the next solve)
   double gdeg = 2.0;                          // electrons per orbital and occupation: 2 restricted, 1 spin orbitals
   std::vector<double> rk_a, rk_b;
   double* d_rkw = nullptr;                    // [P + 1] Simpson weight / beta of each grid point
@@ -172,6 +186,35 @@ struct ftcc_ctx {
 namespace ftcc {
 namespace host {
 
+// Divergence of the fixed-point sweeps of one panel: the max |change| of an
+// instance grew in kDivergeSweeps consecutive sweeps and stands more than
+// kDivergeFactor above the smallest change of the panel so far (a converging
+// iteration, DIIS-accelerated or not, does not grow that long).
+constexpr int kDivergeSweeps = 8;
+constexpr double kDivergeFactor = 1e4;
+struct DivergenceWatch {
+  int grew = 0;
+  double prev = INFINITY, low = INFINITY;
+  bool diverged(double chg) {
+    grew = chg > prev ? grew + 1 : 0;
+    prev = chg;
+    low = std::min(low, chg);
+    return grew >= kDivergeSweeps && chg > kDivergeFactor * low;
+  }
+};
+
+// one exponential-sum launch of the Simpson integral form, per instance: out =
+// x0 * base + (prod ? prod : 1) * sum of terms (X, C, k); see ExpSumProblem
+struct ExpSpec {
+  int mode = 0;
+  const double* base = nullptr;
+  double x0 = 0.0;
+  const double* prod = nullptr;
+  std::vector<std::tuple<const double*, double, double>> terms;
+  double* out = nullptr;
+  bool track = false;
+};
+
 // buffer of node x of an instance (DIIS histories)
 using NodeBufs = std::function<double*(int inst, int x)>;
 
@@ -198,6 +241,7 @@ void trace_executor(ftcc_ctx* c, const char* which, const Executor& ex);
 void sync(ftcc_ctx* c);
 void thermal_setup(ftcc_ctx* c, int i);
 void deriv_setup(ftcc_ctx* c, int i, int which, const double* d_dh, const double* d_deri);
+void deriv_setup_eps(ftcc_ctx* c, int i, int q);
 long node_len_of(long n);
 void check_momentum(ftcc_ctx* c, int i, const double* x, int rank, const char* what);
 bool momentum_on(const ftcc_ctx* c);
@@ -214,6 +258,8 @@ void forward(ftcc_ctx* c);
 void backward(ftcc_ctx* c);
 void d_forward(ftcc_ctx* c);
 void clear_tau_cache(ftcc_ctx* c);
+int tau_problems(ftcc_ctx* c, int mode, int panel, double* partial_base, std::vector<TauProblem>& ps,
+                 std::vector<int>& prefix);
 void tau_run(ftcc_ctx* c, int mode, int panel);
 void set_active(ftcc_ctx* c, const std::vector<bool>& active);
 void set_run(ftcc_ctx* c, const std::vector<bool>& run);
@@ -242,6 +288,15 @@ void rk_recompute_stages(ftcc_ctx* c, int p);
 void set_ebar(ftcc_ctx* c, int x, int grid_point);
 void rk_solve(ftcc_ctx* c, std::vector<int>& status);
 void rk_lambda(ftcc_ctx* c, std::vector<int>& status);
+
+// simpson_march.hip: the implicit integral form generated by Simpson's rule
+std::vector<double> simpson_row(int y);
+void expsum_run(ftcc_ctx* c, long key, const std::function<ExpSpec(int)>& spec);
+void simpson_solve(ftcc_ctx* c, std::vector<int>& status, std::vector<int>& total);
+void simpson_lambda(ftcc_ctx* c, std::vector<int>& status, std::vector<int>& total);
+void simpson_lamt(ftcc_ctx* c, int x);
+void simpson_grid_term(ftcc_ctx* c, int y, int mode, const std::function<double*(int)>& out,
+                       const std::function<const double*(int)>& prod);
 
 // density.hip: the two-body response density
 void build_gamma_executor(ftcc_ctx* c);

@@ -158,6 +158,7 @@ int ftcc_two_body_density(ftcc_ctx* c, double* gamma) {
   return run_guarded([&] {
     if (!c || !gamma) fail(FTCC_EINVAL, "null argument");
     if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
+    if (c->simpson) fail(FTCC_EINVAL, "the two-body density is built for propagators 0 to 4");
     FTCC_HIP(hipSetDevice(c->device));
     build_gamma_executor(c);
     const int B = c->B, m = c->m, P = c->P;

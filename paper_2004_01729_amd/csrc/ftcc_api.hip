@@ -114,6 +114,72 @@ __global__ void dh_assemble_kernel(int n, const double* occ, const double* wo, c
   out[e] = v;
 }
 
+// Direction of the orbital energy eps_q at a frozen reference: dn_p = dn_p/deps_q =
+// -beta n_q (1 - n_q) delta_pq (the weights follow, dw = dn / (2 w) on kept slots),
+// and the explicit dependence of u = f - diag(eps): du = -e_q e_q^T (in dh).
+__global__ void occ_deriv_eps_kernel(int n, int q, const double* eps, const double* occ, const double* wo,
+                                     const double* wv, double mu, double beta, double* dn, double* dwo, double* dwv,
+                                     double* dh) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < (long)n * n) dh[e] = (e == (long)q * n + q) ? -1.0 : 0.0;
+  if (e >= n) return;
+  const int p = (int)e;
+  double d = 0.0;
+  if (p == q) {
+    const double x = beta * (eps[p] - mu);
+    const double nvir = (x > 0.0) ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x));
+    d = -beta * occ[p] * nvir;
+  }
+  dn[p] = d;
+  dwo[p] = (wo[p] > 0.0) ? d / (2.0 * wo[p]) : 0.0;
+  dwv[p] = (wv[p] > 0.0) ? -d / (2.0 * wv[p]) : 0.0;
+}
+
+// Mean-field part of dOmega/deps_q: Omega_0 gives g n_q and the explicit -eps_q n_q of
+// Omega_1 gives -g n_q (they cancel); what remains is Omega_1 through the occupation,
+// g (f_qq - eps_q) dn_q/deps_q = -g (f_qq - eps_q) beta n_q (1 - n_q).
+__global__ void deps_meanfield_kernel(int n, const double* eps, const double* occ, const double* fock, double mu,
+                                      double beta, double g, double* out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double x = beta * (eps[q] - mu);
+  const double nvir = (x > 0.0) ? 1.0 / (1.0 + exp(-x)) : exp(x) / (1.0 + exp(x));
+  out[q] = -g * (fock[(long)q * n + q] - eps[q]) * beta * occ[q] * nvir;
+}
+
+// out[q] += sum over the amplitude elements of D[e] dDelta_e/deps_q (Delta_i^a = eps_a - eps_i
+// on t1[i][a], Delta_ij^ab = eps_a + eps_b - eps_i - eps_j on t2[i][j][a][b]); D is one node
+// state (t1 block, then t2 block).  One block per orbital, fixed summation order.
+__global__ void __launch_bounds__(256) deps_reduce_kernel(int n, const double* __restrict__ D, double* out) {
+  const int q = blockIdx.x;
+  const long n2 = (long)n * n, n3 = n2 * n;
+  const double* t2 = D + n2;
+  double acc = 0.0;
+  for (long r = threadIdx.x; r < n; r += blockDim.x) acc += D[r * n + q] - D[(long)q * n + r];
+  for (long r = threadIdx.x; r < n3; r += blockDim.x) {
+    // r enumerates the other three indices of each slot in row-major order
+    const long hi = r / n2, mid = (r / n) % n, lo = r % n;
+    acc -= t2[(long)q * n3 + r];                                // i = q
+    acc -= t2[hi * n3 + (long)q * n2 + mid * n + lo];           // j = q
+    acc += t2[hi * n3 + mid * n2 + (long)q * n + lo];           // a = q
+    acc += t2[hi * n3 + mid * n2 + lo * n + q];                 // b = q
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[q] += red[0];
+}
+
+// y[e] += a[e] * b[e]
+__global__ void mul_acc_kernel(long len, const double* a, const double* b, double* y) {
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < len; e += (long)gridDim.x * blockDim.x)
+    y[e] += a[e] * b[e];
+}
+
 // Elements of a one-body (rank 2, law k_p = k_q) or two-body (rank 4,
 // k_p + k_q = k_r + k_s) array that are nonzero although momentum forbids them;
 // any such element sets *bad (plain stores of the same value).
@@ -393,6 +459,48 @@ void deriv_setup(ftcc_ctx* c, int i, int which, const double* d_dh, const double
   FTCC_HIP(hipGetLastError());
 }
 
+// derivative blocks along the orbital energy eps_q (occupation and explicit u parts)
+void deriv_setup_eps(ftcc_ctx* c, int i, int q) {
+  Instance& I = c->inst[i];
+  const int n = I.n;
+  const long n2 = (long)n * n;
+  hipLaunchKernelGGL(occ_deriv_eps_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, c->stream, n, q, I.eps,
+                     I.occ, I.wo, I.wv, I.mu, I.beta, I.dn, I.dwo, I.dwv, I.deps_dh);
+  launch_fock_deriv(n, I.eri, nullptr, I.deps_dh, I.occ, I.dn, c->gdeg, I.du_raw, c->stream);
+  for (int k = 0; k < 4; ++k) {
+    BlockSpec b;
+    b.n = n;
+    b.rank = 2;
+    b.pat[0] = kU[k][2];
+    b.pat[1] = kU[k][3];
+    b.base = I.u_raw;
+    b.dbase = I.du_raw;
+    b.wo = I.wo;
+    b.wv = I.wv;
+    b.dwo = I.dwo;
+    b.dwv = I.dwv;
+    b.out = I.dblk[kU[k]];
+    launch_block(b, c->stream);
+  }
+  for (int k = 0; k < 12; ++k) {
+    BlockSpec b;
+    b.n = n;
+    b.rank = 4;
+    for (int s = 0; s < 4; ++s) b.pat[s] = kG[k][2 + s];
+    b.base = I.eri;
+    b.dbase = nullptr;
+    b.wo = I.wo;
+    b.wv = I.wv;
+    b.dwo = I.dwo;
+    b.dwv = I.dwv;
+    b.out = I.dblk[kG[k]];
+    b.idx = I.d_allowed[1];
+    b.count = I.n_allowed[1];
+    launch_block(b, c->stream);
+  }
+  FTCC_HIP(hipGetLastError());
+}
+
 long node_len_of(long n) { return n * n + n * n * n * n; }
 
 // Throws FTCC_EINVAL when a rank-2 or rank-4 array of instance i breaks the
@@ -528,11 +636,12 @@ void build(ftcc_ctx* c) {
     // Lambda of every node and the panel-boundary adjoint states a_p, allocated up
     // front so that the optional caches below are sized to what is left;
     // lambda-tilde is not stored (recomputed from lambda and a_{p+1} when needed)
-    I.lam.resize(P * m);
-    for (int k = 0; k < P * m; ++k) I.lam[k] = c->dalloc(len);
+    const int nlam = c->simpson ? P + 1 : P * m;
+    I.lam.resize(nlam);
+    for (int k = 0; k < nlam; ++k) I.lam[k] = c->dalloc(len);
     I.abuf.resize(P + 1);
     for (int p = 0; p <= P; ++p) I.abuf[p] = c->dalloc(len);
-    if (!c->opt.checkpoint && !c->rk) {
+    if (!c->opt.checkpoint && !c->rk && !c->simpson) {
       I.grid.resize(P * m);
       I.resid.resize(P * m);
       for (int k = 0; k < P * m; ++k) {
@@ -540,14 +649,14 @@ void build(ftcc_ctx* c) {
         I.resid[k] = c->dalloc(len);
       }
     }
-    I.energies.assign(c->rk ? P + 1 : P * m, 0.0);
-    if (c->rk) {
+    I.energies.assign((c->rk || c->simpson) ? P + 1 : P * m, 0.0);
+    if (c->rk || c->simpson) {
       I.rk_tmp[0] = c->dalloc(len);
       I.rk_tmp[1] = c->dalloc(len);
       I.rk_hbar = c->dalloc(1);
     }
   }
-  if (c->rk) {
+  if (c->rk || c->simpson) {
     // (1/beta) g_k of Simpson's rule on the uniform grid: w_k / (3 n_g), w = 1 4 2 ... 4 1
     std::vector<double> w(P + 1);
     for (int k = 0; k <= P; ++k) w[k] = ((k == 0 || k == P) ? 1.0 : (k % 2 ? 4.0 : 2.0)) / (3.0 * P);
@@ -565,7 +674,7 @@ void build(ftcc_ctx* c) {
     c->slots = (need > 0.5 * c->available()) ? 1 : m;
     const char* senv = std::getenv("FTCC_NODE_SLOTS");
     if (senv && senv[0] == '1') c->slots = 1;
-    if (c->rk) c->slots = 1;   // the stages of an explicit step are evaluated in turn
+    if (c->rk || c->simpson) c->slots = 1;   // stages / grid points are evaluated in turn
   }
   const int SL = c->slots;
   const int nn = B * m;
@@ -930,19 +1039,21 @@ void clear_tau_cache(ftcc_ctx* c) {
   c->rk_blocks.clear();
   for (auto& kv : c->rk_dots) (void)hipFree(kv.second);
   c->rk_dots.clear();
+  for (auto& kv : c->sp_cache) (void)hipFree(kv.second.buf);
+  c->sp_cache.clear();
 }
 
 // Descriptor set for the propagator: per instance two segments (t1, t2).
 // `panel` selects per-panel buffers (sb, lambda, a, ...).  Descriptors are built
 // once per (mode, panel) and kept until the next solve (beta may change).
-void tau_run(ftcc_ctx* c, int mode, int panel) {
+// Host descriptors of one propagator launch (mode, panel): per instance the t1 and
+// t2 segments; TAU_BETA partial sums go to partial_base (one per 1024 elements).
+int tau_problems(ftcc_ctx* c, int mode, int panel, double* partial_base, std::vector<TauProblem>& ps,
+                 std::vector<int>& prefix) {
   const int B = c->B, m = c->m;
-  const auto key = std::make_pair(mode, panel);
-  auto it = c->tau_cache.find(key);
-  if (it == c->tau_cache.end()) {
-    std::vector<TauProblem> ps;
-    std::vector<int> prefix;
-    int total = 0;
+  int total = 0;
+  ps.clear();
+  prefix.clear();
     for (int i = 0; i < B; ++i) {
       Instance& I = c->inst[i];
       const long n = I.n, n2 = n * n, n4 = n2 * n2;
@@ -981,23 +1092,36 @@ void tau_run(ftcc_ctx* c, int mode, int panel) {
               t.S[x] = I.lam[panel * m + x] + off;
               break;
             case TAU_BETA:      // S = lambda, R = converged residuals
+            case TAU_DEPS:
               t.S[x] = I.lam[panel * m + x] + off;
               t.R[x] = c->S[p] + off;
               break;
           }
         }
-        if (mode == TAU_INIT || mode == TAU_STEP || mode == TAU_END || mode == TAU_BETA) t.sb = I.sb[panel] + off;
+        if (mode == TAU_INIT || mode == TAU_STEP || mode == TAU_END || mode == TAU_BETA || mode == TAU_DEPS)
+          t.sb = I.sb[panel] + off;
         if (mode == TAU_END) t.out = I.sb[panel + 1] + off;
         if (mode == TAU_LAMT || mode == TAU_APREV) t.sb = I.abuf[panel + 1] + off;
         if (mode == TAU_APREV) t.out = I.abuf[panel] + off;
-        if (mode == TAU_BETA) t.lam_a = I.abuf[panel + 1] + off;
+        if (mode == TAU_BETA || mode == TAU_DEPS) t.lam_a = I.abuf[panel + 1] + off;
+        if (mode == TAU_DEPS) t.out = I.deps_delta + off;
         const int nb = (int)((t.len + 1023) / 1024);
-        t.partial = c->d_partial + (long)total;
+        t.partial = partial_base + (long)total;
         prefix.push_back(total);
         total += nb;
         ps.push_back(t);
       }
     }
+  return total;
+}
+
+void tau_run(ftcc_ctx* c, int mode, int panel) {
+  const auto key = std::make_pair(mode, panel);
+  auto it = c->tau_cache.find(key);
+  if (it == c->tau_cache.end()) {
+    std::vector<TauProblem> ps;
+    std::vector<int> prefix;
+    const int total = tau_problems(c, mode, panel, c->d_partial, ps, prefix);
     TauProblem* d_ps = nullptr;
     int* d_pre = nullptr;
     FTCC_HIP(hipMalloc((void**)&d_ps, sizeof(TauProblem) * ps.size()));
@@ -1149,6 +1273,7 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
   NodeBufs amp_of = [c](int i, int x) { return c->amp[i * c->m + x]; };
   if (diis) diis_reset(c);
   set_run(c, active);   // converged or failed instances stop costing residual evaluations
+  std::vector<DivergenceWatch> watch(B);
   for (int it = 1; it <= c->opt.max_iter; ++it) {
     forward(c);
     c->resid_evals += n_running(c) * c->m;
@@ -1168,6 +1293,11 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
         continue;
       }
       if (chg <= c->opt.tol * std::max(1.0, val)) {
+        active[i] = false;
+        continue;
+      }
+      if (watch[i].diverged(chg)) {
+        status[i] = FTCC_EDIVERGE;
         active[i] = false;
         continue;
       }
@@ -1220,11 +1350,12 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
     ftcc_options o;
     ftcc_default_options(&o);
     if (opt) o = *opt;
-    if (o.propagator < 0 || o.propagator > 4) fail(FTCC_EINVAL, "propagator must be 0..4");
-    const bool rk = o.propagator >= 2;
-    if (rk) {
-      if (o.n_tau < 2 || o.n_tau % 2) fail(FTCC_EINVAL, "the Runge-Kutta forms need an even n_tau >= 2 (Simpson)");
-      if (o.diis_depth != 0) fail(FTCC_EINVAL, "diis_depth applies to the integral form only");
+    if (o.propagator < 0 || o.propagator > 5) fail(FTCC_EINVAL, "propagator must be 0..5");
+    const bool rk = o.propagator >= 2 && o.propagator <= 4;
+    const bool simpson = o.propagator == 5;
+    if (rk || simpson) {
+      if (o.n_tau < 2 || o.n_tau % 2) fail(FTCC_EINVAL, "the uniform-grid forms need an even n_tau >= 2 (Simpson)");
+      if (o.diis_depth != 0) fail(FTCC_EINVAL, "diis_depth applies to the Gauss-Legendre integral form only");
     } else {
       if (o.nodes_per_panel < 1 || o.nodes_per_panel > kMaxNodes)
         fail(FTCC_EINVAL, "nodes_per_panel must be 1..6");
@@ -1270,6 +1401,11 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
       }
       c->P = o.n_tau;
       c->rule = make_rule(c->m, 0);   // unused by the march; keeps the device rule valid
+    } else if (simpson) {
+      c->simpson = true;
+      c->m = 1;
+      c->P = o.n_tau;
+      c->rule = make_rule(1, 0);      // unused by the march; keeps the device rule valid
     } else {
       c->m = o.nodes_per_panel;
       c->P = o.n_tau / o.nodes_per_panel;
@@ -1407,7 +1543,8 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
     std::vector<double> ebuf(B * m);
     const auto wall0 = std::chrono::steady_clock::now();
     if (c->rk) rk_solve(c, status);
-    for (int p = 0; p < (c->rk ? 0 : P); ++p) {
+    if (c->simpson) simpson_solve(c, status, total);
+    for (int p = 0; p < ((c->rk || c->simpson) ? 0 : P); ++p) {
       std::vector<int> its = panel_solve(c, p, status);
       for (int i = 0; i < B; ++i) total[i] += its[i];
       for (int i = 0; i < B; ++i) {
@@ -1440,7 +1577,7 @@ int ftcc_solve_amplitudes(ftcc_ctx* c, const double* mu, const double* beta, int
       FTCC_HIP(hipMemcpy(mf, I.mf, sizeof(mf), hipMemcpyDeviceToHost));
       I.omega0 = mf[0];
       I.omega1 = mf[1];
-      if (!c->rk) {
+      if (!c->rk && !c->simpson) {
         double occ_cc = 0.0;
         for (int p = 0; p < P; ++p)
           for (int x = 0; x < m; ++x) occ_cc += c->rule.b[x] / P * I.energies[p * m + x];
@@ -1483,13 +1620,14 @@ int ftcc_get_amplitudes(ftcc_ctx* c, int i, int k, double* t1, double* t2) {
   return run_guarded([&] {
     if (!c || !t1 || !t2) fail(FTCC_EINVAL, "null argument");
     if (!c->solved) fail(FTCC_ESTATE, "call ftcc_solve_amplitudes first");
-    if (c->opt.checkpoint && !c->rk) fail(FTCC_ESTATE, "amplitudes are not kept with checkpoint = 1");
-    // differential form: the grid states s(tau_k), k = 0..n_tau
-    if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau + (c->rk ? 1 : 0)) fail(FTCC_EINVAL, "index out of range");
+    const bool uniform = c->rk || c->simpson;
+    if (c->opt.checkpoint && !uniform) fail(FTCC_ESTATE, "amplitudes are not kept with checkpoint = 1");
+    // uniform-grid forms: the grid states s(tau_k), k = 0..n_tau
+    if (i < 0 || i >= c->B || k < 0 || k >= c->opt.n_tau + (uniform ? 1 : 0)) fail(FTCC_EINVAL, "index out of range");
     const long n = c->inst[i].n, n2 = n * n;
     FTCC_HIP(hipSetDevice(c->device));
     sync(c);
-    const double* src = c->rk ? c->inst[i].sb[k] : c->inst[i].grid[k];
+    const double* src = uniform ? c->inst[i].sb[k] : c->inst[i].grid[k];
     FTCC_HIP(hipMemcpy(t1, src, sizeof(double) * n2, hipMemcpyDeviceToHost));
     FTCC_HIP(hipMemcpy(t2, src + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
   });
@@ -1553,7 +1691,8 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
       rk_lambda(c, status);
       for (int i = 0; i < B; ++i) total[i] = P;
     }
-    for (int p = (c->rk ? -1 : P - 1); p >= 0; --p) {
+    if (c->simpson) simpson_lambda(c, status, total);
+    for (int p = ((c->rk || c->simpson) ? -1 : P - 1); p >= 0; --p) {
       const std::vector<int> before = total;
       load_panel(c, p);
       // lambda_x = -(g_x/beta) dE/ds : backward with zero S-cotangent
@@ -1571,6 +1710,7 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
       const bool diis = c->opt.diis_depth > 0;
       NodeBufs lam_of = [c, p](int i, int x) { return c->inst[i].lam[p * c->m + x]; };
       if (diis) diis_reset(c);
+      std::vector<DivergenceWatch> watch(B);
       for (int it = 1; it <= c->opt.max_iter; ++it) {
         tau_run(c, TAU_LAMT, p);
         backward(c);
@@ -1591,6 +1731,11 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
             continue;
           }
           if (chg <= c->opt.tol * std::max(val, 1e-30) || chg == 0.0) {
+            active[i] = false;
+            continue;
+          }
+          if (watch[i].diverged(chg)) {
+            status[i] = FTCC_EDIVERGE;
             active[i] = false;
             continue;
           }
@@ -1639,6 +1784,22 @@ int ftcc_get_lambda(ftcc_ctx* c, int i, int k, double* l1, double* l2, double* l
   return run_guarded([&] {
     if (!c) fail(FTCC_EINVAL, "null context");
     if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
+    if (c->simpson) {
+      // Simpson integral form: lambda of grid point k, k = 0..n_tau (lambda_0 = 0)
+      if (i < 0 || i >= c->B || k < 0 || k > c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
+      const long n = c->inst[i].n, n2 = n * n;
+      FTCC_HIP(hipSetDevice(c->device));
+      if (lt1 || lt2) {
+        run_all(c);
+        simpson_lamt(c, k);
+      }
+      sync(c);
+      if (l1) FTCC_HIP(hipMemcpy(l1, c->inst[i].lam[k], sizeof(double) * n2, hipMemcpyDeviceToHost));
+      if (l2) FTCC_HIP(hipMemcpy(l2, c->inst[i].lam[k] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+      if (lt1) FTCC_HIP(hipMemcpy(lt1, c->cot[i * c->m], sizeof(double) * n2, hipMemcpyDeviceToHost));
+      if (lt2) FTCC_HIP(hipMemcpy(lt2, c->cot[i * c->m] + n2, sizeof(double) * n2 * n2, hipMemcpyDeviceToHost));
+      return;
+    }
     if (c->rk) {
       // differential form: the cotangent of the grid state s(tau_k), k = 0..n_tau
       if (i < 0 || i >= c->B || k < 0 || k > c->opt.n_tau) fail(FTCC_EINVAL, "index out of range");
@@ -1666,13 +1827,29 @@ int ftcc_get_lambda(ftcc_ctx* c, int i, int k, double* l1, double* l2, double* l
   });
 }
 
-int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, const double* const* deri_dtheta,
-                  const double* const* dh_dtheta, double* dO_dtheta) {
+int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, double* dO_deps,
+                  const double* const* deri_dtheta, const double* const* dh_dtheta, double* dO_dtheta) {
   return run_guarded([&] {
     if (!c) fail(FTCC_EINVAL, "null context");
     if (!c->have_lambda) fail(FTCC_ESTATE, "call ftcc_lambda first");
     FTCC_HIP(hipSetDevice(c->device));
     const int B = c->B, m = c->m, P = c->P;
+    int nmax = 0;
+    for (int i = 0; i < B; ++i) nmax = std::max(nmax, c->inst[i].n);
+    if (dO_deps) {
+      for (int i = 0; i < B; ++i) {
+        Instance& I = c->inst[i];
+        const long n = I.n;
+        if (!I.deps_acc) {
+          I.deps_acc = c->dalloc(n);
+          I.deps_out = c->dalloc(n);
+          I.deps_dh = c->dalloc(n * n);
+          I.deps_delta = c->dalloc(node_len(c, i));
+        }
+        zero_d(c, I.deps_acc, n);
+        zero_d(c, I.deps_delta, node_len(c, i));
+      }
+    }
     const bool want_theta = dO_dtheta && (deri_dtheta || dh_dtheta);
     // device copies of the theta directions
     std::vector<double*> d_deri(B, nullptr), d_dh(B, nullptr);
@@ -1744,6 +1921,36 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         for (int x = 0; x < m; ++x)
           launch_axpby(1, c->rule.b[x] / P, c->de[i * m + x], 1.0, c->inst[i].acc + slot, c->stream);
     };
+    // the same for the orbital-energy direction q: into deps_acc[q] of the
+    // instances with more than q orbitals
+    auto accumulate_eps = [&](int q) {
+      for (int i = 0; i < B; ++i) {
+        if (q >= c->inst[i].n) continue;
+        const long n = c->inst[i].n;
+        for (int x = 0; x < m; ++x) {
+          DotProblem d{};
+          d.X = c->cot[i * m + x];
+          d.Y = c->dS[i * m + x];
+          d.out = c->inst[i].deps_acc + q;
+          d.len = n * n + n * n * n * n;
+          if (c->inst[i].d_allowed[0]) {
+            d.ia = c->inst[i].d_allowed[0];
+            d.na = c->inst[i].n_allowed[0];
+            d.ib = c->inst[i].d_allowed[1];
+            d.nb = c->inst[i].n_allowed[1];
+            d.second = n * n;
+          }
+          d.alpha = 1.0;
+          d.beta = 1.0;
+          DotProblem* dd = nullptr;
+          FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem), c->stream));
+          FTCC_HIP(hipMemcpyAsync(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice, c->stream));
+          launch_dot(dd, 1, 64, c->scratch.dot_partial, c->stream);
+          FTCC_HIP(hipFreeAsync(dd, c->stream));
+          launch_axpby(1, c->rule.b[x] / P, c->de[i * m + x], 1.0, c->inst[i].deps_acc + q, c->stream);
+        }
+      }
+    };
     const auto wall0 = std::chrono::steady_clock::now();
     if (c->rk) {
       // differential form: every grid point k (energy weight) and every stage of
@@ -1794,6 +2001,41 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
               for (int i = 0; i < B; ++i)
                 if (ok[i]) launch_axpby(1, wk, c->de[i * m], 1.0, c->inst[i].acc + which, c->stream);
           }
+          if (dO_deps) {
+            // the slopes' Delta dependence, d k / d Delta = -Y, weighted by the slope
+            // cotangent: cot = -kbar, so dL/dDelta += cot * Y (stage state in amp)
+            if (k < P)
+              for (int i = 0; i < B; ++i) {
+                if (!ok[i]) continue;
+                const long len = node_len(c, i);
+                hipLaunchKernelGGL(mul_acc_kernel, dim3((unsigned)std::min<long>((len + 255) / 256, 65536)),
+                                   dim3(256), 0, c->stream, len, c->cot[i * m + x], c->amp[i * m + x],
+                                   c->inst[i].deps_delta);
+              }
+            for (int q = 0; q < nmax; ++q) {
+              for (int i = 0; i < B; ++i)
+                if (q < c->inst[i].n) deriv_setup_eps(c, i, q);
+              c->ex_d->run_setup(c->stream);
+              d_forward_one(c, x);
+              for (int i = 0; i < B; ++i) {
+                if (!ok[i] || q >= c->inst[i].n) continue;
+                const long n = c->inst[i].n;
+                DotProblem d{};
+                d.X = c->cot[i * m + x];
+                d.Y = c->dS[i * m + x];
+                d.out = c->inst[i].deps_acc + q;
+                d.len = n * n + n * n * n * n;
+                d.alpha = 1.0;
+                d.beta = 1.0;
+                DotProblem* dd = nullptr;
+                FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem), c->stream));
+                FTCC_HIP(hipMemcpyAsync(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice, c->stream));
+                launch_dot(dd, 1, 64, c->scratch.dot_partial, c->stream);
+                FTCC_HIP(hipFreeAsync(dd, c->stream));
+                if (x == 0) launch_axpby(1, wk, c->de[i * m], 1.0, c->inst[i].deps_acc + q, c->stream);
+              }
+            }
+          }
         }
         if (trace_on()) {
           sync(c);
@@ -1803,7 +2045,111 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
       if (dO_dbeta)
         for (int i = 0; i < B; ++i) launch_axpby(1, 1.0 / P, c->inst[i].rk_hbar, 0.0, c->inst[i].acc + 3, c->stream);
     }
-    for (int p = 0; p < (c->rk ? 0 : P); ++p) {
+    if (c->simpson) {
+      // Simpson integral form: every grid point x (energy weight g_x / beta and
+      // cotangent lamt_x of its residual), then the grid terms of beta and Delta
+      std::vector<bool> ok(B);
+      for (int i = 0; i < B; ++i) ok[i] = c->inst[i].status == 0 && c->inst[i].lam_status == 0;
+      set_run(c, ok);
+      const std::vector<double> g = simpson_row(P);
+      auto dot_into = [&](const double* X, const double* Y, std::function<double*(int)> out) {
+        for (int i = 0; i < B; ++i) {
+          if (!ok[i]) continue;
+          DotProblem d{};
+          d.X = X ? X : c->cot[i * m];
+          d.Y = Y ? Y : c->dS[i * m];
+          d.out = out(i);
+          d.len = node_len(c, i);
+          d.alpha = 1.0;
+          d.beta = 1.0;
+          DotProblem* dd = nullptr;
+          FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem), c->stream));
+          FTCC_HIP(hipMemcpyAsync(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice, c->stream));
+          launch_dot(dd, 1, 64, c->scratch.dot_partial, c->stream);
+          FTCC_HIP(hipFreeAsync(dd, c->stream));
+        }
+      };
+      for (int x = 0; x <= P; ++x) {
+        const double wx = g[x] / P;   // (1/beta) g_x
+        simpson_lamt(c, x);
+        for (int i = 0; i < B; ++i)
+          if (ok[i]) node_copy(c, i, c->amp[i * m], c->inst[i].sb[x]);
+        if (dO_dh) {
+          set_ebar(c, 0, x);
+          forward(c);
+          backward(c);
+          for (int i = 0; i < B; ++i) {
+            if (!ok[i]) continue;
+            const long n = c->inst[i].n;
+            for (int k = 0; k < 4; ++k)
+              launch_axpby(n * n, 1.0, c->ugrad[i * m][k], 1.0, c->inst[i].ugrad_acc[k], c->stream);
+          }
+        }
+        for (int which = 0; which < 3; ++which) {
+          if (which == 0 && !dO_dmu) continue;
+          if (which == 1 && !dO_dbeta) continue;
+          if (which == 2 && !want_theta) continue;
+          for (int i = 0; i < B; ++i) deriv_setup(c, i, which, d_dh[i], d_deri[i]);
+          c->ex_d->run_setup(c->stream);
+          d_forward_one(c, 0);
+          dot_into(nullptr, nullptr, [c, which](int i) { return c->inst[i].acc + which; });
+          for (int i = 0; i < B; ++i)
+            if (ok[i]) launch_axpby(1, wx, c->de[i * m], 1.0, c->inst[i].acc + which, c->stream);
+        }
+        if (dO_deps) {
+          for (int q = 0; q < nmax; ++q) {
+            for (int i = 0; i < B; ++i)
+              if (q < c->inst[i].n) deriv_setup_eps(c, i, q);
+            c->ex_d->run_setup(c->stream);
+            d_forward_one(c, 0);
+            for (int i = 0; i < B; ++i) {
+              if (!ok[i] || q >= c->inst[i].n) continue;
+              DotProblem d{};
+              d.X = c->cot[i * m];
+              d.Y = c->dS[i * m];
+              d.out = c->inst[i].deps_acc + q;
+              d.len = node_len(c, i);
+              d.alpha = 1.0;
+              d.beta = 1.0;
+              DotProblem* dd = nullptr;
+              FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem), c->stream));
+              FTCC_HIP(hipMemcpyAsync(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice, c->stream));
+              launch_dot(dd, 1, 64, c->scratch.dot_partial, c->stream);
+              FTCC_HIP(hipFreeAsync(dd, c->stream));
+              launch_axpby(1, wx, c->de[i * m], 1.0, c->inst[i].deps_acc + q, c->stream);
+            }
+          }
+        }
+      }
+      for (int y = 1; y <= P; ++y) {
+        if (dO_dbeta) {   // (1/n_g) sum_y <lam_y, sum_x d/dh[G^y_x e^{-Delta h (y-x)}] S_x>
+          if (y == 1)
+            for (int i = 0; i < B; ++i) zero_d(c, c->inst[i].rk_hbar, 1);
+          simpson_grid_term(c, y, 1, [c](int i) { return c->inst[i].rk_tmp[0]; }, nullptr);
+          for (int i = 0; i < B; ++i) {
+            if (!ok[i]) continue;
+            DotProblem d{};
+            d.X = c->inst[i].lam[y];
+            d.Y = c->inst[i].rk_tmp[0];
+            d.out = c->inst[i].rk_hbar;
+            d.len = node_len(c, i);
+            d.alpha = 1.0;
+            d.beta = 1.0;
+            DotProblem* dd = nullptr;
+            FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem), c->stream));
+            FTCC_HIP(hipMemcpyAsync(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice, c->stream));
+            launch_dot(dd, 1, 64, c->scratch.dot_partial, c->stream);
+            FTCC_HIP(hipFreeAsync(dd, c->stream));
+          }
+        }
+        if (dO_deps)      // dL/dDelta elementwise: lam_y * sum_x d/dDelta[G^y_x e^{-Delta h (y-x)}] S_x
+          simpson_grid_term(c, y, 2, [c](int i) { return c->inst[i].deps_delta; },
+                            [c, y](int i) { return (const double*)c->inst[i].lam[y]; });
+      }
+      if (dO_dbeta)
+        for (int i = 0; i < B; ++i) launch_axpby(1, 1.0 / P, c->inst[i].rk_hbar, 0.0, c->inst[i].acc + 3, c->stream);
+    }
+    for (int p = 0; p < ((c->rk || c->simpson) ? 0 : P); ++p) {
       if (trace_on() && p > 0) {
         sync(c);
         trace(c, "response", p, P, std::vector<int>(1, 0), wall0);
@@ -1839,6 +2185,18 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         d_forward(c);
         accumulate(which);
       }
+      if (dO_deps) {
+        // the propagator weights' Delta dependence (elementwise), then one
+        // derivative-integral evaluation per orbital energy
+        tau_run(c, TAU_DEPS, p);
+        for (int q = 0; q < nmax; ++q) {
+          for (int i = 0; i < B; ++i)
+            if (q < c->inst[i].n) deriv_setup_eps(c, i, q);
+          c->ex_d->run_setup(c->stream);
+          d_forward(c);
+          accumulate_eps(q);
+        }
+      }
     }
     run_all(c);
     // mean-field parts and assembly
@@ -1859,6 +2217,20 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
         for (int k = 0; k < i; ++k) off += (long)c->inst[k].n * c->inst[k].n;
         FTCC_HIP(hipMemcpyAsync(dO_dh + off, dd, sizeof(double) * n2, hipMemcpyDeviceToHost, c->stream));
         FTCC_HIP(hipFreeAsync(dd, c->stream));
+      }
+    }
+    if (dO_deps) {
+      long off = 0;
+      for (int i = 0; i < B; ++i) {
+        Instance& I = c->inst[i];
+        const int n = I.n;
+        hipLaunchKernelGGL(deps_meanfield_kernel, dim3((n + 63) / 64), dim3(64), 0, c->stream, n, I.eps, I.occ,
+                           I.fock, I.mu, I.beta, c->gdeg, I.deps_out);
+        launch_axpby(n, 1.0, I.deps_acc, 1.0, I.deps_out, c->stream);
+        hipLaunchKernelGGL(deps_reduce_kernel, dim3(n), dim3(256), 0, c->stream, n, I.deps_delta, I.deps_out);
+        FTCC_HIP(hipGetLastError());
+        FTCC_HIP(hipMemcpyAsync(dO_deps + off, I.deps_out, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+        off += n;
       }
     }
     sync(c);
@@ -1970,10 +2342,10 @@ int ftcc_find_mu(ftcc_ctx* c, const double* n_target, double* mu, const double* 
       for (int i = 0; i < B; ++i) any = any || phase[i] != DONE;
       if (!any) break;
       int r = ftcc_solve_amplitudes(c, x.data(), beta, nullptr, fst.data());
-      if (r != FTCC_OK && r != FTCC_ENOCONV && r != FTCC_ENONFINITE) fail(r, g_err);
+      if (r != FTCC_OK && r != FTCC_ENOCONV && r != FTCC_ENONFINITE && r != FTCC_EDIVERGE) fail(r, g_err);
       r = ftcc_lambda(c, nullptr, lst.data());
-      if (r != FTCC_OK && r != FTCC_ENOCONV && r != FTCC_ENONFINITE) fail(r, g_err);
-      r = ftcc_response(c, dmu.data(), nullptr, nullptr, nullptr, nullptr, nullptr);
+      if (r != FTCC_OK && r != FTCC_ENOCONV && r != FTCC_ENONFINITE && r != FTCC_EDIVERGE) fail(r, g_err);
+      r = ftcc_response(c, dmu.data(), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
       if (r != FTCC_OK) fail(r, g_err);
       for (int i = 0; i < B; ++i) {
         if (phase[i] == DONE) continue;

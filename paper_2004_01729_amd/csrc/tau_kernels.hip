@@ -11,7 +11,10 @@
 // its Taylor series for |z| <= 4 and by the recurrence
 // phi_{k+1} = (phi_k - 1/k!) / z from phi_1 = expm1(z)/z otherwise (both
 // directions are well conditioned there).  The h-derivative used by the beta
-// response is d/dh [h phi_{k+1}(a h)] = (z - k) phi_{k+1}(z) + 1/k!.
+// response is d/dh [h phi_{k+1}(a h)] = (z - k) phi_{k+1}(z) + 1/k!; the
+// D-derivative used by the orbital-energy response follows from
+// phi_k'(z) = phi_k(z) - k phi_{k+1}(z):
+// d/dD [h phi_{k+1}(-D h c)] = -h^2 c (phi_{k+1}(z) - (k+1) phi_{k+2}(z)).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -58,36 +61,43 @@ struct Weights {
   double E[M], W[M][M], We[M], Ee;
 };
 
-// need_end: also the panel-end row (Ee, We).
+// need_end: also the panel-end row (Ee, We).  deriv: 0 the weights, 1 their
+// h-derivatives at fixed D, 2 their D-derivatives at fixed h.
 template <int M>
-__device__ void weights(const PanelRule& R, double D, double h, Weights<M>& w, bool deriv, bool need_end) {
+__device__ void weights(const PanelRule& R, double D, double h, Weights<M>& w, int deriv, bool need_end) {
   // R is the rule in global memory (uniform across the grid: scalar loads)
   constexpr int m = M;
-  double phi[M + 1];
+  double phi[M + 2];
   for (int x = 0; x <= m; ++x) {
     if (x == m && !need_end) break;
     const double cx = (x < m) ? R.c[x] : 1.0;
     const double z = -D * h * cx;
     double e = exp(z);
-    if (deriv) e = -D * cx * e;            // dE/dh
+    if (deriv == 1) e = -D * cx * e;            // dE/dh
+    else if (deriv == 2) e = -h * cx * e;       // dE/dD
     if (x < m) w.E[x] = e; else w.Ee = e;
     if (R.lawson) {
       for (int y = 0; y < m; ++y) {
         const double arg = D * h * (R.c[y] - cx);
         const double a = (x < m) ? R.A[x][y] : R.b[y];
-        const double v = deriv ? a * exp(arg) * (1.0 + arg) : h * a * exp(arg);
+        const double v = deriv == 1 ? a * exp(arg) * (1.0 + arg)
+                                    : (deriv == 2 ? h * a * exp(arg) * h * (R.c[y] - cx) : h * a * exp(arg));
         if (x < m) w.W[x][y] = v; else w.We[y] = v;
       }
       continue;
     }
-    phi_all<M>(z, phi);
+    if (deriv == 2) phi_all<M + 1>(z, phi);
+    else phi_all<M>(z, phi);
     for (int y = 0; y < m; ++y) {
       double acc = 0.0;
       for (int k = 0; k < m; ++k) {
         const double g = R.gc[x][y][k];
-        acc += deriv ? g * ((z - k) * phi[k + 1] + c_inv_fact[k]) : g * phi[k + 1];
+        if (deriv == 1) acc += g * ((z - k) * phi[k + 1] + c_inv_fact[k]);
+        else if (deriv == 2) acc += g * (phi[k + 1] - (k + 1) * phi[k + 2]);
+        else acc += g * phi[k + 1];
       }
-      if (!deriv) acc *= h;
+      if (deriv == 0) acc *= h;
+      else if (deriv == 2) acc *= -h * h * cx;
       if (x < m) w.W[x][y] = acc; else w.We[y] = acc;
     }
   }
@@ -159,7 +169,7 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
       }
       continue;
     }
-    if (mode == TAU_BETA) {
+    if (mode == TAU_BETA || mode == TAU_DEPS) {
       double Rv[M];
       bool anyb = any || (P.lam_a && gview(P.lam_a)[e] != 0.0);
       for (int y = 0; y < m; ++y) {
@@ -168,19 +178,22 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
       }
       if (!anyb) continue;
       Weights<M> w;
-      weights<M>(R, delta_of(P, e), P.h, w, true, P.lam_a != nullptr);
+      weights<M>(R, delta_of(P, e), P.h, w, mode == TAU_BETA ? 1 : 2, P.lam_a != nullptr);
+      double val = 0.0;
       for (int x = 0; x < m; ++x) {
         double f = (sb != 0.0) ? -w.E[x] * sb : 0.0;
         for (int y = 0; y < m; ++y)
           if (Rv[y] != 0.0) f += w.W[x][y] * Rv[y];
-        acc += Sv[x] * f;
+        val += Sv[x] * f;
       }
       if (P.lam_a) {
         double f = (sb != 0.0) ? -w.Ee * sb : 0.0;
         for (int y = 0; y < m; ++y)
           if (Rv[y] != 0.0) f += w.We[y] * Rv[y];
-        acc += gview(P.lam_a)[e] * f;
+        val += gview(P.lam_a)[e] * f;
       }
+      if (mode == TAU_BETA) acc += val;
+      else gview(P.out)[e] += val;
       continue;
     }
     if (!any) {
@@ -198,7 +211,7 @@ __global__ void __launch_bounds__(256) tau_kernel(const PanelRule* __restrict__ 
       continue;
     }
     Weights<M> w;
-    weights<M>(R, delta_of(P, e), P.h, w, false, mode != TAU_INIT && mode != TAU_STEP);
+    weights<M>(R, delta_of(P, e), P.h, w, 0, mode != TAU_INIT && mode != TAU_STEP);
     if (mode == TAU_INIT) {
       for (int x = 0; x < m; ++x) gview(P.s[x])[e] = (sb != 0.0) ? w.E[x] * sb : 0.0;
     } else if (mode == TAU_STEP) {
@@ -318,6 +331,63 @@ __global__ void __launch_bounds__(256) rk_combine_kernel(const RKProblem* __rest
 void launch_rk_combine(const RKProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks, hipStream_t s) {
   if (total_blocks <= 0) return;
   hipLaunchKernelGGL(rk_combine_kernel, dim3(total_blocks), dim3(256), 0, s, d_probs, d_prefix, n_prob);
+}
+
+__global__ void __launch_bounds__(256) expsum_kernel(const ExpSumProblem* __restrict__ probs,
+                                                     const int* __restrict__ prefix, int n_prob) {
+  int lo = 0, hi = n_prob - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const ExpSumProblem& P = probs[lo];
+  if (P.active && *gview(P.active) == 0) return;   // uniform per block, before the barrier
+  const long first = (long)(b - prefix[lo]) * 1024;
+  double vmax = 0.0, cmax = 0.0;
+  for (int u = 0; u < 4; ++u) {
+    const long ei = first + u * 256 + threadIdx.x;
+    if (ei >= P.len) break;
+    const long e = P.idx ? (long)gview(P.idx)[ei] : ei;
+    const double d = seg_delta(P.eps, P.n, P.rank, e);
+    double acc = 0.0;
+    for (int l = 0; l < P.nterms; ++l) {
+      const ExpTerm t = P.terms[l];
+      const double x = gview(t.X)[e];
+      if (x == 0.0) continue;
+      const double z = d * P.h * t.k;
+      const double ex = exp(-z);
+      const double f = P.mode == 0 ? P.h * t.C * ex
+                                   : (P.mode == 1 ? t.C * ex * (1.0 - z) : -P.h * P.h * t.C * t.k * ex);
+      acc += f * x;
+    }
+    if (P.prod) acc *= gview(P.prod)[e];
+    const double v = (P.base ? P.x0 * gview(P.base)[e] : 0.0) + acc;
+    if (P.maxbits) cmax = nan_max(cmax, fabs(v - gview(P.out)[e]));
+    gview(P.out)[e] = v;
+    vmax = nan_max(vmax, fabs(v));
+  }
+  if (!P.maxbits) return;   // uniform per launch problem
+  __shared__ double r0[256], r1[256];
+  r0[threadIdx.x] = cmax;
+  r1[threadIdx.x] = vmax;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      r0[threadIdx.x] = nan_max(r0[threadIdx.x], r0[threadIdx.x + st]);
+      r1[threadIdx.x] = nan_max(r1[threadIdx.x], r1[threadIdx.x + st]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomic_max_pos(P.maxbits, r0[0]);
+    atomic_max_pos(P.maxbits + 1, r1[0]);
+  }
+}
+
+void launch_expsum(const ExpSumProblem* d_probs, const int* d_prefix, int n_prob, int total_blocks, hipStream_t s) {
+  if (total_blocks <= 0) return;
+  hipLaunchKernelGGL(expsum_kernel, dim3(total_blocks), dim3(256), 0, s, d_probs, d_prefix, n_prob);
 }
 
 __global__ void __launch_bounds__(256) copy_listed_kernel(const unsigned* __restrict__ a, long na,

@@ -17,9 +17,9 @@ _LIB_PATH = os.path.join(_PKG, "libftcc.so")
 
 _lib = None
 
-OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ESTATE, ENOMEM, EDEVICE, ENOCONV, ENONFINITE, EDIVERGE = 0, -1, -2, -3, -4, -5, -6, -7
 _NAMES = {EINVAL: "EINVAL", ESTATE: "ESTATE", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE",
-          ENOCONV: "ENOCONV", ENONFINITE: "ENONFINITE"}
+          ENOCONV: "ENOCONV", ENONFINITE: "ENONFINITE", EDIVERGE: "EDIVERGE"}
 
 
 class FTCCError(RuntimeError):
@@ -66,7 +66,7 @@ def library():
         "ftcc_get_amplitudes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D]),
         "ftcc_lambda": (ctypes.c_int, [ctypes.c_void_p, _I, _I]),
         "ftcc_get_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]),
-        "ftcc_response": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D), _D]),
+        "ftcc_response": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D), _D]),
         "ftcc_eval_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                               _D, _D, _D, _D, _D]),
         "ftcc_time_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D]),
@@ -196,7 +196,7 @@ class Context:
         st = np.zeros(self.B, dtype=np.int32)
         rc = self.lib.ftcc_solve_amplitudes(self._h, _ptr(mu), _ptr(beta), its.ctypes.data_as(_I),
                                            st.ctypes.data_as(_I))
-        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE))
+        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE, EDIVERGE))
         return its, st
 
     def grand_potential(self):
@@ -221,7 +221,7 @@ class Context:
         its = np.zeros(self.B, dtype=np.int32)
         st = np.zeros(self.B, dtype=np.int32)
         rc = self.lib.ftcc_lambda(self._h, its.ctypes.data_as(_I), st.ctypes.data_as(_I))
-        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE))
+        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE, EDIVERGE))
         return its, st
 
     def get_lambda(self, inst, node, tilde=True):
@@ -235,14 +235,17 @@ class Context:
                                         *[nul if a is None else _ptr(a) for a in out]))
         return out
 
-    def response(self, want_mu=True, want_beta=True, want_h=True, deri_dtheta=None, dh_dtheta=None):
-        """dOmega/dmu, dbeta, dh (list of n_i x n_i arrays) and the optional theta direction."""
+    def response(self, want_mu=True, want_beta=True, want_h=True, deri_dtheta=None, dh_dtheta=None,
+                 want_eps=False):
+        """dOmega/dmu, dbeta, dh (list of n_i x n_i arrays), dOmega/deps (list of length-n_i
+        arrays, when want_eps) and the optional theta direction."""
         B = self.B
         sizes = [self.sizes[i] for i in range(B)]
         n = max(sizes)
         dmu = np.zeros(B) if want_mu else None
         dbeta = np.zeros(B) if want_beta else None
         dh_flat = np.zeros(sum(k * k for k in sizes)) if want_h else None
+        deps_flat = np.zeros(sum(sizes)) if want_eps else None
         dth = None
         keep = []
         p_deri = p_dh = None
@@ -260,6 +263,7 @@ class Context:
         _check(self.lib.ftcc_response(self._h, _ptr(dmu) if dmu is not None else nul,
                                       _ptr(dbeta) if dbeta is not None else nul,
                                       _ptr(dh_flat) if dh_flat is not None else nul,
+                                      _ptr(deps_flat) if deps_flat is not None else nul,
                                       p_deri, p_dh, _ptr(dth) if dth is not None else nul))
         dh = None
         if dh_flat is not None:
@@ -267,7 +271,13 @@ class Context:
             for k in sizes:
                 dh.append(dh_flat[off:off + k * k].reshape(k, k))
                 off += k * k
-        return dict(mu=dmu, beta=dbeta, h=dh, theta=dth)
+        deps = None
+        if deps_flat is not None:
+            deps, off = [], 0
+            for k in sizes:
+                deps.append(deps_flat[off:off + k].copy())
+                off += k
+        return dict(mu=dmu, beta=dbeta, h=dh, eps=deps, theta=dth)
 
     def two_body_density(self):
         """Gamma_pqrs = dOmega/d<pq|rs> of every instance (list of n_i^4 arrays)."""
@@ -291,7 +301,7 @@ class Context:
         st = np.zeros(B, dtype=np.int32)
         rc = self.lib.ftcc_find_mu(self._h, _ptr(nt), _ptr(mu), _ptr(beta), float(tol), int(max_iter), _ptr(n_out),
                                    its.ctypes.data_as(_I), st.ctypes.data_as(_I))
-        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE))
+        _check(rc, allow=() if raise_on_status else (ENOCONV, ENONFINITE, EDIVERGE))
         return mu, n_out, its, st
 
     def eval_residual(self, inst, mu, beta, t1, t2):
