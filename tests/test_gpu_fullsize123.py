@@ -83,3 +83,32 @@ def test_full_configuration_context_fits():
     assert np.abs(a1 - b1).max() < 1e-12 * max(1.0, np.abs(b1).max())
     assert np.abs(a2 - b2).max() < 1e-12 * max(1.0, np.abs(b2).max())
     assert abs(ae - be) < 1e-12 * max(1.0, abs(be))
+
+
+def test_residual_n123_against_oracle_rows():
+    """The dense 123-plane-wave residual in the context the benchmark times (16
+    tau nodes in 4 panels, checkpointing, occupation threshold 1e-6) against the
+    oracle's values at seeded dense random amplitudes (written by
+    tests/golden/make_ueg123.py): E, all of S1, and S2 on the rows i in {0, 1, 122},
+    j in {4, 5, 122} (136161 elements: both sides of the 128-row tile boundary and
+    the last, ragged row)."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2004_01729_amd import ftcc as F
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "ueg123_residual.npz"))
+    s = fi.ueg_config(int(g["n_pw"]), int(g["n_el"]), float(g["rs"]), float(g["theta"]))
+    assert abs(s.mu - float(g["mu"])) < 1e-14 and abs(s.beta - float(g["beta"])) < 1e-14
+    t1, t2 = fi.random_amplitudes(s.n, seed=int(g["seed"]), scale=float(g["scale"]))
+    print("[fullsize123] residual n=123 seed=123 dense against the oracle rows", flush=True)
+    ctx = F.Context(1, n_tau=16, nodes_per_panel=4, occ_thresh=float(g["thr"]), tol=1e-12, checkpoint=1)
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    S1, S2, E = ctx.eval_residual(0, s.mu, s.beta, t1, t2)
+    ctx.close()
+    I, J = g["rows_i"], g["rows_j"]
+    rows = S2[np.ix_(I, J)]
+    del S2
+    assert abs(E - float(g["E"])) < 1e-12 * max(1.0, abs(float(g["E"])))
+    assert np.abs(S1 - g["S1"]).max() < 1e-11 * max(1.0, np.abs(g["S1"]).max())
+    assert np.abs(rows - g["S2_rows"]).max() < 1e-11 * max(1.0, np.abs(g["S2_rows"]).max())
