@@ -7,9 +7,12 @@ Lambda adjoint against the oracle's discrete adjoint and against central finite
 differences of the GPU's own Omega (step 1e-4, Richardson-extrapolated with
 step 5e-5) at a frozen reference (orbitals and eps fixed).
 
-At T <= 0.5 the fixed-point march does not converge for this U with a
-restricted reference (amplitudes grow like exp(beta |Delta| / 2) for the
-inverted pairs); those temperatures are not run."""
+At T <= 0.5 the march of the discrete equations has no finite continuation
+for this U with a restricted reference: the oracle's own march diverges at
+T = 0.5 (plain, damped, four times finer panels, DIIS; pinned in
+tests/test_oracle_limits.py), and the GPU must report the instance as failed
+(FTCC_EDIVERGE or FTCC_ENONFINITE) with a NaN Omega, which the last test checks
+at T = 0.5, 0.25 and 0.1."""
 import json
 import os
 
@@ -77,3 +80,20 @@ def test_hubbard10_u8_omega_and_gradients(F):
     for i in range(len(systems)):
         assert abs(fd_mu[i] - r["mu"][i]) < 1e-7 * max(1.0, abs(r["mu"][i]))
         assert abs(fd_U[i] - r["theta"][i]) < 1e-7 * max(1.0, abs(r["theta"][i]))
+
+
+def test_hubbard10_u8_low_temperature_reports_failure(F):
+    """T = 0.5, 0.25, 0.1 in one batch: every instance fails in its own status
+    slot (the oracle's march diverges too) and the call returns promptly."""
+    import time
+    g = json.load(open(GOLDEN))
+    systems = [fi.hubbard_config(L=g["L"], U=g["U"], T=T) for T in (0.5, 0.25, 0.1)]
+    print("[hubbard10] L=10 U=8 T=0.5,0.25,0.1 n_tau=40 thr=1e-6: expected to fail", flush=True)
+    ctx = _ctx(F, g, systems)
+    t0 = time.perf_counter()
+    _, st = ctx.solve([s.mu for s in systems], [s.beta for s in systems], raise_on_status=False)
+    om, _ = ctx.grand_potential()
+    ctx.close()
+    assert all(int(v) in (F.EDIVERGE, F.ENONFINITE) for v in st), st
+    assert np.all(np.isnan(om))
+    assert time.perf_counter() - t0 < 60.0

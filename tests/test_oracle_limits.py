@@ -146,3 +146,17 @@ def test_p11_propagators_converge_to_the_same_limit():
         diffs.append(abs(a - b))
     assert diffs[2] < diffs[1] < diffs[0]
     assert diffs[0] / diffs[2] > 2 ** 8                 # both at least fourth order
+
+
+def test_ten_site_ring_u8_t05_march_has_no_finite_continuation():
+    """The 10-site ring at U = 8, mu = U/2, T = 0.5, 40 tau nodes (10 panels x 4),
+    occupation threshold 1e-6: the amplitudes grow to about 25 by the sixth panel
+    and the fixed-point sweeps of that panel then blow up (the same happens with
+    damping, four times finer panels and DIIS), so the discrete equations have no
+    solution reachable by marching from s(0) = 0.  The GPU reports such an
+    instance as failed."""
+    s = fi.hubbard_config(L=10, U=8.0, T=0.5)
+    model = R.RestrictedModel(R.RestrictedIntegrals(s.h, s.eri, s.eps, s.mu, s.beta, 1e-6))
+    with pytest.raises((FloatingPointError, RuntimeError)):
+        with np.errstate(all="ignore"):
+            S.solve(model, G.Grid(s.beta, 10, 4), tol=1e-12, max_iter=200)
