@@ -11,7 +11,8 @@ At T <= 0.5 the march of the discrete equations has no finite continuation
 for this U with a restricted reference: the oracle's own march diverges at
 T = 0.5 (plain, damped, four times finer panels, DIIS; pinned in
 tests/test_oracle_limits.py), and the GPU must report the instance as failed
-(FTCC_EDIVERGE or FTCC_ENONFINITE) with a NaN Omega, which the last test checks
+(FTCC_EDIVERGE, FTCC_ENONFINITE or, when the sweeps neither settle nor grow
+steadily, FTCC_ENOCONV) with a NaN Omega, which the last test checks
 at T = 0.5, 0.25 and 0.1."""
 import json
 import os
@@ -84,7 +85,8 @@ def test_hubbard10_u8_omega_and_gradients(F):
 
 def test_hubbard10_u8_low_temperature_reports_failure(F):
     """T = 0.5, 0.25, 0.1 in one batch: every instance fails in its own status
-    slot (the oracle's march diverges too) and the call returns promptly."""
+    slot (the oracle's march diverges too) and the call returns promptly (at
+    T = 0.5 and 0.1 through the divergence test, at T = 0.25 at max_iter)."""
     import time
     g = json.load(open(GOLDEN))
     systems = [fi.hubbard_config(L=g["L"], U=g["U"], T=T) for T in (0.5, 0.25, 0.1)]
@@ -94,6 +96,6 @@ def test_hubbard10_u8_low_temperature_reports_failure(F):
     _, st = ctx.solve([s.mu for s in systems], [s.beta for s in systems], raise_on_status=False)
     om, _ = ctx.grand_potential()
     ctx.close()
-    assert all(int(v) in (F.EDIVERGE, F.ENONFINITE) for v in st), st
+    assert all(int(v) in (F.EDIVERGE, F.ENONFINITE, F.ENOCONV) for v in st), st
     assert np.all(np.isnan(om))
     assert time.perf_counter() - t0 < 60.0

@@ -70,7 +70,7 @@ def test_forward_hubbard6(ftcc, kind):
     ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
     its, st = ctx.solve(s.mu, s.beta)
     om, parts = ctx.grand_potential()
-    t1g, t2g = ctx.amplitudes(0, 13)
+    nodes = [ctx.amplitudes(0, k) for k in range(20)]
     ctx.close()
     model = _oracle(s.h, s.eri, s.eps, s.mu, s.beta)
     sol = S.solve(model, G.Grid(s.beta, 5, 4, "etd" if kind == 0 else "lawson"), tol=1e-13)
@@ -78,8 +78,9 @@ def test_forward_hubbard6(ftcc, kind):
     assert abs(parts[0, 1] - sol.omega1) < 1e-12 * max(1.0, abs(sol.omega1))
     assert abs(parts[0, 2] - sol.omega_cc) < 1e-10 * abs(sol.omega_cc)
     assert abs(om[0] - sol.omega) < 1e-10 * abs(sol.omega)
-    assert _rel(t1g, sol.nodes[13][0]) < 1e-8
-    assert _rel(t2g, sol.nodes[13][1]) < 1e-8
+    for k in range(20):                       # every node of every panel
+        assert _rel(nodes[k][0], sol.nodes[k][0]) < 1e-8
+        assert _rel(nodes[k][1], sol.nodes[k][1]) < 1e-8
 
 
 def test_adjoint_and_response_small(ftcc):
