@@ -1674,7 +1674,7 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
     if (!c->solved) fail(FTCC_ESTATE, "call ftcc_solve_amplitudes first");
     FTCC_HIP(hipSetDevice(c->device));
     const int B = c->B, m = c->m, P = c->P;
-    for (int i = 0; i < B; ++i) {
+    for (int i = 0; i < B && !c->simpson; ++i) {   // a_P = 0 (the Simpson form keeps S[s_P] there)
       Instance& I = c->inst[i];
       const long n = I.n, len = n * n + n * n * n * n;
       zero_d(c, I.abuf[P], len);

@@ -130,7 +130,8 @@ def test_rk4_momentum_blocked_matches_oracle(F):
 
 
 def test_rk_option_errors(F):
-    for kw in (dict(n_tau=7, propagator=4), dict(n_tau=8, propagator=4, diis_depth=3), dict(n_tau=8, propagator=5)):
+    for kw in (dict(n_tau=7, propagator=4), dict(n_tau=8, propagator=4, diis_depth=3), dict(n_tau=8, propagator=6),
+               dict(n_tau=7, propagator=5), dict(n_tau=8, propagator=5, diis_depth=2)):
         with pytest.raises(F.FTCCError):
             F.Context(1, **kw)
     s = fi.hubbard_config(L=2, U=1.0, T=1.0)
