@@ -166,23 +166,32 @@ def batch_bench(per_instance, group=32, momentum=False, subset="all"):
             systems.append(fi.hubbard_config(L=kw["L"], U=kw["U"], T=kw["T"]))
     opts = dict(n_tau=20, nodes_per_panel=4, occ_thresh=1e-6, tol=1e-12, max_iter=200)
 
-    def run(sys_):
+    def run(sys_, fd=False):
         ctx = F.Context(len(sys_), **opts)
         for i, s in enumerate(sys_):
             if momentum:
                 ctx.set_momentum(i, *s.momentum)
             ctx.set_hamiltonian(i, s.h, s.eri, s.eps)
+        mus, betas = [s.mu for s in sys_], [s.beta for s in sys_]
         t0 = time.perf_counter()
-        _, st = ctx.solve([s.mu for s in sys_], [s.beta for s in sys_], raise_on_status=False)
+        _, st = ctx.solve(mus, betas, raise_on_status=False)
         ctx.grand_potential()
         evals = ctx.stats()["resid_evals"]
         t1 = time.perf_counter()
         ctx.lam(raise_on_status=False)
         ctx.response(want_mu=True, want_beta=True, want_h=True)
         t2 = time.perf_counter()
+        out = dict(forward_s=t1 - t0, gradient_s=t2 - t1, total_s=t2 - t0, forward_resid_evals=evals,
+                   failed=[i for i, v in enumerate(st.tolist()) if v != 0])
+        if fd:   # central differences of Omega in mu and beta: four more forward solves, measured
+            d = 1e-4
+            t3 = time.perf_counter()
+            for dm, db in ((d, 0.0), (-d, 0.0), (0.0, d), (0.0, -d)):
+                ctx.solve([m + dm for m in mus], [b + db * b for b in betas], raise_on_status=False)
+                ctx.grand_potential()
+            out["fd_mu_beta_s"] = time.perf_counter() - t3
         ctx.close()
-        return dict(forward_s=t1 - t0, gradient_s=t2 - t1, total_s=t2 - t0, forward_resid_evals=evals,
-                    failed=[i for i, v in enumerate(st.tolist()) if v != 0])
+        return out
 
     # interleave the two families so that every context mixes large and small instances
     order = [i for pair in zip(range(16), range(16, 32)) for i in pair]
@@ -197,10 +206,18 @@ def batch_bench(per_instance, group=32, momentum=False, subset="all"):
     out = dict(mode="batch", workload=wl, n_instances=len(order),
                n_tau=20, occ_thresh=1e-6, group=group, momentum_blocked=momentum, batched=batched)
     if per_instance:
-        rows = [run([systems[i]]) for i in order]
-        out["per_instance"] = {k: sum(r[k] for r in rows) for k in ("forward_s", "gradient_s", "total_s")}
+        rows = [run([systems[i]], fd=True) for i in order]
+        out["per_instance"] = {k: sum(r[k] for r in rows)
+                               for k in ("forward_s", "gradient_s", "total_s", "fd_mu_beta_s")}
         out["per_instance"]["failed"] = [order[i] for i, r in enumerate(rows) if r["failed"]]
         out["batched_speedup"] = out["per_instance"]["total_s"] / out["batched"]["total_s"]
+        # the batched adjoint form (one context: forward, Lambda, response for mu, beta and every h_pq)
+        # against plain per-instance forward solves with central finite differences in mu and beta
+        # (1 + 4 forward solves per instance, every one measured)
+        pi = out["per_instance"]
+        out["per_instance_forward_plus_fd_s"] = pi["forward_s"] + pi["fd_mu_beta_s"]
+        out["batched_adjoint_vs_per_instance_fd_speedup"] = (pi["forward_s"] + pi["fd_mu_beta_s"]) / \
+            out["batched"]["total_s"]
     return out
 
 
