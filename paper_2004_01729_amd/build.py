@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libftcc.so")
 SOURCES = ["kernels.hip", "tau_kernels.hip", "engine.hip", "residual.hip", "ftcc_api.hip", "rk_march.hip",
-           "simpson_march.hip", "density.hip"]
+           "simpson_march.hip", "density.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -298,6 +298,9 @@ void simpson_lamt(ftcc_ctx* c, int x);
 void simpson_grid_term(ftcc_ctx* c, int y, int mode, const std::function<double*(int)>& out,
                        const std::function<const double*(int)>& prod);
 
+// noalloc.hip: the fixed device scratch of the allocation-free entry point
+void noalloc_setup(int device);
+
 // density.hip: the two-body response density
 void build_gamma_executor(ftcc_ctx* c);
 void gamma_pass(ftcc_ctx* c);

@@ -1376,6 +1376,7 @@ int ftcc_create(ftcc_ctx** out, int device, int n_instances, const ftcc_options*
     if (std::string(prop.gcnArchName).rfind("gfx950", 0) != 0)
       fail(FTCC_EDEVICE, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
     FTCC_HIP(init_tau_constants());
+    noalloc_setup(device);
     std::unique_ptr<ftcc_ctx> c(new ftcc_ctx());
     c->device = device;
     c->opt = o;

@@ -67,6 +67,7 @@ def library():
         "ftcc_lambda": (ctypes.c_int, [ctypes.c_void_p, _I, _I]),
         "ftcc_get_lambda": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]),
         "ftcc_response": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, _D, ctypes.POINTER(_D), ctypes.POINTER(_D), _D]),
+        "ftcc_response_noalloc": (ctypes.c_int, [ctypes.c_void_p, _D, _D]),
         "ftcc_eval_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                               _D, _D, _D, _D, _D]),
         "ftcc_time_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D]),
@@ -90,7 +91,7 @@ def exported_symbols():
     return ["ftcc_default_options", "ftcc_create", "ftcc_destroy", "ftcc_set_stream", "ftcc_set_allocator",
             "ftcc_set_momentum", "ftcc_set_hamiltonian",
             "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
-            "ftcc_get_lambda", "ftcc_response", "ftcc_find_mu", "ftcc_eval_residual", "ftcc_time_residual",
+            "ftcc_get_lambda", "ftcc_response", "ftcc_response_noalloc", "ftcc_find_mu", "ftcc_eval_residual", "ftcc_time_residual",
             "ftcc_stats",
             "ftcc_kernel_profile", "ftcc_two_body_density",
             "ftcc_last_error", "ftcc_abi_version"]
@@ -278,6 +279,15 @@ class Context:
                 deps.append(deps_flat[off:off + k].copy())
                 off += k
         return dict(mu=dmu, beta=dbeta, h=dh, eps=deps, theta=dth)
+
+    def response_noalloc(self, want_mu=True, want_beta=True):
+        """dOmega/dmu and dOmega/dbeta through the allocation-free entry point."""
+        nul = ctypes.cast(None, _D)
+        dmu = np.zeros(self.B) if want_mu else None
+        dbeta = np.zeros(self.B) if want_beta else None
+        _check(self.lib.ftcc_response_noalloc(self._h, _ptr(dmu) if dmu is not None else nul,
+                                              _ptr(dbeta) if dbeta is not None else nul))
+        return dict(mu=dmu, beta=dbeta)
 
     def two_body_density(self):
         """Gamma_pqrs = dOmega/d<pq|rs> of every instance (list of n_i^4 arrays)."""
