@@ -152,7 +152,7 @@ def copy_calibration(reps, nbytes=1 << 30):
                 gbps=2 * nbytes * reps / el / 1e9)
 
 
-def batch_bench(per_instance, group=32, momentum=False, subset="all"):
+def batch_bench(per_instance, group=32, momentum=False, subset="all", diis=0):
     """One step (forward + Lambda + response for mu, beta, h) of the mixed batch,
     batched in contexts of `group` instances (electron-gas and ring instances
     interleaved) and optionally per instance."""
@@ -164,7 +164,7 @@ def batch_bench(per_instance, group=32, momentum=False, subset="all"):
             systems.append(fi.ueg_config(kw["n_pw"], 14, kw["rs"], kw["theta"]))
         else:
             systems.append(fi.hubbard_config(L=kw["L"], U=kw["U"], T=kw["T"]))
-    opts = dict(n_tau=20, nodes_per_panel=4, occ_thresh=1e-6, tol=1e-12, max_iter=200)
+    opts = dict(n_tau=20, nodes_per_panel=4, occ_thresh=1e-6, tol=1e-12, max_iter=200, diis_depth=diis)
 
     def run(sys_, fd=False):
         ctx = F.Context(len(sys_), **opts)
@@ -204,7 +204,8 @@ def batch_bench(per_instance, group=32, momentum=False, subset="all"):
     batched["contexts"] = len(groups)
     wl = "batch32_ueg57pw_x16_hubbard_L6-14_x16" if subset == "all" else "batch16_hubbard_L6-14_x16"
     out = dict(mode="batch", workload=wl, n_instances=len(order),
-               n_tau=20, occ_thresh=1e-6, group=group, momentum_blocked=momentum, batched=batched)
+               n_tau=20, occ_thresh=1e-6, group=group, momentum_blocked=momentum, diis_depth=diis,
+               batched=batched)
     if per_instance:
         rows = [run([systems[i]], fd=True) for i in order]
         out["per_instance"] = {k: sum(r[k] for r in rows)
@@ -672,6 +673,7 @@ def main():
     ap.add_argument("--subset", default="all", choices=("all", "rings"))
     ap.add_argument("--momentum", action="store_true")
     ap.add_argument("--dense", action="store_true", help="--mode numerr: dense contractions")
+    ap.add_argument("--diis", type=int, default=0, help="--mode batch: DIIS depth of the fixed-point sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -696,7 +698,8 @@ def main():
         print(json.dumps(numerr_bench(momentum=not args.dense)), flush=True)
         return
     if args.mode == "batch":
-        print(json.dumps(batch_bench(args.per_instance, args.group, args.momentum, args.subset)), flush=True)
+        print(json.dumps(batch_bench(args.per_instance, args.group, args.momentum, args.subset, args.diis)),
+              flush=True)
         return
     if args.mode == "residual":
         s, opts, cfg = workload(args.workload)
