@@ -120,10 +120,12 @@ def test_failed_instance_does_not_disturb_batch(F):
 
 def test_kernel_profile_enabled_before_first_solve(F):
     """The plan is built (autotuned, graph-captured) inside the first solve; an
-    enabled kernel profiler must not record inside that capture."""
-    s = fi.hubbard_config(L=12, U=2.0, T=1.0)
-    print("[profile] hubbard L=12, profiler on before the first solve", flush=True)
-    ctx = F.Context(1, n_tau=8, nodes_per_panel=4, tol=1e-12)
+    enabled kernel profiler must not record inside that capture.  The
+    57-plane-wave gas, whose O(n^6) GEMMs run in the profiled 128 x 128 tiles
+    (the autotuner gives small systems 64 x 64 tiles)."""
+    s = fi.ueg_config(57, 14, 1.0, 0.5)
+    print("[profile] ueg 57 PW n_tau=16, profiler on before the first solve", flush=True)
+    ctx = F.Context(1, n_tau=16, nodes_per_panel=4, tol=1e-12)
     ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
     ctx.kernel_profile(1)
     ctx.solve(s.mu, s.beta)
