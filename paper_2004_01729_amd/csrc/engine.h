@@ -107,6 +107,8 @@ struct Launch {
   std::vector<int> prob_inst;
   float tuned_ms = 0.f;
   std::string tag;
+  std::vector<Launch> alts;         // GEMM: other descriptor sets of the same contraction (tile
+                                    // size, split-K) for the autotuner; emptied once it has chosen
 };
 
 struct ProblemRef {

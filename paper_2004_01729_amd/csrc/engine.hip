@@ -475,93 +475,105 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
   const double gbeta = (c_direct || c_table) ? beta : 0.0;
   const PerProb& Cp = (c_direct || c_table) ? out : scratch_->c;
 
-  std::vector<GemmProblem> gs(np);
-  std::vector<int> prefix(np), prefix2(np);
   int cfg = 0;
   {
     const long m = ipow(n0, (int)M.size()), nn = ipow(n0, (int)N.size()), kk = ipow(n0, (int)K.size());
     cfg = (m >= 128 && nn >= 128) ? (kk >= 512 ? 2 : 0) : 1;
   }
-  const int BM = gemm_bm(cfg), BN = gemm_bn(cfg);
-  int total = 0, total2 = 0;
-  bool any_split = false;
-  double flops = 0.0;
-  // split-K when the grouped launch would not fill the device
-  long tiles_all = 0;
-  for (int p = 0; p < np; ++p) {
-    const long n = probs_[p].n;
-    tiles_all += ((ipow(n, (int)M.size()) + BM - 1) / BM) * ((ipow(n, (int)N.size()) + BN - 1) / BN);
-  }
-  for (int p = 0; p < np; ++p) {
-    const long n = probs_[p].n;
-    GemmProblem& g = gs[p];
-    g.M = (int)ipow(n, (int)M.size());
-    g.N = (int)ipow(n, (int)N.size());
-    g.K = (int)ipow(n, (int)K.size());
-    g.A = Ap[p];
-    g.B = Bp[p];
-    g.C = Cp[p];
-    g.lda = ta ? g.M : g.K;
-    g.ldb = tb ? g.K : g.N;
-    g.ldc = g.N;
-    g.alpha = galpha;
-    g.beta = gbeta;
-    g.active = gate_for(dst, p);
-    g.tiles_m = (g.M + BM - 1) / BM;
-    g.tiles_n = (g.N + BN - 1) / BN;
-    if (c_table) {
-      g.offM = out_offsets(n, M, oi);
-      g.offN = out_offsets(n, N, oi);
+  // descriptors of the grouped launch for one tile configuration; allow_split:
+  // split K when the launch would not fill the device
+  auto build_gemm = [&](int gcfg, bool allow_split) {
+    std::vector<GemmProblem> gs(np);
+    std::vector<int> prefix(np), prefix2(np);
+    const int BM = gemm_bm(gcfg), BN = gemm_bn(gcfg);
+    int total = 0, total2 = 0;
+    bool any_split = false;
+    double flops = 0.0;
+    long tiles_all = 0;
+    for (int p = 0; p < np; ++p) {
+      const long n = probs_[p].n;
+      tiles_all += ((ipow(n, (int)M.size()) + BM - 1) / BM) * ((ipow(n, (int)N.size()) + BN - 1) / BN);
     }
-    int ks = 1;
-    if (tiles_all < 512 && g.K >= 512) {
-      ks = (int)std::min<long>((512 + tiles_all - 1) / tiles_all, g.K / 256);
-      // the partial buffer holds n^4 doubles
-      while (ks > 1 && (long)ks * g.M * g.N > ipow(n, 4)) --ks;
-      ks = std::max(ks, 1);
+    for (int p = 0; p < np; ++p) {
+      const long n = probs_[p].n;
+      GemmProblem& g = gs[p];
+      g.M = (int)ipow(n, (int)M.size());
+      g.N = (int)ipow(n, (int)N.size());
+      g.K = (int)ipow(n, (int)K.size());
+      g.A = Ap[p];
+      g.B = Bp[p];
+      g.C = Cp[p];
+      g.lda = ta ? g.M : g.K;
+      g.ldb = tb ? g.K : g.N;
+      g.ldc = g.N;
+      g.alpha = galpha;
+      g.beta = gbeta;
+      g.active = gate_for(dst, p);
+      g.tiles_m = (g.M + BM - 1) / BM;
+      g.tiles_n = (g.N + BN - 1) / BN;
+      if (c_table) {
+        g.offM = out_offsets(n, M, oi);
+        g.offN = out_offsets(n, N, oi);
+      }
+      int ks = 1;
+      if (allow_split && tiles_all < 512 && g.K >= 512) {
+        ks = (int)std::min<long>((512 + tiles_all - 1) / tiles_all, g.K / 256);
+        // the partial buffer holds n^4 doubles
+        while (ks > 1 && (long)ks * g.M * g.N > ipow(n, 4)) --ks;
+        ks = std::max(ks, 1);
+      }
+      if ((long)g.M * g.K >= (1L << 31) || (long)g.K * g.N >= (1L << 31) || (long)g.M * g.N >= (1L << 31))
+        throw std::runtime_error("GEMM operand exceeds 2^31 elements: " + tag);
+      g.ksplit = ks;
+      g.kchunk = (g.K + ks - 1) / ks;
+      g.kchunk = ((g.kchunk + 15) / 16) * 16;
+      g.ksplit = (g.K + g.kchunk - 1) / g.kchunk;
+      g.partial = scratch_->part[p];
+      if (g.ksplit > 1) any_split = true;
+      prefix[p] = total;
+      total += g.tiles_m * g.tiles_n * g.ksplit;
+      prefix2[p] = total2;
+      total2 += (int)(((long)g.M * g.N + 1023) / 1024);
+      flops += 2.0 * g.M * (double)g.N * g.K;
     }
-    if ((long)g.M * g.K >= (1L << 31) || (long)g.K * g.N >= (1L << 31) || (long)g.M * g.N >= (1L << 31))
-      throw std::runtime_error("GEMM operand exceeds 2^31 elements: " + tag);
-    g.ksplit = ks;
-    g.kchunk = (g.K + ks - 1) / ks;
-    g.kchunk = ((g.kchunk + 15) / 16) * 16;
-    g.ksplit = (g.K + g.kchunk - 1) / g.kchunk;
-    g.partial = scratch_->part[p];
-    if (g.ksplit > 1) any_split = true;
-    prefix[p] = total;
-    total += g.tiles_m * g.tiles_n * g.ksplit;
-    prefix2[p] = total2;
-    total2 += (int)(((long)g.M * g.N + 1023) / 1024);
-    flops += 2.0 * g.M * (double)g.N * g.K;
-  }
-  std::vector<double> pf(np);
-  std::vector<int> pinst(np);
-  for (int p = 0; p < np; ++p) {
-    pf[p] = 2.0 * gs[p].M * (double)gs[p].N * gs[p].K;
-    pinst[p] = probs_[p].inst;
-  }
-  Launch L;
-  L.kind = Launch::GEMM;
-  L.n_prob = np;
-  L.total = total;
-  L.min_k = np > 0 ? gs[0].K : 0;
-  for (int p = 1; p < np; ++p) L.min_k = std::min(L.min_k, gs[p].K);
+    std::vector<double> pf(np);
+    std::vector<int> pinst(np);
+    for (int p = 0; p < np; ++p) {
+      pf[p] = 2.0 * gs[p].M * (double)gs[p].N * gs[p].K;
+      pinst[p] = probs_[p].inst;
+    }
+    Launch L;
+    L.kind = Launch::GEMM;
+    L.n_prob = np;
+    L.total = total;
+    L.min_k = np > 0 ? gs[0].K : 0;
+    for (int p = 1; p < np; ++p) L.min_k = std::min(L.min_k, gs[p].K);
+    if (&dst != &setup_) {
+      L.prob_flops = pf;
+      L.prob_inst = pinst;
+    }
+    L.cfg = gcfg;
+    L.ta = ta;
+    L.tb = tb;
+    L.d_desc = upload(gs.data(), sizeof(GemmProblem) * np);
+    L.d_prefix = (int*)upload(prefix.data(), sizeof(int) * np);
+    if (any_split) {
+      // problems without a split still need their own reduce pass skipped: mark via ksplit
+      L.splitk_blocks = total2;
+      L.d_prefix2 = (int*)upload(prefix2.data(), sizeof(int) * np);
+    }
+    L.flops = flops;
+    L.tag = tag;
+    return L;
+  };
+  Launch L = build_gemm(cfg, true);
   if (&dst != &setup_) {
-    L.prob_flops = pf;
-    L.prob_inst = pinst;
+    // candidates for the autotuner: 64 x 64 tiles while the 128 x 128 launch is
+    // short of four waves of resident blocks (beyond that its edge waste is small
+    // and the larger tile wins), and the launch without split-K
+    if (gemm_bm(cfg) == 128 && L.total < 4 * gemm_slots(cfg)) L.alts.push_back(build_gemm(1, true));
+    if (L.splitk_blocks > 0) L.alts.push_back(build_gemm(cfg, false));
   }
-  L.cfg = cfg;
-  L.ta = ta;
-  L.tb = tb;
-  L.d_desc = upload(gs.data(), sizeof(GemmProblem) * np);
-  L.d_prefix = (int*)upload(prefix.data(), sizeof(int) * np);
-  if (any_split) {
-    // problems without a split still need their own reduce pass skipped: mark via ksplit
-    L.splitk_blocks = total2;
-    L.d_prefix2 = (int*)upload(prefix2.data(), sizeof(int) * np);
-  }
-  L.flops = flops;
-  L.tag = tag;
   dst.push_back(L);
   if (!c_direct && !c_table) perm(dst, scratch_->c, M + N, out, oi, 1.0, beta, nullptr, tag + ":permC");
 }
@@ -1112,32 +1124,60 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
 // overwrites it; gradient buffers are zero-filled before each backward).
 void Executor::autotune(hipStream_t s) {
   const char* env = std::getenv("FTCC_AUTOTUNE");
-  if (env && env[0] == '0') return;
   hipEvent_t e0, e1;
   FTCC_HIP(hipEventCreate(&e0));
   FTCC_HIP(hipEventCreate(&e1));
+  // every candidate of a GEMM launch: its own descriptor set (tile size, split-K)
+  // with each tile configuration of that size (BK 16 or 32 for 128 x 128 tiles),
+  // timed over two launches after a warm-up (split-K reduce included)
+  auto time_one = [&](const Launch& v, int cfg) {
+    auto go = [&] {
+      launch_gemm(cfg, v.ta, v.tb, (const GemmProblem*)v.d_desc, v.d_prefix, v.n_prob, v.total, tail_of(v, cfg), s);
+      if (v.splitk_blocks > 0)
+        launch_splitk_reduce((const GemmProblem*)v.d_desc, v.d_prefix2, v.n_prob, v.splitk_blocks, s);
+    };
+    go();
+    FTCC_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 2; ++r) go();
+    FTCC_HIP(hipEventRecord(e1, s));
+    FTCC_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    FTCC_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return ms * 0.5f;
+  };
   for (std::vector<Launch>* lst : {&fwd_, &bwd_}) {
     for (Launch& l : *lst) {
-      if (l.kind != Launch::GEMM || gemm_bm(l.cfg) != 128) continue;
-      int best = l.cfg;
+      if (l.kind != Launch::GEMM) continue;
+      if (env && env[0] == '0') {
+        l.alts.clear();
+        continue;
+      }
+      int best_v = -1, best_cfg = l.cfg;
       float best_ms = 1e30f;
-      for (int cfg : {0, 2}) {
-        const GemmTail tail = tail_of(l, cfg);
-        launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, tail, s);
-        FTCC_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < 2; ++r)
-          launch_gemm(cfg, l.ta, l.tb, (const GemmProblem*)l.d_desc, l.d_prefix, l.n_prob, l.total, tail, s);
-        FTCC_HIP(hipEventRecord(e1, s));
-        FTCC_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        FTCC_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = cfg;
+      for (int v = -1; v < (int)l.alts.size(); ++v) {
+        const Launch& cand = v < 0 ? l : l.alts[v];
+        const std::vector<int> cfgs = gemm_bm(cand.cfg) == 128 ? std::vector<int>{0, 2} : std::vector<int>{1};
+        for (int cfg : cfgs) {
+          const float ms = time_one(cand, cfg);
+          if (ms < best_ms) {
+            best_ms = ms;
+            best_v = v;
+            best_cfg = cfg;
+          }
         }
       }
-      l.cfg = best;
-      l.tuned_ms = best_ms * 0.5f;
+      if (best_v >= 0) {
+        const Launch& w = l.alts[best_v];
+        l.d_desc = w.d_desc;
+        l.d_prefix = w.d_prefix;
+        l.d_prefix2 = w.d_prefix2;
+        l.total = w.total;
+        l.splitk_blocks = w.splitk_blocks;
+        l.min_k = w.min_k;
+      }
+      l.cfg = best_cfg;
+      l.tuned_ms = best_ms;
+      l.alts.clear();
     }
   }
   FTCC_HIP(hipEventDestroy(e0));
