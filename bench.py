@@ -51,6 +51,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix, flop/s
+PEAK_HBM = 8.0e12              # MI355X HBM3E, bytes/s
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm128_ueg123_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_01729_amd", "csrc", "kernels.hip")
 
@@ -131,9 +132,15 @@ def residual_throughput(ctx, reps, n_tau):
     converged amplitudes the solve left there), between HIP events."""
     sec, fl = ctx.time_residual(reps)
     m = ctx.opt.nodes_per_panel
+    plan = ctx.plan_info()
+    # one pass of the slot program evaluates `slots` nodes; algorithmic bytes per node evaluation
+    by = plan["bytes_forward"] / plan["slots"]
     return dict(evals_per_s=reps * m / sec, ms_per_eval=1e3 * sec / (reps * m),
                 gemm_tflops=fl * reps / sec / 1e12, frac_fp64_mfma=fl * reps / sec / PEAK_FP64_MFMA,
-                gemm_flop_per_eval=fl / m)
+                gemm_flop_per_eval=fl / m, algorithmic_bytes_per_eval=by,
+                achieved_gbps=by * reps * m / sec / 1e9, frac_hbm=by * reps * m / sec / PEAK_HBM,
+                dispatches_per_forward_pass=plan["dispatches_forward"],
+                dispatches_per_backward_pass=plan["dispatches_backward"], slots=plan["slots"])
 
 
 def copy_calibration(reps, nbytes=1 << 30):

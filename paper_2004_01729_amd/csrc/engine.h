@@ -17,6 +17,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <functional>
 #include <map>
 #include <string>
@@ -109,6 +110,17 @@ struct Launch {
   std::string tag;
   std::vector<Launch> alts;         // GEMM: other descriptor sets of the same contraction (tile
                                     // size, split-K) for the autotuner; emptied once it has chosen
+  // Device byte ranges [lo, hi) the launch reads and writes.  `ranged` false: not
+  // recorded, and the launch stays ordered against every other one.
+  std::vector<std::pair<uintptr_t, uintptr_t>> rd, wr;
+  bool ranged = false;
+  // algorithmic bytes: each operand element read once, each result element written
+  // once (and read where it accumulates), over the allowed elements when blocked
+  double bytes = 0.0;
+  // SGEMM: host copies of the descriptors, kept until the launch lists are fused
+  std::vector<SgemmProblem> sprobs;
+  std::vector<SgemmTask> stasks;
+  std::vector<SgemmReduce> sreds;
 };
 
 struct ProblemRef {
@@ -199,6 +211,10 @@ class Executor {
   double gemm_flops_forward() const;
   double gemm_flops_backward() const;
   int n_launches_forward() const { return (int)fwd_.size(); }
+  // kernel dispatches of one pass of a launch list, and the algorithmic bytes of the forward list
+  long dispatches_forward() const { return dispatches(fwd_); }
+  long dispatches_backward() const { return dispatches(bwd_); }
+  double bytes_forward() const;
   // device bytes taken by the cached permuted copies of value operands and by the
   // permuted copies of constants
   size_t cache_bytes() const { return cache_bytes_; }
@@ -207,6 +223,7 @@ class Executor {
  private:
   using PerProb = std::vector<double*>;
   void run(const std::vector<Launch>& L, hipStream_t s) const;
+  long dispatches(const std::vector<Launch>& L) const;
   void contract(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
                 const PerProb& A, const std::string& ai, int a_const, const PerProb* B, const std::string& bi,
                 int b_const, bool acc, const std::string& tag, int a_val = -1, int b_val = -1, int t_out = -1,
@@ -222,7 +239,8 @@ class Executor {
                    const std::string& bi, const PerProb& out, double alpha, double beta, int t_a,
                    const std::string& tag);
   bool elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
-                    const std::string& yi, double alpha, double beta, int t_y, int t_x, const std::string& tag);
+                    const std::string& yi, double alpha, double beta, int t_y, int t_x, const std::string& tag,
+                    const std::vector<const double*>* scale = nullptr);
   PerProb const_permuted(int tensor, const PerProb& X, const std::string& xi, const std::string& yi);
   void* upload(const void* host, size_t bytes);
   void dump_plan() const;
@@ -233,6 +251,14 @@ class Executor {
   bool inline_setup_ = false;
   // consecutive zero fills write disjoint buffers: one launch serves them all
   void merge_fills(std::vector<Launch>& L);
+  // Momentum-blocked lists: every launch moves to the earliest dependency level
+  // its byte ranges allow, and the blocked contractions (and the blocked
+  // elementwise ops) of one level become one launch each.  Every buffer sees its
+  // writes in program order, so results are unchanged.
+  void fuse_levels(std::vector<Launch>& L);
+  Launch merge_sgemm(const std::vector<Launch*>& parts);
+  Launch merge_elem(const std::vector<Launch*>& parts);
+  void release(const std::vector<void*>& dev);
   std::function<double*(int, size_t)> const_alloc_;
   std::map<std::pair<int, std::string>, PerProb> const_cache_;
   struct CacheEntry {

@@ -107,6 +107,51 @@ void* Executor::upload(const void* host, size_t bytes) {
   return d;
 }
 
+void Executor::release(const std::vector<void*>& dev) {
+  if (dev.empty()) return;
+  std::vector<void*> keep;
+  keep.reserve(owned_.size());
+  for (void* p : owned_) {
+    if (std::find(dev.begin(), dev.end(), p) != dev.end()) FTCC_HIP(hipFree(p));
+    else keep.push_back(p);
+  }
+  owned_.swap(keep);
+}
+
+using Ranges = std::vector<std::pair<uintptr_t, uintptr_t>>;
+
+static void add_range(Ranges& v, const void* p, size_t bytes) {
+  if (p && bytes) v.emplace_back((uintptr_t)p, (uintptr_t)p + bytes);
+}
+
+// sorted, overlapping and touching ranges joined
+static void normalize(Ranges& v) {
+  if (v.empty()) return;
+  std::sort(v.begin(), v.end());
+  size_t w = 0;
+  for (size_t k = 1; k < v.size(); ++k) {
+    if (v[k].first <= v[w].second) v[w].second = std::max(v[w].second, v[k].second);
+    else v[++w] = v[k];
+  }
+  v.resize(w + 1);
+}
+
+static bool overlaps(const Ranges& a, const Ranges& b) {
+  size_t i = 0, j = 0;
+  while (i < a.size() && j < b.size()) {
+    if (a[i].second <= b[j].first) ++i;
+    else if (b[j].second <= a[i].first) ++j;
+    else return true;
+  }
+  return false;
+}
+
+// must b run after a (a earlier in program order)?
+static bool ordered(const Launch& a, const Launch& b) {
+  if (!a.ranged || !b.ranged) return true;
+  return overlaps(a.wr, b.rd) || overlaps(a.wr, b.wr) || overlaps(a.rd, b.wr);
+}
+
 // Task of the first element of every 256-element block of an element-task list
 // (the largest task index whose first element is at or before it), and the last
 // task after the final block: the kernels search only between two neighbours.
@@ -131,6 +176,7 @@ void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::strin
   if ((int)xi.size() != r) throw std::runtime_error("permute rank mismatch " + xi + "->" + yi);
   std::vector<PermProblem> ps(np);
   std::vector<int> prefix(np);
+  Ranges rd, wr;
   int total = 0;
   for (int p = 0; p < np; ++p) {
     const long n = probs_[p].n;
@@ -160,6 +206,9 @@ void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::strin
     }
     for (int k = 0; k < 4; ++k) q.div[k] = make_fastdiv((unsigned)q.d[k]);
     prefix[p] = total;
+    if (alpha != 0.0) add_range(rd, X[p], sizeof(double) * (size_t)ipow(n, r));
+    if (q.scale) add_range(rd, q.scale, sizeof(double));
+    add_range(wr, Y[p], sizeof(double) * (size_t)ipow(n, r));
     if (q.tb < 0) {
       const long el = (long)q.d[0] * q.d[1] * q.d[2] * q.d[3];
       total += (int)((el + 1023) / 1024);
@@ -180,6 +229,11 @@ void Executor::perm(std::vector<Launch>& dst, const PerProb& X, const std::strin
   L.d_desc = upload(ps.data(), sizeof(PermProblem) * np);
   L.d_prefix = (int*)upload(prefix.data(), sizeof(int) * np);
   L.tag = tag;
+  for (int p = 0; p < np; ++p)
+    L.bytes += sizeof(double) * (double)ipow(probs_[p].n, r) * ((alpha != 0.0) + (beta != 0.0) + 1);
+  L.rd = std::move(rd);
+  L.wr = std::move(wr);
+  L.ranged = true;
   dst.push_back(L);
 }
 
@@ -215,6 +269,11 @@ void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const 
     total += (int)((q.d[3] + 1023) / 1024);
   }
   Launch L;
+  for (int p = 0; p < np; ++p) {
+    add_range(L.wr, Y[p], sizeof(double) * (size_t)ipow(probs_[p].n, rank));
+    L.bytes += sizeof(double) * (double)ipow(probs_[p].n, rank);
+  }
+  L.ranged = true;
   L.kind = Launch::FILL;
   L.n_prob = np;
   L.total = total;
@@ -344,12 +403,16 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     perm(dst, A, ai, out, oi, alpha, beta, nullptr, tag);
     return;
   }
-  // scalar operand: scaled permute with a device scalar
+  // scalar operand: scaled permute with a device scalar (over the allowed elements
+  // when the laws are known)
   if (ai.empty() || bi.empty()) {
     const PerProb& S = ai.empty() ? A : *B;
     const PerProb& X = ai.empty() ? *B : A;
     const std::string& xi = ai.empty() ? bi : ai;
     std::vector<const double*> sc(S.begin(), S.end());
+    const int t_x = ai.empty() ? t_b : t_a;
+    if (&dst != &setup_ && !oi.empty() && elem_blocked(dst, X, xi, out, oi, alpha, beta, t_out, t_x, tag, &sc))
+      return;
     perm(dst, X, xi, out, oi, alpha, beta, &sc, tag);
     return;
   }
@@ -379,6 +442,13 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
       ds[p].active = gate_for(dst, p);
     }
     Launch L;
+    for (int p = 0; p < np; ++p) {
+      add_range(L.rd, ds[p].X, sizeof(double) * (size_t)ds[p].len);
+      add_range(L.rd, ds[p].Y, sizeof(double) * (size_t)ds[p].len);
+      add_range(L.wr, ds[p].out, sizeof(double));
+      L.bytes += 2.0 * sizeof(double) * (double)ds[p].len;
+    }
+    L.ranged = true;
     L.kind = Launch::DOT;
     L.n_prob = np;
     L.dot_blocks = 64;
@@ -538,11 +608,13 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     }
     std::vector<double> pf(np);
     std::vector<int> pinst(np);
+    Launch L;
     for (int p = 0; p < np; ++p) {
       pf[p] = 2.0 * gs[p].M * (double)gs[p].N * gs[p].K;
       pinst[p] = probs_[p].inst;
+      L.bytes += sizeof(double) * ((double)gs[p].M * gs[p].K + (double)gs[p].K * gs[p].N +
+                                   (double)gs[p].M * gs[p].N * (beta != 0.0 ? 2 : 1));
     }
-    Launch L;
     L.kind = Launch::GEMM;
     L.n_prob = np;
     L.total = total;
@@ -696,6 +768,39 @@ const Executor::GroupTable& Executor::group_table(int inst, long n, const std::s
   return group_cache_.emplace(key, std::move(T)).first->second;
 }
 
+// Tile shape of one block of a blocked contraction (ml rows, nl columns, kl inner):
+// 0 (16 x 16 MFMA tiles) or a lane-mapped shape code, whichever needs fewer wave
+// latencies by a simple count: a wave costs 3 dependent memory latencies (task,
+// offsets, the store) plus 2 per step of its inner loop; an MFMA step covers 32
+// inner indices, a lane-mapped step 8 per lane of the inner slices (at most 2
+// steps: a lane-mapped wave with a longer chain outlasted the split MFMA tiles
+// in the 123-plane-wave step, 4.3 s against 4.0 s with this cap, 4.5 s without
+// lane-mapped tiles).
+static int sgemm_shape(int ml, int nl, int kl) {
+  auto cdiv = [](long a, long b) { return (a + b - 1) / b; };
+  auto steps = [&](long per) { return std::max(1L, cdiv(kl, per)); };
+  const long mfma = cdiv(ml, 16) * cdiv(nl, 16) * (3 + 2 * steps(32));
+  long best = mfma;
+  int shape = 0;
+  for (int lr = 0; lr <= 6; ++lr)
+    for (int lc = 0; lr + lc <= 6; ++lc) {
+      const int ls = 6 - lr - lc;
+      if (steps(8L << ls) > 2) continue;   // longer ranges: MFMA tiles split over several waves
+      const long c = cdiv(ml, 1L << lr) * cdiv(nl, 1L << lc) * (3 + 2 * steps(8L << ls));
+      if (c < best) {
+        best = c;
+        shape = sgemm_thin_shape(lr, lc, ls);
+      }
+    }
+  return shape;
+}
+
+// wave latencies of a task by the same count (the order of a merged task list)
+static long sgemm_task_cost(const SgemmTask& t) {
+  const long per = t.shape ? (8L << ((t.shape >> 6) & 7)) : 32L;
+  return 3 + 2 * std::max(1L, (t.klen + per - 1) / per);
+}
+
 // C[oi] (+)= alpha A[ai] B[bi] over the momentum-allowed blocks: rows M (letters
 // of A and C), inner K (A and B), columns N (B and C).  A row tuple of momentum
 // q pairs with inner tuples of A-momentum -q and column tuples of B-momentum s q.
@@ -730,9 +835,13 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
   std::vector<SgemmProblem> ps(np);
   std::vector<SgemmTask> tasks;
   struct Tile {
-    int p, m0, ml, k0, kl, n0, nl;
+    int p, m0, ml, k0, kl, n0, nl, shape;
   };
   std::vector<Tile> tiles;
+  // FTCC_SGEMM_THIN=0: 16 x 16 MFMA tiles for every block (diagnostics)
+  double bytes = 0.0;
+  const char* thin_env = std::getenv("FTCC_SGEMM_THIN");
+  const bool thin_ok = !(thin_env && thin_env[0] == '0');
   std::vector<double> pf(np, 0.0);
   std::vector<int> pinst(np);
   double flops = 0.0;
@@ -779,10 +888,13 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
       if (kl == 0 && acc) continue;   // nothing to add; a set writes its zeros
       const int m0 = blk.second.first, ml = blk.second.second;
       const int n0 = nb->second.first, nl = nb->second.second;
-      for (int r = 0; r < ml; r += 16)
-        for (int c = 0; c < nl; c += 16)
-          tiles.push_back(Tile{p, m0 + r, std::min(16, ml - r), k0, kl, n0 + c, std::min(16, nl - c)});
+      const int shape = thin_ok ? sgemm_shape(ml, nl, kl) : 0;
+      const int R = shape ? 1 << (shape & 7) : 16, C = shape ? 1 << ((shape >> 3) & 7) : 16;
+      for (int r = 0; r < ml; r += R)
+        for (int c = 0; c < nl; c += C)
+          tiles.push_back(Tile{p, m0 + r, std::min(R, ml - r), k0, kl, n0 + c, std::min(C, nl - c), shape});
       pf[p] += 2.0 * ml * (double)nl * kl;
+      bytes += sizeof(double) * ((double)ml * kl + (double)kl * nl + (double)ml * nl * (acc ? 2 : 1));
     }
     flops += pf[p];
   }
@@ -795,23 +907,36 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
   auto parts_needed = [&](int ch) {
     long n = 0;
     for (const Tile& t : tiles)
-      if (t.kl > ch + ch / 2) n += (t.kl + ch - 1) / ch;
+      if (!t.shape && t.kl > ch + ch / 2) n += (t.kl + ch - 1) / ch;
     return n;
   };
   while (ws_tiles > 0 && parts_needed(chunk) > ws_tiles) chunk *= 2;
   std::vector<SgemmReduce> reds;
   int parts = 0;
   for (const Tile& t : tiles) {
-    if (ws_tiles == 0 || t.kl <= chunk + chunk / 2) {
-      tasks.push_back(SgemmTask{t.p, t.m0, t.ml, t.k0, t.kl, t.n0, t.nl, -1});
+    if (t.shape || ws_tiles == 0 || t.kl <= chunk + chunk / 2) {
+      tasks.push_back(SgemmTask{t.p, t.m0, t.ml, t.k0, t.kl, t.n0, t.nl, -1, t.shape});
       continue;
     }
     const int first = parts;
     for (int k = 0; k < t.kl; k += chunk)
-      tasks.push_back(SgemmTask{t.p, t.m0, t.ml, t.k0 + k, std::min(chunk, t.kl - k), t.n0, t.nl, parts++});
+      tasks.push_back(SgemmTask{t.p, t.m0, t.ml, t.k0 + k, std::min(chunk, t.kl - k), t.n0, t.nl, parts++, 0});
     reds.push_back(SgemmReduce{t.p, t.m0, t.ml, t.n0, t.nl, first, parts - first});
   }
   Launch L;
+  for (int p = 0; p < np; ++p) {
+    const long n = probs_[p].n;
+    add_range(L.rd, A[p], sizeof(double) * (size_t)ipow(n, (int)ai.size()));
+    add_range(L.rd, B[p], sizeof(double) * (size_t)ipow(n, (int)bi.size()));
+    add_range(L.wr, out[p], sizeof(double) * (size_t)ipow(n, (int)oi.size()));
+  }
+  L.ranged = true;
+  L.bytes = bytes;
+  if (&dst != &setup_) {
+    L.sprobs = ps;
+    L.stasks = tasks;
+    L.sreds = reds;
+  }
   L.kind = Launch::SGEMM;
   L.n_prob = np;
   L.d_desc = upload(ps.data(), sizeof(SgemmProblem) * np);
@@ -838,7 +963,7 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
 // Returns false (dense lowering) when a law is unknown.
 bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
                             const std::string& yi, double alpha, double beta, int t_y, int t_x,
-                            const std::string& tag) {
+                            const std::string& tag, const std::vector<const double*>* scale) {
   if (mom_.empty() || t_y < 0 || t_x < 0 || !law_ok_[t_y] || !law_ok_[t_x] || yi.empty()) return false;
   const std::vector<int>& ly = law_[t_y];
   const std::vector<int>& lx = law_[t_x];
@@ -873,6 +998,7 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
     P.alpha = alpha;
     P.beta = beta;
     P.active = gate_for(dst, p);
+    P.scale = scale ? (*scale)[p] : nullptr;
     const InstMomentum& Mm = *mom_[inst];
     for (const auto& blk : T1.blocks) {
       std::vector<int> q(Mm.dims);
@@ -887,6 +1013,14 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
     }
   }
   Launch L;
+  for (int p = 0; p < np; ++p) {
+    const long n = probs_[p].n;
+    if (alpha != 0.0 && scale) add_range(L.rd, (*scale)[p], sizeof(double));
+    if (alpha != 0.0) add_range(L.rd, X[p], sizeof(double) * (size_t)ipow(n, (int)xi.size()));
+    if (beta != 0.0) add_range(L.rd, Y[p], sizeof(double) * (size_t)ipow(n, (int)yi.size()));
+    add_range(L.wr, Y[p], sizeof(double) * (size_t)ipow(n, (int)yi.size()));
+  }
+  L.ranged = true;
   L.kind = Launch::ELEM;
   L.n_prob = np;
   L.d_desc = upload(ps.data(), sizeof(ElemProblem) * np);
@@ -897,8 +1031,9 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
     L.d_bfirst = upload(bf.data(), sizeof(int) * bf.size());
   }
   L.n_elem = total;
-  if (alpha == 0.0 && beta == 0.0) {
-    L.zero_fill = true;
+  L.bytes = sizeof(double) * (double)total * ((alpha != 0.0) + (beta != 0.0) + 1);
+  L.zero_fill = alpha == 0.0 && beta == 0.0;
+  if (&dst != &setup_) {
     L.eprobs = ps;
     L.etasks = tasks;
   }
@@ -956,6 +1091,13 @@ bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std
   }
   if ((total + 255) / 256 > (long long)scratch_->tail_ws_doubles) return false;
   Launch L;
+  for (int p = 0; p < np; ++p) {
+    const long n = probs_[p].n;
+    add_range(L.rd, A[p], sizeof(double) * (size_t)ipow(n, (int)ai.size()));
+    add_range(L.rd, B[p], sizeof(double) * (size_t)ipow(n, (int)bi.size()));
+    add_range(L.wr, out[p], sizeof(double));
+  }
+  L.ranged = true;
   L.kind = Launch::DOTB;
   L.n_prob = np;
   L.d_desc = upload(ps.data(), sizeof(DotbProblem) * np);
@@ -966,6 +1108,7 @@ bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std
     L.d_bfirst = upload(bf.data(), sizeof(int) * bf.size());
   }
   L.n_elem = total;
+  L.bytes = 2.0 * sizeof(double) * (double)total;
   L.d_partial = scratch_->tail_ws;
   L.tag = tag + "(blocked dot)";
   dst.push_back(L);
@@ -987,6 +1130,7 @@ void Executor::merge_fills(std::vector<Launch>& L) {
         m.etasks.push_back(t);
       }
       m.n_elem += l.n_elem;
+      m.bytes += l.bytes;
       m.tag += "+" + l.tag;
       merged.back() = true;
       continue;
@@ -1013,6 +1157,155 @@ double Executor::sgemm_flops_forward() const {
   for (const Launch& l : fwd_)
     if (l.kind == Launch::SGEMM) f += l.flops;
   return f;
+}
+
+Launch Executor::merge_sgemm(const std::vector<Launch*>& parts) {
+  Launch M;
+  M.kind = Launch::SGEMM;
+  M.ranged = true;
+  int part_base = 0;
+  for (const Launch* l : parts) {
+    const int po = (int)M.sprobs.size();
+    M.sprobs.insert(M.sprobs.end(), l->sprobs.begin(), l->sprobs.end());
+    for (SgemmTask t : l->stasks) {
+      t.prob += po;
+      if (t.part >= 0) t.part += part_base;
+      M.stasks.push_back(t);
+    }
+    int n_parts = 0;
+    for (SgemmReduce r : l->sreds) {
+      r.prob += po;
+      r.first += part_base;
+      n_parts += r.count;
+      M.sreds.push_back(r);
+    }
+    part_base += n_parts;
+    M.flops += l->flops;
+    M.bytes += l->bytes;
+    M.prob_flops.insert(M.prob_flops.end(), l->prob_flops.begin(), l->prob_flops.end());
+    M.prob_inst.insert(M.prob_inst.end(), l->prob_inst.begin(), l->prob_inst.end());
+    M.rd.insert(M.rd.end(), l->rd.begin(), l->rd.end());
+    M.wr.insert(M.wr.end(), l->wr.begin(), l->wr.end());
+    M.tag += (M.tag.empty() ? "" : "+") + l->tag;
+  }
+  // longest tasks first, so that the last wave of the launch holds short ones
+  std::stable_sort(M.stasks.begin(), M.stasks.end(),
+                   [](const SgemmTask& a, const SgemmTask& b) { return sgemm_task_cost(a) > sgemm_task_cost(b); });
+  normalize(M.rd);
+  normalize(M.wr);
+  M.n_prob = (int)M.sprobs.size();
+  M.d_desc = upload(M.sprobs.data(), sizeof(SgemmProblem) * M.sprobs.size());
+  M.n_tasks = (int)M.stasks.size();
+  M.d_tasks = upload(M.stasks.data(), sizeof(SgemmTask) * std::max<size_t>(M.stasks.size(), 1));
+  M.n_red = (int)M.sreds.size();
+  if (M.n_red > 0) {
+    M.d_red = upload(M.sreds.data(), sizeof(SgemmReduce) * M.sreds.size());
+    M.d_partial = scratch_->tail_ws;
+  }
+  M.total = (M.n_tasks + 3) / 4;
+  return M;
+}
+
+Launch Executor::merge_elem(const std::vector<Launch*>& parts) {
+  Launch M;
+  M.kind = Launch::ELEM;
+  M.ranged = true;
+  M.zero_fill = true;
+  for (const Launch* l : parts) {
+    const int po = (int)M.eprobs.size();
+    M.eprobs.insert(M.eprobs.end(), l->eprobs.begin(), l->eprobs.end());
+    for (ElemTask t : l->etasks) {
+      t.prob += po;
+      t.first += M.n_elem;
+      M.etasks.push_back(t);
+    }
+    M.n_elem += l->n_elem;
+    M.bytes += l->bytes;
+    M.zero_fill = M.zero_fill && l->zero_fill;
+    M.rd.insert(M.rd.end(), l->rd.begin(), l->rd.end());
+    M.wr.insert(M.wr.end(), l->wr.begin(), l->wr.end());
+    M.tag += (M.tag.empty() ? "" : "+") + l->tag;
+  }
+  normalize(M.rd);
+  normalize(M.wr);
+  M.n_prob = (int)M.eprobs.size();
+  M.d_desc = upload(M.eprobs.data(), sizeof(ElemProblem) * M.eprobs.size());
+  M.n_tasks = (int)M.etasks.size();
+  M.d_tasks = upload(M.etasks.data(), sizeof(ElemTask) * std::max<size_t>(M.etasks.size(), 1));
+  const std::vector<int> bf = block_first_tasks(M.etasks, M.n_elem);
+  M.d_bfirst = upload(bf.data(), sizeof(int) * bf.size());
+  M.total = (int)std::min<long long>((M.n_elem + 255) / 256, 1 << 30);
+  return M;
+}
+
+void Executor::fuse_levels(std::vector<Launch>& L) {
+  const int nL = (int)L.size();
+  for (Launch& l : L) {
+    normalize(l.rd);
+    normalize(l.wr);
+  }
+  // level: one more than the highest level of any earlier launch it must follow
+  std::vector<int> level(nL, 0);
+  int top = 0;
+  for (int i = 0; i < nL; ++i) {
+    int lv = 0;
+    for (int j = i - 1; j >= 0; --j)
+      if (level[j] + 1 > lv && ordered(L[j], L[i])) lv = level[j] + 1;
+    level[i] = lv;
+    top = std::max(top, lv);
+  }
+  std::vector<std::vector<int>> at(top + 1);
+  for (int i = 0; i < nL; ++i) at[level[i]].push_back(i);
+  const long ws_tiles = scratch_ && scratch_->tail_ws ? (long)(scratch_->tail_ws_doubles / 256) : 0;
+  std::vector<Launch> out;
+  std::vector<void*> freed;
+  auto retire = [&](Launch& l) {
+    for (void* d : {l.d_desc, l.d_tasks, l.d_red, l.d_bfirst})
+      if (d) freed.push_back(d);
+  };
+  for (const std::vector<int>& lv : at) {
+    std::vector<Launch*> sg, el;
+    for (int i : lv) {
+      Launch& l = L[i];
+      if (l.kind == Launch::SGEMM && !l.sprobs.empty()) sg.push_back(&l);
+      else if (l.kind == Launch::ELEM && !l.eprobs.empty()) el.push_back(&l);
+      else out.push_back(std::move(l));
+    }
+    if (el.size() == 1) {
+      out.push_back(std::move(*el[0]));
+    } else if (el.size() > 1) {
+      out.push_back(merge_elem(el));
+      for (Launch* l : el) retire(*l);
+    }
+    // blocked contractions: one launch while their partial tiles fit the workspace
+    size_t k = 0;
+    while (k < sg.size()) {
+      std::vector<Launch*> grp;
+      long parts = 0;
+      for (; k < sg.size(); ++k) {
+        long np = 0;
+        for (const SgemmReduce& r : sg[k]->sreds) np += r.count;
+        if (!grp.empty() && parts + np > ws_tiles) break;
+        grp.push_back(sg[k]);
+        parts += np;
+      }
+      if (grp.size() == 1) {
+        out.push_back(std::move(*grp[0]));
+      } else {
+        out.push_back(merge_sgemm(grp));
+        for (Launch* l : grp) retire(*l);
+      }
+    }
+  }
+  release(freed);
+  for (Launch& l : out) {   // host copies no longer needed
+    std::vector<SgemmProblem>().swap(l.sprobs);
+    std::vector<SgemmTask>().swap(l.stasks);
+    std::vector<SgemmReduce>().swap(l.sreds);
+    std::vector<ElemProblem>().swap(l.eprobs);
+    std::vector<ElemTask>().swap(l.etasks);
+  }
+  L = std::move(out);
 }
 
 // ------------------------------------------------------------------ build
@@ -1089,6 +1382,8 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
     version_[o.out]++;
   }
   if (!want_backward) {
+    const char* fz = std::getenv("FTCC_FUSE");
+    if (!mom_.empty() && !(fz && fz[0] == '0')) fuse_levels(fwd_);
     dump_plan();
     return;
   }
@@ -1113,7 +1408,14 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
       contract(bwd_, grd[o.b], o.bi, o.alpha, fwd[o.a], o.ai, cidx(o.a), &grd[o.out], o.oi, -1, true, tag + ":dB",
                vidx(o.a), -1, o.b, o.a, o.out);
   }
-  merge_fills(bwd_);
+  // FTCC_FUSE=0 keeps the program order, one launch per contraction (diagnostics)
+  const char* fz = std::getenv("FTCC_FUSE");
+  if (!mom_.empty() && !(fz && fz[0] == '0')) {
+    fuse_levels(fwd_);
+    fuse_levels(bwd_);
+  } else {
+    merge_fills(bwd_);
+  }
   dump_plan();
 }
 
@@ -1298,6 +1600,31 @@ void KernelProfiler::harvest() {
 
 KernelProfiler::~KernelProfiler() {
   for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+long Executor::dispatches(const std::vector<Launch>& L) const {
+  long k = 0;
+  for (const Launch& l : L) {
+    switch (l.kind) {
+      case Launch::GEMM: {
+        const GemmTail t = tail_of(l, l.cfg);
+        k += (l.total > 0) + (t.splits > 1 && t.dp_tiles < l.total) + (l.splitk_blocks > 0);
+        break;
+      }
+      case Launch::SGEMM: k += (l.n_tasks > 0) + (l.n_tasks > 0 && l.n_red > 0); break;
+      case Launch::DOT: k += 2; break;
+      case Launch::DOTB: k += 1 + (l.n_elem > 0 && l.n_tasks > 0); break;
+      case Launch::ELEM: k += (l.n_tasks > 0 && l.n_elem > 0); break;
+      default: k += (l.total > 0); break;
+    }
+  }
+  return k;
+}
+
+double Executor::bytes_forward() const {
+  double b = 0.0;
+  for (const Launch& l : fwd_) b += l.bytes;
+  return b;
 }
 
 double Executor::gemm_flops_forward() const {

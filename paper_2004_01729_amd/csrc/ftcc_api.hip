@@ -2299,6 +2299,17 @@ int ftcc_time_residual(ftcc_ctx* c, int reps, double* seconds_out, double* flops
   });
 }
 
+int ftcc_plan_info(ftcc_ctx* c, long* disp_fwd, long* disp_bwd, double* bytes_fwd, int* slots_out) {
+  return run_guarded([&] {
+    if (!c) fail(FTCC_EINVAL, "null context");
+    if (!c->built) fail(FTCC_ESTATE, "evaluate a residual or solve first");
+    if (disp_fwd) *disp_fwd = c->ex_main->dispatches_forward();
+    if (disp_bwd) *disp_bwd = c->ex_main->dispatches_backward();
+    if (bytes_fwd) *bytes_fwd = c->ex_main->bytes_forward();
+    if (slots_out) *slots_out = c->slots;
+  });
+}
+
 int ftcc_kernel_profile(ftcc_ctx* c, int enable, double* flops, double* seconds, long* launches) {
   return run_guarded([&] {
     if (!c) fail(FTCC_EINVAL, "null context");

@@ -104,11 +104,16 @@ struct SgemmProblem {
 };
 struct SgemmTask {
   int prob;
-  int mb, mlen;          // first row (index into offAM / offCM) and rows (<= 16)
+  int mb, mlen;          // first row (index into offAM / offCM) and rows
   int kb, klen;          // first inner index (into offAK / offBK) and count
-  int nb, nlen;          // first column (into offBN / offCN) and columns (<= 16)
+  int nb, nlen;          // first column (into offBN / offCN) and columns
   int part;              // -1: write C; else the 16 x 16 partial tile goes to ws[part * 256 ...]
+  int shape;             // 0: one 16 x 16 MFMA tile (rows, columns <= 16); else a lane-mapped tile of
+                         // 2^lr rows x 2^lc columns whose inner range is split over 2^ls lanes
+                         // (lr | lc << 3 | ls << 6, lr + lc + ls = 6; never split into parts)
 };
+// shape code of a lane-mapped tile
+constexpr int sgemm_thin_shape(int lr, int lc, int ls) { return lr | (lc << 3) | (ls << 6); }
 // A tile whose inner range was split into `count` consecutive partial tiles
 // ws[first .. first + count - 1]: C = alpha * (their sum, in order) + beta * C.
 struct SgemmReduce {
@@ -124,9 +129,10 @@ void launch_sgemm(const SgemmProblem* d_probs, const SgemmTask* d_tasks, int n_t
                   const SgemmReduce* d_red, int n_red, hipStream_t s);
 
 // Momentum-blocked elementwise op over the allowed elements of Y only:
-// Y[oy1[u] + oy2[v]] = alpha * X[ox1[u] + ox2[v]] + beta * Y[oy1[u] + oy2[v]] for
-// every pair (u, v) of a matched pair of index-group blocks (alpha = beta = 0:
-// zero fill, nothing read).  Forbidden elements are never touched.
+// Y[oy1[u] + oy2[v]] = alpha * s * X[ox1[u] + ox2[v]] + beta * Y[oy1[u] + oy2[v]] for
+// every pair (u, v) of a matched pair of index-group blocks, s = *scale (a device
+// scalar) or 1 (alpha = beta = 0: zero fill, nothing read).  Forbidden elements
+// are never touched.
 struct ElemProblem {
   const double* X;
   double* Y;
@@ -136,6 +142,7 @@ struct ElemProblem {
   const unsigned* oy2;
   double alpha, beta;
   const int* active;
+  const double* scale;   // optional device scalar factor of X
 };
 struct ElemTask {
   long long first;       // elements of the tasks before this one

@@ -387,6 +387,50 @@ __global__ void __launch_bounds__(256) sgemm_kernel(const SgemmProblem* __restri
   const gptr<const double> __restrict__ B = gview(P.B);
   const gptr<const unsigned> __restrict__ offAK = gview(P.offAK) + T.kb;
   const gptr<const unsigned> __restrict__ offBK = gview(P.offBK) + T.kb;
+  if (T.shape) {
+    // Lane-mapped tile of a thin block (a single row or column, or a long inner
+    // range on a few outputs): lane = (row, column, inner slice); each lane adds its
+    // slice's products, 8 gathers in flight, then the slices are added by a fixed
+    // butterfly over the wave (every lane takes part, so the order is the same on
+    // every run).
+    const int ls = (T.shape >> 6) & 7, lc = (T.shape >> 3) & 7;
+    const int S = 1 << ls;
+    const int s = lane & (S - 1);
+    const int tc = (lane >> ls) & ((1 << lc) - 1);
+    const int tr = lane >> (ls + lc);
+    const bool ok = tr < T.mlen && tc < T.nlen;
+    double acc = 0.0;
+    if (ok) {
+      const unsigned am = gview(P.offAM)[T.mb + tr];
+      const unsigned bn = gview(P.offBN)[T.nb + tc];
+      int k = s;
+      for (; k + 7 * S < T.klen; k += 8 * S) {
+        unsigned ak[8], bk[8];
+        double a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          ak[u] = offAK[k + u * S];
+          bk[u] = offBK[k + u * S];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          a[u] = A[am + ak[u]];
+          b[u] = B[bk[u] + bn];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(a[u], b[u], acc);
+      }
+      for (; k < T.klen; k += S) acc = fma(A[am + offAK[k]], B[offBK[k] + bn], acc);
+    }
+    for (int o = S >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (ok && s == 0) {
+      const gptr<double> c = gview(P.C) + (size_t)gview(P.offCM)[T.mb + tr] + gview(P.offCN)[T.nb + tc];
+      double v = P.alpha * acc;
+      if (P.beta != 0.0) v += P.beta * (*c);
+      *c = v;
+    }
+    return;
+  }
   const int r = lane & 15, q = lane >> 4;
   const bool row_ok = r < T.mlen, col_ok = r < T.nlen;
   const unsigned am = row_ok ? gview(P.offAM)[T.mb + r] : 0u;
@@ -494,7 +538,10 @@ __global__ void __launch_bounds__(256) elem_kernel(const ElemProblem* __restrict
   const int u = T.u0 + r / T.vlen, v = T.v0 + r % T.vlen;
   const gptr<double> y = gview(P.Y) + gview(P.oy1)[u] + gview(P.oy2)[v];
   double val = 0.0;
-  if (P.alpha != 0.0) val = P.alpha * gview(P.X)[gview(P.ox1)[u] + gview(P.ox2)[v]];
+  if (P.alpha != 0.0) {
+    const double a = P.scale ? P.alpha * *gview(P.scale) : P.alpha;
+    val = a * gview(P.X)[gview(P.ox1)[u] + gview(P.ox2)[v]];
+  }
   if (P.beta != 0.0) val += P.beta * (*y);
   *y = val;
 }

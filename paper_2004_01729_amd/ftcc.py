@@ -74,6 +74,7 @@ def library():
         "ftcc_stats": (ctypes.c_int, [ctypes.c_void_p, _L, _L, _D, _D]),
         "ftcc_find_mu": (ctypes.c_int, [ctypes.c_void_p, _D, _D, _D, ctypes.c_double, ctypes.c_int, _D, _I, _I]),
         "ftcc_kernel_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _D, _D, _L]),
+        "ftcc_plan_info": (ctypes.c_int, [ctypes.c_void_p, _L, _L, _D, _I]),
         "ftcc_two_body_density": (ctypes.c_int, [ctypes.c_void_p, _D]),
         "ftcc_last_error": (ctypes.c_char_p, []),
         "ftcc_abi_version": (ctypes.c_int, []),
@@ -92,7 +93,7 @@ def exported_symbols():
             "ftcc_set_momentum", "ftcc_set_hamiltonian",
             "ftcc_solve_amplitudes", "ftcc_grand_potential", "ftcc_get_amplitudes", "ftcc_lambda",
             "ftcc_get_lambda", "ftcc_response", "ftcc_response_noalloc", "ftcc_find_mu", "ftcc_eval_residual", "ftcc_time_residual",
-            "ftcc_stats",
+            "ftcc_stats", "ftcc_plan_info",
             "ftcc_kernel_profile", "ftcc_two_body_density",
             "ftcc_last_error", "ftcc_abi_version"]
 
@@ -330,6 +331,18 @@ class Context:
         fl = np.zeros(1)
         _check(self.lib.ftcc_time_residual(self._h, int(reps), _ptr(sec), _ptr(fl)))
         return float(sec[0]), float(fl[0])
+
+    def plan_info(self):
+        """Kernel dispatches of one forward / backward pass of the slot program, the
+        algorithmic bytes of one forward pass, and the nodes per instance it evaluates."""
+        df = ctypes.c_long()
+        db = ctypes.c_long()
+        by = ctypes.c_double()
+        sl = ctypes.c_int()
+        _check(self.lib.ftcc_plan_info(self._h, ctypes.byref(df), ctypes.byref(db), ctypes.byref(by),
+                                       ctypes.byref(sl)))
+        return dict(dispatches_forward=df.value, dispatches_backward=db.value, bytes_forward=by.value,
+                    slots=sl.value)
 
     def kernel_profile(self, enable):
         """Totals of the dominant GEMM kernel since the previous call; then enable/disable."""

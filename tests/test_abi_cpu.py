@@ -43,7 +43,7 @@ def test_binding_lists_match_header():
 
 def test_abi_version_and_error_string(lib):
     lib.ftcc_abi_version.restype = ctypes.c_int
-    assert lib.ftcc_abi_version() == 5
+    assert lib.ftcc_abi_version() == 6
     lib.ftcc_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.ftcc_last_error(), bytes)
 

@@ -153,3 +153,30 @@ def test_one_slot_schedule_blocked(F, monkeypatch):
     assert abs(o0 - o1) < 1e-12 * abs(o0)
     assert abs(m0 - m1) < 1e-10 * max(1.0, abs(m0)) and abs(b0 - b1) < 1e-10 * max(1.0, abs(b0))
     assert np.abs(h0 - h1).max() < 1e-10
+
+
+def test_fused_launch_levels_change_no_result(F, monkeypatch):
+    """The blocked launch lists run as dependency levels (independent blocked
+    contractions and elementwise ops of a level share one launch); every buffer
+    still receives its writes in program order, so a mixed batch gives the same
+    bits as the one-launch-per-contraction order (FTCC_FUSE=0)."""
+    systems = [fi.ueg_config(19, 14, 1.0, 1.0), fi.hubbard_config(L=5, U=3.0, T=0.8),
+               fi.hubbard_config(L=6, U=2.0, T=1.0)]
+    out = []
+    for fuse in ("1", "0"):
+        monkeypatch.setenv("FTCC_FUSE", fuse)
+        print(f"[momentum] mixed batch FTCC_FUSE={fuse}", flush=True)
+        ctx = _ctx(F, systems, n_tau=8, nodes_per_panel=4, tol=1e-13)
+        ctx.solve([s.mu for s in systems], [s.beta for s in systems])
+        om, parts = ctx.grand_potential()
+        amp = ctx.amplitudes(0, 5)
+        ctx.lam()
+        r = ctx.response(want_mu=True, want_beta=True, want_h=True)
+        ctx.close()
+        out.append((om, parts, amp, r))
+    (o0, p0, a0, r0), (o1, p1, a1, r1) = out
+    assert np.array_equal(o0, o1) and np.array_equal(p0, p1)
+    assert np.array_equal(a0[0], a1[0]) and np.array_equal(a0[1], a1[1])
+    assert np.array_equal(r0["mu"], r1["mu"]) and np.array_equal(r0["beta"], r1["beta"])
+    for a, b in zip(r0["h"], r1["h"]):
+        assert np.array_equal(a, b)
