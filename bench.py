@@ -560,6 +560,43 @@ def step_bench(args, measure_fd_beta=False):
     return line
 
 
+def gradient_once(args):
+    """One forward march, Lambda and response (mu, beta, every h_pq) of a workload
+    in a fresh context, each phase timed once: the full-size adjoint as a run,
+    not a throughput (dense or momentum-blocked)."""
+    import numpy as np
+    import torch
+    from paper_2004_01729_amd import ftcc as F
+    s, opts, cfg = workload(args.workload)
+    if args.n_tau:
+        opts = dict(opts, n_tau=args.n_tau)
+        cfg = dict(cfg, n_tau=args.n_tau)
+    if args.tol:
+        opts = dict(opts, tol=args.tol)
+        cfg = dict(cfg, tol=args.tol)
+    t0 = time.perf_counter()
+    ctx = F.Context(1, **opts)
+    if args.momentum:
+        ctx.set_momentum(0, *s.momentum)
+        cfg = dict(cfg, momentum_blocked=True)
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    ctx.solve(s.mu, s.beta)
+    om, parts = ctx.grand_potential()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.lam()
+    r = ctx.response(want_mu=True, want_beta=True, want_h=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    st = ctx.stats()
+    ctx.close()
+    h = r["h"][0]
+    return dict(mode="gradient", config=cfg, forward_with_setup_s=t1 - t0, lambda_and_response_s=t2 - t1,
+                resid_evals=st["resid_evals"], vjp_evals=st["vjp_evals"], omega=float(om[0]),
+                omega_cc=float(parts[0, 2]), dOmega_dmu=float(r["mu"][0]), dOmega_dbeta=float(r["beta"][0]),
+                dOmega_dh_trace=float(np.trace(h)), dOmega_dh_norm=float(np.linalg.norm(h)))
+
+
 def cpu_model():
     try:
         for row in open("/proc/cpuinfo"):
@@ -681,7 +718,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--mode", default="m1",
-                    choices=("m1", "step", "residual", "copy", "batch", "numerr", "afm", "exc"))
+                    choices=("m1", "step", "residual", "copy", "batch", "numerr", "afm", "exc", "gradient"))
+    ap.add_argument("--n-tau", type=int, default=0, help="--mode gradient: tau nodes (0: the workload's)")
+    ap.add_argument("--tol", type=float, default=0.0, help="--mode gradient: sweep tolerance (0: the workload's)")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
     ap.add_argument("--group", type=int, default=32)
@@ -691,7 +730,7 @@ def main():
     ap.add_argument("--diis", type=int, default=0, help="--mode batch: DIIS depth of the fixed-point sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py runs on one GPU; there is no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -711,6 +750,9 @@ def main():
         return
     if args.mode == "numerr":
         print(json.dumps(numerr_bench(momentum=not args.dense)), flush=True)
+        return
+    if args.mode == "gradient":
+        print(json.dumps(gradient_once(args)), flush=True)
         return
     if args.mode == "batch":
         print(json.dumps(batch_bench(args.per_instance, args.group, args.momentum, args.subset, args.diis)),

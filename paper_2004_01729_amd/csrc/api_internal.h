@@ -234,6 +234,8 @@ struct RKSpec {
 long ipow(long n, int r);
 int run_guarded(const std::function<void()>& f);
 bool trace_on();
+// FTCC_TRACE=2: a line per sweep as well (the largest change over the batch)
+void trace_sweep(const char* phase, int panel, int it, const std::vector<double>& maxbits);
 void trace(ftcc_ctx* c, const char* phase, int panel, int n_panels, const std::vector<int>& sweeps,
            std::chrono::steady_clock::time_point t0);
 void trace_mem(ftcc_ctx* c, const char* stage);

@@ -324,12 +324,22 @@ int run_guarded(const std::function<void()>& f) {
 
 // Progress lines on stderr (one per panel of each phase) when FTCC_TRACE is set:
 // large instances spend minutes per phase.
-bool trace_on() {
-  static const bool on = [] {
+static int trace_level() {
+  static const int lv = [] {
     const char* e = std::getenv("FTCC_TRACE");
-    return e && e[0] && e[0] != '0';
+    return e ? std::atoi(e) : 0;
   }();
-  return on;
+  return lv;
+}
+
+bool trace_on() { return trace_level() > 0; }
+
+void trace_sweep(const char* phase, int panel, int it, const std::vector<double>& maxbits) {
+  if (trace_level() < 2) return;
+  double mx = 0.0;
+  for (size_t k = 0; k + 1 < maxbits.size(); k += 2) mx = std::max(mx, maxbits[k]);
+  std::fprintf(stderr, "[ftcc] %s panel %d sweep %d: largest change %.3e\n", phase, panel, it, mx);
+  std::fflush(stderr);
 }
 
 void trace(ftcc_ctx* c, const char* phase, int panel, int n_panels, const std::vector<int>& sweeps,
@@ -1282,6 +1292,7 @@ std::vector<int> panel_solve(ftcc_ctx* c, int panel, std::vector<int>& status) {
     if (diis) diis_before(c, amp_of, active);
     tau_run(c, TAU_STEP, panel);
     std::vector<double> mb = read_maxbits(c);
+    trace_sweep("forward", panel, it, mb);
     bool any = false;
     for (int i = 0; i < B; ++i) {
       if (!active[i]) continue;
@@ -1721,6 +1732,7 @@ int ftcc_lambda(ftcc_ctx* c, int* iters_out, int* status_out) {
         if (diis) diis_before(c, lam_of, active);
         tau_run(c, TAU_LSTEP, p);
         std::vector<double> mb = read_maxbits(c);
+        trace_sweep("lambda", p, it, mb);
         bool any = false;
         for (int i = 0; i < B; ++i) {
           if (!active[i]) continue;

@@ -172,9 +172,14 @@ def test_fused_launch_levels_change_no_result(F, monkeypatch):
         amp = ctx.amplitudes(0, 5)
         ctx.lam()
         r = ctx.response(want_mu=True, want_beta=True, want_h=True)
+        plan = ctx.plan_info()
         ctx.close()
-        out.append((om, parts, amp, r))
-    (o0, p0, a0, r0), (o1, p1, a1, r1) = out
+        out.append((om, parts, amp, r, plan))
+    (o0, p0, a0, r0, q0), (o1, p1, a1, r1, q1) = out
+    # the same work in fewer dispatches
+    assert q0["bytes_forward"] == q1["bytes_forward"] > 0
+    assert q0["dispatches_forward"] < q1["dispatches_forward"]
+    assert q0["dispatches_backward"] < q1["dispatches_backward"]
     assert np.array_equal(o0, o1) and np.array_equal(p0, p1)
     assert np.array_equal(a0[0], a1[0]) and np.array_equal(a0[1], a1[1])
     assert np.array_equal(r0["mu"], r1["mu"]) and np.array_equal(r0["beta"], r1["beta"])
