@@ -109,6 +109,7 @@ struct ftcc_ctx {
   std::vector<double*> s_amp, s_S, s_e, s_gr, s_cot, s_ebar, s_dS, s_de;
   std::vector<std::array<double*, 4>> s_ugrad;
   std::map<std::pair<int, int>, double*> inter, inter_grad, dderived;   // (tensor, problem) / (tensor, inst)
+  std::map<const double*, long> buf_elems;    // element counts of the buffers above (shared by executors)
   std::map<std::pair<int, int>, double*> derived;
   std::vector<std::array<double*, 4>> ugrad;
   Scratch scratch;
@@ -234,6 +235,10 @@ struct RKSpec {
 long ipow(long n, int r);
 int run_guarded(const std::function<void()>& f);
 bool trace_on();
+// the buffer of (t, key) in `store`, allocated with `count` elements on first use;
+// a later request for more elements than it holds is an error (executors that
+// share intermediates must agree on their storage)
+double* shared_buf(ftcc_ctx* c, std::map<std::pair<int, int>, double*>& store, int t, int key, long count);
 // FTCC_TRACE=2: a line per sweep as well (the largest change over the batch)
 void trace_sweep(const char* phase, int panel, int it, const std::vector<double>& maxbits);
 void trace(ftcc_ctx* c, const char* phase, int panel, int n_panels, const std::vector<int>& sweeps,

@@ -72,14 +72,9 @@ void build_gamma_executor(ftcc_ctx* c) {
   const int id_t1 = prog.id("t1"), id_t2 = prog.id("t2"), id_S1 = prog.id("S1"), id_S2 = prog.id("S2"),
             id_E = prog.id("E");
   auto buf = [c](std::map<std::pair<int, int>, double*>& store, int t, int key, long count) {
-    auto k = std::make_pair(t, key);
-    auto it = store.find(k);
-    if (it != store.end()) return it->second;
-    double* p = c->dalloc(count);
-    store[k] = p;
-    return p;
+    return shared_buf(c, store, t, key, count);
   };
-  Binder bind = [&, c](int t, int p, bool grad) -> double* {
+  Binder bind = [&, c](int t, int p, bool grad, size_t count) -> double* {
     const TensorDecl& d = prog.t[t];
     const int i = probs[p].inst;
     const long n = probs[p].n, n2 = n * n, cnt = ipow(n, d.rank);
@@ -90,7 +85,7 @@ void build_gamma_executor(ftcc_ctx* c) {
     if (t == id_E) return grad ? c->s_ebar[p] : c->s_e[p];
     if (d.kind == T_CONST) return grad ? buf(c->g_cgrad, t, p, cnt) : c->inst[i].blk[d.name];
     if (d.derived) return buf(grad ? c->g_cgrad : c->g_derived, t, p, cnt);
-    return buf(grad ? c->inter_grad : c->inter, t, p, cnt);
+    return buf(grad ? c->inter_grad : c->inter, t, p, (long)count);
   };
   std::vector<int> cgrads;
   for (int k = 0; k < (int)prog.t.size(); ++k)

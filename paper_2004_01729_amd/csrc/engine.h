@@ -19,6 +19,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <initializer_list>
 #include <map>
 #include <string>
 #include <vector>
@@ -137,8 +138,18 @@ struct InstMomentum {
   std::vector<int> labels;
 };
 
-// (tensor id, problem index, gradient buffer?) -> device pointer
-using Binder = std::function<double*(int tensor, int prob, bool grad)>;
+// (tensor id, problem index, gradient buffer?, elements the executor addresses)
+// -> device pointer.  The count is n^rank, or n^(rank-1) for an intermediate the
+// executor stores packed (see Executor::packed).
+using Binder = std::function<double*(int tensor, int prob, bool grad, size_t count)>;
+
+// Packed storage of momentum-blocked intermediates: when every orbital of an
+// instance has its own momentum label, the last index of an allowed element is
+// fixed by the others, so an intermediate is stored as n^(rank-1) doubles indexed
+// by all but its last axis.  Labels that repeat (several orbitals per momentum)
+// keep dense storage.  FTCC_PACK=0 keeps every intermediate dense (diagnostics).
+bool labels_distinct(const struct InstMomentum& m);
+bool packing_enabled();
 
 struct Scratch {
   std::vector<double*> a, b, c, part;   // per problem: n^4 doubles each
@@ -208,6 +219,8 @@ class Executor {
   // evaluated over its momentum-allowed blocks only (laws from the Program).
   void set_momentum(const std::vector<const InstMomentum*>& by_instance) { mom_ = by_instance; }
   double sgemm_flops_forward() const;
+  // intermediates stored packed (after build)
+  int n_packed() const;
   double gemm_flops_forward() const;
   double gemm_flops_backward() const;
   int n_launches_forward() const { return (int)fwd_.size(); }
@@ -236,7 +249,7 @@ class Executor {
   void fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const std::string& tag, int t_y = -1);
   // full contraction <A, B> over A's momentum-allowed elements
   bool dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std::string& ai, const PerProb& B,
-                   const std::string& bi, const PerProb& out, double alpha, double beta, int t_a,
+                   const std::string& bi, const PerProb& out, double alpha, double beta, int t_a, int t_b,
                    const std::string& tag);
   bool elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
                     const std::string& yi, double alpha, double beta, int t_y, int t_x, const std::string& tag,
@@ -290,8 +303,18 @@ class Executor {
   bool contract_blocked(std::vector<Launch>& dst, const PerProb& out, const std::string& oi, double alpha,
                         const PerProb& A, const std::string& ai, const PerProb& B, const std::string& bi, bool acc,
                         const std::string& tag, int t_out, int t_a, int t_b);
-  const GroupTable& group_table(int inst, long n, const std::string& letters, const std::string& xi,
-                                const std::string& yi, const std::vector<int>& signs);
+  const GroupTable& group_table(int inst, long n, const std::string& letters, const std::string& xi, bool xp,
+                                const std::string& yi, bool yp, const std::vector<int>& signs);
+  std::vector<char> packed_;               // per tensor: stored packed (n^(rank-1) doubles)
+  void plan_packing(bool want_backward);
+  bool is_packed(int t) const { return t >= 0 && t < (int)packed_.size() && packed_[t]; }
+  size_t elems(int t, long n, int rank) const { return (size_t)ipow_l(n, is_packed(t) ? rank - 1 : rank); }
+  static long ipow_l(long n, int r) {
+    long v = 1;
+    for (int k = 0; k < r; ++k) v *= n;
+    return v;
+  }
+  void dense_guard(const std::string& tag, std::initializer_list<int> ts) const;
   double run_flops(const Launch& l) const;
   GemmTail tail_of(const Launch& l, int cfg) const {
     return plan_gemm_tail(cfg, l.total, l.min_k, l.splitk_blocks > 0, scratch_ ? scratch_->tail_ws : nullptr,

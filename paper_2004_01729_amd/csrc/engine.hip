@@ -245,6 +245,7 @@ void Executor::fill(std::vector<Launch>& dst, const PerProb& Y, int rank, const 
     for (int k = 0; k < rank; ++k) idx.push_back((char)('p' + k));
     if (elem_blocked(dst, Y, idx, Y, idx, 0.0, 0.0, t_y, t_y, tag)) return;
   }
+  dense_guard(tag, {t_y});
   const int np = (int)probs_.size();
   std::vector<PermProblem> ps(np);
   std::vector<int> prefix(np);
@@ -400,6 +401,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     for (char c : ai)
       if (!has(oi, c)) throw std::runtime_error("single-operand reduction unsupported: " + tag);
     if (&dst != &setup_ && elem_blocked(dst, A, ai, out, oi, alpha, beta, t_out, t_a, tag)) return;
+    dense_guard(tag, {t_out, t_a});
     perm(dst, A, ai, out, oi, alpha, beta, nullptr, tag);
     return;
   }
@@ -413,6 +415,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     const int t_x = ai.empty() ? t_b : t_a;
     if (&dst != &setup_ && !oi.empty() && elem_blocked(dst, X, xi, out, oi, alpha, beta, t_out, t_x, tag, &sc))
       return;
+    dense_guard(tag, {t_out, t_a, t_b});
     perm(dst, X, xi, out, oi, alpha, beta, &sc, tag);
     return;
   }
@@ -425,7 +428,8 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
 
   // full contraction -> dot
   if (oi.empty()) {
-    if (&dst != &setup_ && dot_blocked(dst, A, ai, *B, bi, out, alpha, beta, t_a, tag)) return;
+    if (&dst != &setup_ && dot_blocked(dst, A, ai, *B, bi, out, alpha, beta, t_a, t_b, tag)) return;
+    dense_guard(tag, {t_a, t_b, t_out});
     PerProb Bp = *B;
     if (bi != ai) {
       if (b_const >= 0) Bp = const_permuted(b_const, *B, bi, ai);
@@ -459,6 +463,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
     return;
   }
 
+  dense_guard(tag, {t_out, t_a, t_b});
   const std::string M_a = filter(ai, bi, oi, false, true);   // in A and out only
   const std::string K_a = filter(ai, bi, oi, true, false);   // in A and B only
   const std::string N_b = filter(bi, ai, oi, false, true);
@@ -657,6 +662,64 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
 // orientation s of B's law (sign_A * sign_B, the same for every contracted
 // letter), and out gets sign_A on A's free letters and -s * sign_B on B's.
 // Every op writing a tensor must give the same law up to an overall sign.
+bool packing_enabled() {
+  const char* e = std::getenv("FTCC_PACK");
+  return !(e && e[0] == '0');
+}
+
+bool labels_distinct(const InstMomentum& M) {
+  const int D = M.dims;
+  if (D <= 0) return false;
+  const int n = (int)(M.labels.size() / D);
+  std::vector<std::vector<int>> keys(n, std::vector<int>(D));
+  for (int p = 0; p < n; ++p)
+    for (int c = 0; c < D; ++c) {
+      int v = M.labels[(size_t)p * D + c];
+      if (M.modulus[c] > 0) v = ((v % M.modulus[c]) + M.modulus[c]) % M.modulus[c];
+      keys[p][c] = v;
+    }
+  std::sort(keys.begin(), keys.end());
+  return std::adjacent_find(keys.begin(), keys.end()) == keys.end();
+}
+
+void Executor::dense_guard(const std::string& tag, std::initializer_list<int> ts) const {
+  for (int t : ts)
+    if (is_packed(t)) throw std::runtime_error("packed intermediate on a dense path: " + tag);
+}
+
+int Executor::n_packed() const {
+  int k = 0;
+  for (char v : packed_) k += v ? 1 : 0;
+  return k;
+}
+
+// Which intermediates are stored packed: rank >= 2, a known momentum law, every
+// instance's labels distinct, and every op that touches the tensor (forward, and
+// its reverse forms when the backward list is built) has known laws on all of
+// its tensors, so that it lowers to blocked kernels, which address elements
+// through offset tables only.  Derived constants keep dense storage (their set-up
+// ops are dense permutes).
+void Executor::plan_packing(bool want_backward) {
+  const int nt = (int)prog_->t.size();
+  packed_.assign(nt, 0);
+  if (mom_.empty() || !packing_enabled()) return;
+  for (const ProblemRef& p : probs_)
+    if (p.inst < 0 || p.inst >= (int)mom_.size() || !mom_[p.inst] || !labels_distinct(*mom_[p.inst])) return;
+  for (int k = 0; k < nt; ++k) {
+    const TensorDecl& d = prog_->t[k];
+    packed_[k] = (d.kind == T_INTER && !d.derived && d.rank >= 2 && law_ok_[k]) ? 1 : 0;
+  }
+  (void)want_backward;   // the reverse forms of an op lower blocked exactly when the forward does
+  for (const SymOp& o : prog_->ops) {
+    if (o.setup && !inline_setup_) continue;
+    const bool ok = law_ok_[o.out] && law_ok_[o.a] && (o.b < 0 || law_ok_[o.b]);
+    if (ok) continue;
+    packed_[o.out] = 0;
+    packed_[o.a] = 0;
+    if (o.b >= 0) packed_[o.b] = 0;
+  }
+}
+
 void Executor::infer_laws() {
   const int nt = (int)prog_->t.size();
   law_.assign(nt, {});
@@ -713,22 +776,26 @@ static long long pack_momentum(const std::vector<int>& q) {
 // offsets in the operands indexed by xi and yi (row-major, every axis n) and
 // the packed momentum sum_l signs[l] k(index_l) of each block.
 const Executor::GroupTable& Executor::group_table(int inst, long n, const std::string& letters,
-                                                  const std::string& xi, const std::string& yi,
-                                                  const std::vector<int>& signs) {
-  std::string key = std::to_string(inst) + "|" + letters + "|" + xi + "|" + yi + "|";
+                                                  const std::string& xi, bool xp, const std::string& yi,
+                                                  bool yp, const std::vector<int>& signs) {
+  std::string key = std::to_string(inst) + "|" + letters + "|" + xi + (xp ? "#" : "") + "|" + yi +
+                    (yp ? "#" : "") + "|";
   for (int v : signs) key += (v > 0 ? '+' : '-');
   auto it = group_cache_.find(key);
   if (it != group_cache_.end()) return it->second;
   const InstMomentum& M = *mom_[inst];
   const int g = (int)letters.size(), D = M.dims;
-  auto stride = [&](const std::string& idx, char c) -> unsigned long {
-    const size_t pos = idx.find(c);
-    return (unsigned long)ipow(n, (int)idx.size() - 1 - (int)pos);
+  // row-major strides; a packed tensor drops its last axis (stride 0: that index
+  // is fixed by the others on every allowed element)
+  auto stride = [&](const std::string& idx, bool packed, char c) -> unsigned long {
+    const int pos = (int)idx.find(c), len = (int)idx.size();
+    if (!packed) return (unsigned long)ipow(n, len - 1 - pos);
+    return pos == len - 1 ? 0ul : (unsigned long)ipow(n, len - 2 - pos);
   };
   std::vector<unsigned long> sx(g), sy(g);
   for (int l = 0; l < g; ++l) {
-    sx[l] = stride(xi, letters[l]);
-    sy[l] = stride(yi, letters[l]);
+    sx[l] = stride(xi, xp, letters[l]);
+    sy[l] = stride(yi, yp, letters[l]);
   }
   const long count = ipow(n, g);
   struct Row {
@@ -851,9 +918,9 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
     if (inst < 0 || inst >= (int)mom_.size() || !mom_[inst]) throw std::runtime_error("momentum labels missing");
     if (ipow(n, (int)std::max(std::max(ai.size(), bi.size()), oi.size())) >= (1L << 32))
       throw std::runtime_error("tensor exceeds 2^32 elements: " + tag);
-    const GroupTable& TM = group_table(inst, n, M, ai, oi, sgM);
-    const GroupTable& TK = group_table(inst, n, K, ai, bi, sgK);
-    const GroupTable& TN = group_table(inst, n, N, bi, oi, sgN);
+    const GroupTable& TM = group_table(inst, n, M, ai, is_packed(t_a), oi, is_packed(t_out), sgM);
+    const GroupTable& TK = group_table(inst, n, K, ai, is_packed(t_a), bi, is_packed(t_b), sgK);
+    const GroupTable& TN = group_table(inst, n, N, bi, is_packed(t_b), oi, is_packed(t_out), sgN);
     SgemmProblem& P = ps[p];
     P.A = A[p];
     P.B = B[p];
@@ -926,9 +993,9 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
   Launch L;
   for (int p = 0; p < np; ++p) {
     const long n = probs_[p].n;
-    add_range(L.rd, A[p], sizeof(double) * (size_t)ipow(n, (int)ai.size()));
-    add_range(L.rd, B[p], sizeof(double) * (size_t)ipow(n, (int)bi.size()));
-    add_range(L.wr, out[p], sizeof(double) * (size_t)ipow(n, (int)oi.size()));
+    add_range(L.rd, A[p], sizeof(double) * elems(t_a, n, (int)ai.size()));
+    add_range(L.rd, B[p], sizeof(double) * elems(t_b, n, (int)bi.size()));
+    add_range(L.wr, out[p], sizeof(double) * elems(t_out, n, (int)oi.size()));
   }
   L.ranged = true;
   L.bytes = bytes;
@@ -986,8 +1053,8 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
     const int inst = probs_[p].inst;
     const long n = probs_[p].n;
     if (ipow(n, (int)yi.size()) >= (1L << 32)) throw std::runtime_error("tensor exceeds 2^32 elements: " + tag);
-    const GroupTable& T1 = group_table(inst, n, G1, xi, yi, s1);
-    const GroupTable& T2 = group_table(inst, n, G2, xi, yi, s2);
+    const GroupTable& T1 = group_table(inst, n, G1, xi, is_packed(t_x), yi, is_packed(t_y), s1);
+    const GroupTable& T2 = group_table(inst, n, G2, xi, is_packed(t_x), yi, is_packed(t_y), s2);
     ElemProblem& P = ps[p];
     P.X = X[p];
     P.Y = Y[p];
@@ -1016,9 +1083,9 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
   for (int p = 0; p < np; ++p) {
     const long n = probs_[p].n;
     if (alpha != 0.0 && scale) add_range(L.rd, (*scale)[p], sizeof(double));
-    if (alpha != 0.0) add_range(L.rd, X[p], sizeof(double) * (size_t)ipow(n, (int)xi.size()));
-    if (beta != 0.0) add_range(L.rd, Y[p], sizeof(double) * (size_t)ipow(n, (int)yi.size()));
-    add_range(L.wr, Y[p], sizeof(double) * (size_t)ipow(n, (int)yi.size()));
+    if (alpha != 0.0) add_range(L.rd, X[p], sizeof(double) * elems(t_x, n, (int)xi.size()));
+    if (beta != 0.0) add_range(L.rd, Y[p], sizeof(double) * elems(t_y, n, (int)yi.size()));
+    add_range(L.wr, Y[p], sizeof(double) * elems(t_y, n, (int)yi.size()));
   }
   L.ranged = true;
   L.kind = Launch::ELEM;
@@ -1044,7 +1111,7 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
 }
 
 bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std::string& ai, const PerProb& B,
-                           const std::string& bi, const PerProb& out, double alpha, double beta, int t_a,
+                           const std::string& bi, const PerProb& out, double alpha, double beta, int t_a, int t_b,
                            const std::string& tag) {
   if (mom_.empty() || t_a < 0 || !law_ok_[t_a] || ai.empty() || !scratch_ || !scratch_->tail_ws) return false;
   const std::vector<int>& la = law_[t_a];
@@ -1059,8 +1126,8 @@ bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std
     const long n = probs_[p].n;
     if (ipow(n, (int)ai.size()) >= (1L << 32)) throw std::runtime_error("tensor exceeds 2^32 elements: " + tag);
     // A's allowed elements: index groups G1 of momentum q with G2 of momentum -q
-    const GroupTable& T1 = group_table(inst, n, G1, ai, bi, s1);
-    const GroupTable& T2 = group_table(inst, n, G2, ai, bi, s2);
+    const GroupTable& T1 = group_table(inst, n, G1, ai, is_packed(t_a), bi, is_packed(t_b), s1);
+    const GroupTable& T2 = group_table(inst, n, G2, ai, is_packed(t_a), bi, is_packed(t_b), s2);
     DotbProblem& P = ps[p];
     P.X = A[p];
     P.Y = B[p];
@@ -1093,8 +1160,8 @@ bool Executor::dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std
   Launch L;
   for (int p = 0; p < np; ++p) {
     const long n = probs_[p].n;
-    add_range(L.rd, A[p], sizeof(double) * (size_t)ipow(n, (int)ai.size()));
-    add_range(L.rd, B[p], sizeof(double) * (size_t)ipow(n, (int)bi.size()));
+    add_range(L.rd, A[p], sizeof(double) * elems(t_a, n, (int)ai.size()));
+    add_range(L.rd, B[p], sizeof(double) * elems(t_b, n, (int)bi.size()));
     add_range(L.wr, out[p], sizeof(double));
   }
   L.ranged = true;
@@ -1321,18 +1388,19 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
   scratch_ = scratch;
   const_alloc_ = const_alloc;
   if (!mom_.empty()) infer_laws();
+  plan_packing(want_backward);
   const int np = (int)probs.size();
   const int nt = (int)prog->t.size();
   std::vector<PerProb> fwd(nt, PerProb(np)), grd(nt, PerProb(np));
   std::vector<bool> need_grad(nt, false);
   for (int k = 0; k < nt; ++k) {
     const TensorDecl& d = prog->t[k];
-    for (int p = 0; p < np; ++p) fwd[k][p] = bind(k, p, false);
+    for (int p = 0; p < np; ++p) fwd[k][p] = bind(k, p, false, elems(k, probs[p].n, d.rank));
     bool g = (d.kind == T_INPUT || d.kind == T_OUTPUT || (d.kind == T_INTER && (!d.derived || inline_setup_)));
     if (std::find(const_grads.begin(), const_grads.end(), k) != const_grads.end()) g = true;
     need_grad[k] = g && want_backward;
     if (need_grad[k])
-      for (int p = 0; p < np; ++p) grd[k][p] = bind(k, p, true);
+      for (int p = 0; p < np; ++p) grd[k][p] = bind(k, p, true, elems(k, probs[p].n, d.rank));
   }
   auto cidx = [&](int k) {
     return (k >= 0 && (prog->t[k].kind == T_CONST || (prog->t[k].derived && !inline_setup_))) ? k : -1;

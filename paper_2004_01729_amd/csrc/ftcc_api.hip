@@ -324,6 +324,21 @@ int run_guarded(const std::function<void()>& f) {
 
 // Progress lines on stderr (one per panel of each phase) when FTCC_TRACE is set:
 // large instances spend minutes per phase.
+double* shared_buf(ftcc_ctx* c, std::map<std::pair<int, int>, double*>& store, int t, int key, long count) {
+  auto k = std::make_pair(t, key);
+  auto it = store.find(k);
+  if (it != store.end()) {
+    if (c->buf_elems[it->second] < count)
+      fail(FTCC_EINVAL, "an executor asked for " + std::to_string(count) + " elements of a shared buffer of " +
+                            std::to_string(c->buf_elems[it->second]));
+    return it->second;
+  }
+  double* p = c->dalloc(count);
+  store[k] = p;
+  c->buf_elems[p] = count;
+  return p;
+}
+
 static int trace_level() {
   static const int lv = [] {
     const char* e = std::getenv("FTCC_TRACE");
@@ -361,8 +376,11 @@ void trace_mem(ftcc_ctx* c, const char* stage) {
 
 void trace_executor(ftcc_ctx* c, const char* which, const Executor& ex) {
   if (!trace_on()) return;
-  std::fprintf(stderr, "[ftcc] %s executor built: %.2f GiB held (cached operand copies %.2f GiB, permuted constants %.2f GiB)\n",
-               which, c->bytes / 1073741824.0, ex.cache_bytes() / 1073741824.0, ex.const_copy_bytes() / 1073741824.0);
+  std::fprintf(stderr,
+               "[ftcc] %s executor built: %.2f GiB held (cached operand copies %.2f GiB, permuted constants %.2f GiB, "
+               "%d packed intermediates, %d slots)\n",
+               which, c->bytes / 1073741824.0, ex.cache_bytes() / 1073741824.0, ex.const_copy_bytes() / 1073741824.0,
+               ex.n_packed(), c->slots);
   std::fflush(stderr);
 }
 
@@ -675,12 +693,17 @@ void build(ftcc_ctx* c) {
   }
   trace_mem(c, "integrals, panel states and Lambda storage");
   // Executor slots per instance: every node of a panel evaluated in one grouped
-  // launch (slots = m) unless the per-slot working set (about 40 n^4 doubles:
-  // intermediates, their gradients, scratch) would take more than half of the
-  // free device memory; then the nodes go through one slot in turn.
+  // launch (slots = m) unless the per-slot working set would take more than half
+  // of the free device memory; then the nodes go through one slot in turn.  The
+  // working set is about 40 n^4 doubles (intermediates, their gradients,
+  // scratch), or, when the momentum-blocked intermediates are stored packed
+  // (n^3 each), the scratch and the derivative residual of each slot, 5 n^4.
   {
+    bool packed = momentum_on(c) && packing_enabled();
+    for (const Instance& I : c->inst) packed = packed && labels_distinct(I.mom);
     double need = 0.0;
-    for (int i = 0; i < B; ++i) need += 40.0 * m * std::pow((double)c->inst[i].n, 4) * sizeof(double);
+    for (int i = 0; i < B; ++i)
+      need += (packed ? 5.0 : 40.0) * m * std::pow((double)c->inst[i].n, 4) * sizeof(double);
     c->slots = (need > 0.5 * c->available()) ? 1 : m;
     const char* senv = std::getenv("FTCC_NODE_SLOTS");
     if (senv && senv[0] == '1') c->slots = 1;
@@ -818,17 +841,13 @@ void build(ftcc_ctx* c) {
             id_E = prog.id("E");
 
   auto tensor_buf = [c, &probs](std::map<std::pair<int, int>, double*>& store, int t, int key, long count) {
-    auto k = std::make_pair(t, key);
-    auto it = store.find(k);
-    if (it != store.end()) return it->second;
-    double* p = c->dalloc(count);
-    store[k] = p;
-    return p;
+    return shared_buf(c, store, t, key, count);
   };
-  auto bind_common = [&, c](int t, int p, bool grad) -> double* {
+  // intermediates take the element count the executor addresses (packed or dense)
+  auto bind_common = [&, c](int t, int p, bool grad, size_t count) -> double* {
     const TensorDecl& d = prog.t[t];
     const long n = probs[p].n, n2 = n * n;
-    const long cnt = ipow(n, d.rank);
+    const long cnt = (long)count;
     if (t == id_t1) return grad ? c->s_gr[p] : c->s_amp[p];
     if (t == id_t2) return grad ? c->s_gr[p] + n2 : c->s_amp[p] + n2;
     if (grad) {
@@ -845,9 +864,9 @@ void build(ftcc_ctx* c) {
     if (d.kind == T_INTER && !d.derived) return tensor_buf(c->inter, t, p, cnt);
     return nullptr;
   };
-  Binder bind_main = [&, c](int t, int p, bool grad) -> double* {
+  Binder bind_main = [&, c](int t, int p, bool grad, size_t count) -> double* {
     const TensorDecl& d = prog.t[t];
-    if (double* q = bind_common(t, p, grad)) return q;
+    if (double* q = bind_common(t, p, grad, count)) return q;
     const int i = probs[p].inst;
     const long n = probs[p].n, n2 = n * n;
     if (d.kind == T_CONST) return c->inst[i].blk[d.name];
@@ -857,9 +876,9 @@ void build(ftcc_ctx* c) {
     if (t == id_E) return c->s_e[p];
     fail(FTCC_EINVAL, "unbound tensor " + d.name);
   };
-  Binder bind_d = [&, c](int t, int p, bool grad) -> double* {
+  Binder bind_d = [&, c](int t, int p, bool grad, size_t count) -> double* {
     const TensorDecl& d = prog.t[t];
-    if (double* q = bind_common(t, p, grad)) return q;
+    if (double* q = bind_common(t, p, grad, count)) return q;
     const int i = probs[p].inst;
     const long n = probs[p].n, n2 = n * n;
     if (d.kind == T_CONST) return c->inst[i].dblk[d.name];
