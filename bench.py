@@ -723,7 +723,7 @@ def main():
     ap.add_argument("--tol", type=float, default=0.0, help="--mode gradient: sweep tolerance (0: the workload's)")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
-    ap.add_argument("--group", type=int, default=32)
+    ap.add_argument("--group", type=int, default=32, help="--mode batch: instances per context")
     ap.add_argument("--subset", default="all", choices=("all", "rings"))
     ap.add_argument("--momentum", action="store_true")
     ap.add_argument("--dense", action="store_true", help="--mode numerr: dense contractions")
