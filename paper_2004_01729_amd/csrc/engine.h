@@ -251,9 +251,10 @@ class Executor {
   bool dot_blocked(std::vector<Launch>& dst, const PerProb& A, const std::string& ai, const PerProb& B,
                    const std::string& bi, const PerProb& out, double alpha, double beta, int t_a, int t_b,
                    const std::string& tag);
+  // xp / yp >= 0 override the storage (packed or not) of the X / Y side
   bool elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
                     const std::string& yi, double alpha, double beta, int t_y, int t_x, const std::string& tag,
-                    const std::vector<const double*>* scale = nullptr);
+                    const std::vector<const double*>* scale = nullptr, int xp = -1, int yp = -1);
   PerProb const_permuted(int tensor, const PerProb& X, const std::string& xi, const std::string& yi);
   void* upload(const void* host, size_t bytes);
   void dump_plan() const;
@@ -306,7 +307,11 @@ class Executor {
   const GroupTable& group_table(int inst, long n, const std::string& letters, const std::string& xi, bool xp,
                                 const std::string& yi, bool yp, const std::vector<int>& signs);
   std::vector<char> packed_;               // per tensor: stored packed (n^(rank-1) doubles)
+  bool pack_on_ = false;                   // packing applies to this executor's problems
   void plan_packing(bool want_backward);
+  // constants (and derived constants) read through packed copies: no gradient asked
+  // for them, and every op that reads them lowers to blocked kernels
+  std::vector<int> plan_const_packing(const std::vector<int>& const_grads) const;
   bool is_packed(int t) const { return t >= 0 && t < (int)packed_.size() && packed_[t]; }
   size_t elems(int t, long n, int rank) const { return (size_t)ipow_l(n, is_packed(t) ? rank - 1 : rank); }
   static long ipow_l(long n, int r) {

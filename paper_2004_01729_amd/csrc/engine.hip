@@ -702,9 +702,11 @@ int Executor::n_packed() const {
 void Executor::plan_packing(bool want_backward) {
   const int nt = (int)prog_->t.size();
   packed_.assign(nt, 0);
+  pack_on_ = false;
   if (mom_.empty() || !packing_enabled()) return;
   for (const ProblemRef& p : probs_)
     if (p.inst < 0 || p.inst >= (int)mom_.size() || !mom_[p.inst] || !labels_distinct(*mom_[p.inst])) return;
+  pack_on_ = true;
   for (int k = 0; k < nt; ++k) {
     const TensorDecl& d = prog_->t[k];
     packed_[k] = (d.kind == T_INTER && !d.derived && d.rank >= 2 && law_ok_[k]) ? 1 : 0;
@@ -718,6 +720,26 @@ void Executor::plan_packing(bool want_backward) {
     packed_[o.a] = 0;
     if (o.b >= 0) packed_[o.b] = 0;
   }
+}
+
+std::vector<int> Executor::plan_const_packing(const std::vector<int>& const_grads) const {
+  std::vector<int> out;
+  if (!pack_on_ || inline_setup_) return out;
+  const int nt = (int)prog_->t.size();
+  for (int k = 0; k < nt; ++k) {
+    const TensorDecl& d = prog_->t[k];
+    if (!(d.kind == T_CONST || d.derived) || d.rank < 2 || !law_ok_[k]) continue;
+    if (std::find(const_grads.begin(), const_grads.end(), k) != const_grads.end()) continue;
+    bool ok = true, used = false;
+    for (const SymOp& o : prog_->ops) {
+      if (o.setup) continue;
+      if (o.out != k && o.a != k && o.b != k) continue;
+      used = true;
+      if (!(law_ok_[o.out] && law_ok_[o.a] && (o.b < 0 || law_ok_[o.b]))) ok = false;
+    }
+    if (ok && used) out.push_back(k);
+  }
+  return out;
 }
 
 void Executor::infer_laws() {
@@ -1030,7 +1052,8 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
 // Returns false (dense lowering) when a law is unknown.
 bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const std::string& xi, const PerProb& Y,
                             const std::string& yi, double alpha, double beta, int t_y, int t_x,
-                            const std::string& tag, const std::vector<const double*>* scale) {
+                            const std::string& tag, const std::vector<const double*>* scale, int xp, int yp) {
+  const bool xpk = xp >= 0 ? xp != 0 : is_packed(t_x), ypk = yp >= 0 ? yp != 0 : is_packed(t_y);
   if (mom_.empty() || t_y < 0 || t_x < 0 || !law_ok_[t_y] || !law_ok_[t_x] || yi.empty()) return false;
   const std::vector<int>& ly = law_[t_y];
   const std::vector<int>& lx = law_[t_x];
@@ -1053,8 +1076,8 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
     const int inst = probs_[p].inst;
     const long n = probs_[p].n;
     if (ipow(n, (int)yi.size()) >= (1L << 32)) throw std::runtime_error("tensor exceeds 2^32 elements: " + tag);
-    const GroupTable& T1 = group_table(inst, n, G1, xi, is_packed(t_x), yi, is_packed(t_y), s1);
-    const GroupTable& T2 = group_table(inst, n, G2, xi, is_packed(t_x), yi, is_packed(t_y), s2);
+    const GroupTable& T1 = group_table(inst, n, G1, xi, xpk, yi, ypk, s1);
+    const GroupTable& T2 = group_table(inst, n, G2, xi, xpk, yi, ypk, s2);
     ElemProblem& P = ps[p];
     P.X = X[p];
     P.Y = Y[p];
@@ -1083,9 +1106,11 @@ bool Executor::elem_blocked(std::vector<Launch>& dst, const PerProb& X, const st
   for (int p = 0; p < np; ++p) {
     const long n = probs_[p].n;
     if (alpha != 0.0 && scale) add_range(L.rd, (*scale)[p], sizeof(double));
-    if (alpha != 0.0) add_range(L.rd, X[p], sizeof(double) * elems(t_x, n, (int)xi.size()));
-    if (beta != 0.0) add_range(L.rd, Y[p], sizeof(double) * elems(t_y, n, (int)yi.size()));
-    add_range(L.wr, Y[p], sizeof(double) * elems(t_y, n, (int)yi.size()));
+    const size_t ex = (size_t)ipow_l(n, (int)xi.size() - (xpk ? 1 : 0));
+    const size_t ey = (size_t)ipow_l(n, (int)yi.size() - (ypk ? 1 : 0));
+    if (alpha != 0.0) add_range(L.rd, X[p], sizeof(double) * ex);
+    if (beta != 0.0) add_range(L.rd, Y[p], sizeof(double) * ey);
+    add_range(L.wr, Y[p], sizeof(double) * ey);
   }
   L.ranged = true;
   L.kind = Launch::ELEM;
@@ -1437,6 +1462,27 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
       if (o.b >= 0) ob = sub(fwd[o.b]);
       contract(setup_, sub(fwd[o.out]), o.oi, o.alpha, sub(fwd[o.a]), o.ai, -1, o.b >= 0 ? &ob : nullptr, o.bi,
                -1, o.accumulate, "setup:" + prog->t[o.out].name);
+    }
+    // Packed copies of the constants the blocked ops read, gathered from the dense
+    // blocks (after the derived ones are made) each time the set-up list runs; the
+    // program then reads the copies.
+    for (int k : plan_const_packing(const_grads)) {
+      const TensorDecl& d = prog->t[k];
+      std::string ix;
+      for (int a = 0; a < d.rank; ++a) ix.push_back((char)('p' + a));
+      PerProb pk;
+      std::map<int, double*> of_inst;
+      for (const ProblemRef& f : firsts) {
+        const size_t cnt = (size_t)ipow_l(f.n, d.rank - 1);
+        double* q = const_alloc_(f.inst, cnt);
+        const_bytes_ += sizeof(double) * cnt;
+        of_inst[f.inst] = q;
+        pk.push_back(q);
+      }
+      if (!elem_blocked(setup_, sub(fwd[k]), ix, pk, ix, 1.0, 0.0, k, k, "setup:pack:" + d.name, nullptr, 0, 1))
+        throw std::runtime_error("no packed copy of constant " + d.name);
+      for (int p = 0; p < np; ++p) fwd[k][p] = of_inst[probs[p].inst];
+      packed_[k] = 1;
     }
     probs_ = probs;
     scratch_ = scratch;
