@@ -312,6 +312,9 @@ class Executor {
   // constants (and derived constants) read through packed copies: no gradient asked
   // for them, and every op that reads them lowers to blocked kernels
   std::vector<int> plan_const_packing(const std::vector<int>& const_grads) const;
+  // inputs and outputs of rank >= 2 worked on through packed shadows: gathered from
+  // their dense buffers at the start of a pass, scattered back at its end
+  std::vector<int> plan_io_packing() const;
   bool is_packed(int t) const { return t >= 0 && t < (int)packed_.size() && packed_[t]; }
   size_t elems(int t, long n, int rank) const { return (size_t)ipow_l(n, is_packed(t) ? rank - 1 : rank); }
   static long ipow_l(long n, int r) {

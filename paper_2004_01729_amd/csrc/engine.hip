@@ -742,6 +742,23 @@ std::vector<int> Executor::plan_const_packing(const std::vector<int>& const_grad
   return out;
 }
 
+std::vector<int> Executor::plan_io_packing() const {
+  std::vector<int> out;
+  if (!pack_on_ || inline_setup_) return out;
+  const int nt = (int)prog_->t.size();
+  for (int k = 0; k < nt; ++k) {
+    const TensorDecl& d = prog_->t[k];
+    if (!(d.kind == T_INPUT || d.kind == T_OUTPUT) || d.rank < 2 || !law_ok_[k]) continue;
+    bool ok = true;
+    for (const SymOp& o : prog_->ops) {
+      if (o.setup || (o.out != k && o.a != k && o.b != k)) continue;
+      if (!(law_ok_[o.out] && law_ok_[o.a] && (o.b < 0 || law_ok_[o.b]))) ok = false;
+    }
+    if (ok) out.push_back(k);
+  }
+  return out;
+}
+
 void Executor::infer_laws() {
   const int nt = (int)prog_->t.size();
   law_.assign(nt, {});
@@ -1487,6 +1504,44 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
     probs_ = probs;
     scratch_ = scratch;
   }
+  // Packed shadows of the rank >= 2 inputs and outputs (and of their gradients):
+  // the ops work on the shadows, the inputs are gathered into them first and the
+  // outputs scattered back last (over the allowed elements; the dense buffers'
+  // forbidden elements stay zero).
+  const std::vector<int> io = plan_io_packing();
+  std::vector<PerProb> dense_f(nt), dense_g(nt);
+  auto shadows = [&](int k) {
+    PerProb s(np);
+    for (int p = 0; p < np; ++p) {
+      const size_t cnt = (size_t)ipow_l(probs[p].n, prog->t[k].rank - 1);
+      s[p] = const_alloc_(probs[p].inst, cnt);
+      const_bytes_ += sizeof(double) * cnt;
+    }
+    return s;
+  };
+  auto letters = [](int r) {
+    std::string ix;
+    for (int a = 0; a < r; ++a) ix.push_back((char)('p' + a));
+    return ix;
+  };
+  for (int k : io) {
+    dense_f[k] = fwd[k];
+    fwd[k] = shadows(k);
+    if (need_grad[k]) {
+      dense_g[k] = grd[k];
+      grd[k] = shadows(k);
+    }
+    packed_[k] = 1;
+  }
+  auto move_packed = [&](std::vector<Launch>& dst, const PerProb& X, const PerProb& Y, int k, bool to_packed,
+                         const std::string& what) {
+    const std::string ix = letters(prog->t[k].rank);
+    if (!elem_blocked(dst, X, ix, Y, ix, 1.0, 0.0, k, k, what + prog->t[k].name, nullptr, to_packed ? 0 : 1,
+                      to_packed ? 1 : 0))
+      throw std::runtime_error("no packed shadow of " + prog->t[k].name);
+  };
+  for (int k : io)
+    if (prog->t[k].kind == T_INPUT) move_packed(fwd_, dense_f[k], fwd[k], k, true, "gather:");
   version_.assign(nt, 0);
   auto vidx = [&](int k) { return (k >= 0 && cidx(k) < 0) ? k : -1; };
   for (const SymOp& o : prog->ops) {
@@ -1495,6 +1550,8 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
              cidx(o.b), o.accumulate, prog->t[o.out].name, vidx(o.a), vidx(o.b), o.out, o.a, o.b);
     version_[o.out]++;
   }
+  for (int k : io)
+    if (prog->t[k].kind == T_OUTPUT) move_packed(fwd_, fwd[k], dense_f[k], k, false, "scatter:");
   if (!want_backward) {
     const char* fz = std::getenv("FTCC_FUSE");
     if (!mom_.empty() && !(fz && fz[0] == '0')) fuse_levels(fwd_);
@@ -1505,6 +1562,8 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
   for (int k = 0; k < nt; ++k)
     if (need_grad[k] && prog->t[k].kind != T_OUTPUT)
       fill(bwd_, grd[k], prog->t[k].rank, "zero:" + prog->t[k].name, k);
+  for (int k : io)
+    if (need_grad[k] && prog->t[k].kind == T_OUTPUT) move_packed(bwd_, dense_g[k], grd[k], k, true, "gather:d");
   for (int i = (int)prog->ops.size() - 1; i >= 0; --i) {
     const SymOp& o = prog->ops[i];
     if (o.setup && !inline_setup_) continue;
@@ -1522,6 +1581,8 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
       contract(bwd_, grd[o.b], o.bi, o.alpha, fwd[o.a], o.ai, cidx(o.a), &grd[o.out], o.oi, -1, true, tag + ":dB",
                vidx(o.a), -1, o.b, o.a, o.out);
   }
+  for (int k : io)
+    if (need_grad[k] && prog->t[k].kind == T_INPUT) move_packed(bwd_, grd[k], dense_g[k], k, false, "scatter:d");
   // FTCC_FUSE=0 keeps the program order, one launch per contraction (diagnostics)
   const char* fz = std::getenv("FTCC_FUSE");
   if (!mom_.empty() && !(fz && fz[0] == '0')) {
