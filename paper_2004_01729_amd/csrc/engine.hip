@@ -400,7 +400,7 @@ void Executor::contract(std::vector<Launch>& dst, const PerProb& out, const std:
   if (!B) {
     for (char c : ai)
       if (!has(oi, c)) throw std::runtime_error("single-operand reduction unsupported: " + tag);
-    if (&dst != &setup_ && elem_blocked(dst, A, ai, out, oi, alpha, beta, t_out, t_a, tag)) return;
+    if (elem_blocked(dst, A, ai, out, oi, alpha, beta, t_out, t_a, tag)) return;
     dense_guard(tag, {t_out, t_a});
     perm(dst, A, ai, out, oi, alpha, beta, nullptr, tag);
     return;
@@ -1478,7 +1478,7 @@ void Executor::build(const Program* prog, const std::vector<ProblemRef>& probs, 
       PerProb ob;
       if (o.b >= 0) ob = sub(fwd[o.b]);
       contract(setup_, sub(fwd[o.out]), o.oi, o.alpha, sub(fwd[o.a]), o.ai, -1, o.b >= 0 ? &ob : nullptr, o.bi,
-               -1, o.accumulate, "setup:" + prog->t[o.out].name);
+               -1, o.accumulate, "setup:" + prog->t[o.out].name, -1, -1, o.out, o.a, o.b);
     }
     // Packed copies of the constants the blocked ops read, gathered from the dense
     // blocks (after the derived ones are made) each time the set-up list runs; the

@@ -1166,6 +1166,10 @@ void tau_run(ftcc_ctx* c, int mode, int panel) {
 }
 
 void set_active(ftcc_ctx* c, const std::vector<bool>& active) {
+  // the device flags change only here: no copy when they already hold this set
+  bool same = (int)c->active_host.size() == c->B;
+  for (int i = 0; same && i < c->B; ++i) same = (c->active_host[i] != 0) == active[i];
+  if (same) return;
   c->active_host.assign(c->B, 0);
   for (int i = 0; i < c->B; ++i) c->active_host[i] = active[i] ? 1 : 0;
   FTCC_HIP(hipMemcpyAsync(c->d_active, c->active_host.data(), sizeof(int) * c->B, hipMemcpyHostToDevice,
