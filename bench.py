@@ -12,6 +12,9 @@ s(tau) = -S0 (1 - exp(-Delta tau)) / Delta at tau = beta / 2 (S0 the residual at
 zero amplitudes), on device-resident data through the replayed HIP graph.
 value = residual evaluations per second.  The dominant kernel's duration comes
 from a separate pass with per-launch HIP events after the timed steps.
+config.momentum_blocked_same_residual: the same residual at the same
+amplitudes through the momentum-blocked path (crystal momentum of the plane
+waves set on the instance), its throughput and energy against the dense one.
 Secondary fields (config.secondary): the 57-plane-wave gas (r_s = 1,
 Theta = 0.5, 16 tau points) through the whole path -- forward march, Lambda
 adjoint, response dOmega/dmu, dOmega/dbeta, dOmega/dh -- and the adjoint
@@ -20,7 +23,7 @@ Synthetic: every Hamiltonian is generated from these parameters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-secondary]
        python bench.py --mode step [--workload ueg57|ueg123|hubbard6|hubbard10] [--momentum]
-       python bench.py --mode residual|copy|batch|numerr|exc|afm ...
+       python bench.py --mode residual|copy|batch|numerr|gradient|exc|afm ...
 
 --mode step times whole steps (thermal set-up + forward march + Lambda +
 response) of one workload.  --mode residual times R back-to-back residual
@@ -656,6 +659,7 @@ def m1_bench(args):
         ctx.time_residual(1)
     prof = ctx.kernel_profile(0)
     ctx.close()
+    blocked = blocked_m1(s, opts, t1, t2, float(E), args.steps, args.warmup)
     evals = args.steps * m
     achieved = prof["flops"] / prof["seconds"] if prof["seconds"] > 0 else 0.0
     roofline = {
@@ -691,10 +695,39 @@ def m1_bench(args):
                        gemm_flop_per_eval=flop_sweep / m,
                        step_gemm_tflops=flop_sweep * args.steps / el / 1e12,
                        step_frac_fp64_mfma=flop_sweep * args.steps / el / PEAK_FP64_MFMA,
-                       E_first_order=float(E)),
+                       E_first_order=float(E), momentum_blocked_same_residual=blocked),
         "roofline": roofline,
     }
     return line, s
+
+
+def blocked_m1(s, opts, t1, t2, e_dense, steps, warmup):
+    """The same residual at the same amplitudes through the momentum-blocked path
+    (crystal momentum of the plane waves set on the instance; packed blocked
+    storage, four node slots): throughput, the energy against the dense path's,
+    and the algorithmic bytes against the HBM peak."""
+    import torch
+    from paper_2004_01729_amd import ftcc as F
+    t0 = time.perf_counter()
+    ctx = F.Context(1, **opts)
+    ctx.set_momentum(0, *s.momentum)
+    ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
+    _, _, e_b = ctx.eval_residual(0, s.mu, s.beta, t1, t2)
+    setup = time.perf_counter() - t0
+    for _ in range(warmup):
+        ctx.time_residual(1)
+    torch.cuda.synchronize()
+    reps = max(steps, 1) * 20
+    sec, fl = ctx.time_residual(reps)
+    plan = ctx.plan_info()
+    ctx.close()
+    m = opts["nodes_per_panel"]
+    by = plan["bytes_forward"] / plan["slots"]
+    return dict(evals_per_s=reps * m / sec, ms_per_eval=1e3 * sec / (reps * m), reps=reps,
+                E_first_order=float(e_b), E_rel_diff_vs_dense=abs(float(e_b) - e_dense) / abs(e_dense),
+                blocked_flop_per_eval=fl / m, algorithmic_bytes_per_eval=by,
+                achieved_gbps=by * reps * m / sec / 1e9, frac_hbm=by * reps * m / sec / PEAK_HBM,
+                dispatches_per_forward_pass=plan["dispatches_forward"], slots=plan["slots"], context_setup_s=setup)
 
 
 def secondary_57(steps=1, warmup=1):

@@ -185,3 +185,37 @@ def test_fused_launch_levels_change_no_result(F, monkeypatch):
     assert np.array_equal(r0["mu"], r1["mu"]) and np.array_equal(r0["beta"], r1["beta"])
     for a, b in zip(r0["h"], r1["h"]):
         assert np.array_equal(a, b)
+
+
+def test_packed_storage_changes_no_result(F, monkeypatch):
+    """Every orbital of these instances has its own momentum label, so the blocked
+    executors work on packed data (intermediates, copies of the integral blocks,
+    shadows of t and S: n^(rank-1) doubles each); the kernels and their order of
+    operations are the same as with dense storage (FTCC_PACK=0), so are the bits.
+    Packing also lets the batch keep one executor slot per node."""
+    systems = [fi.ueg_config(19, 14, 1.0, 1.0), fi.hubbard_config(L=5, U=3.0, T=0.8),
+               fi.hubbard_config(L=6, U=2.0, T=1.0)]
+    out = []
+    for pack in ("1", "0"):
+        monkeypatch.setenv("FTCC_PACK", pack)
+        print(f"[momentum] mixed batch FTCC_PACK={pack}", flush=True)
+        ctx = _ctx(F, systems, n_tau=8, nodes_per_panel=4, tol=1e-13)
+        ctx.solve([s.mu for s in systems], [s.beta for s in systems])
+        om, parts = ctx.grand_potential()
+        amp = ctx.amplitudes(2, 7)
+        ctx.lam()
+        lam = ctx.get_lambda(0, 3)
+        r = ctx.response(want_mu=True, want_beta=True, want_h=True, want_eps=True)
+        ctx.close()
+        out.append((om, parts, amp, lam, r))
+    (o0, p0, a0, l0, r0), (o1, p1, a1, l1, r1) = out
+    assert np.array_equal(o0, o1) and np.array_equal(p0, p1)
+    for x, y in zip(a0, a1):
+        assert np.array_equal(x, y)
+    for x, y in zip(l0, l1):
+        assert np.array_equal(x, y)
+    for key in ("mu", "beta"):
+        assert np.array_equal(r0[key], r1[key])
+    for key in ("h", "eps"):
+        for x, y in zip(r0[key], r1[key]):
+            assert np.array_equal(x, y)
