@@ -878,11 +878,13 @@ const Executor::GroupTable& Executor::group_table(int inst, long n, const std::s
 // 0 (16 x 16 MFMA tiles) or a lane-mapped shape code, whichever needs fewer wave
 // latencies by a simple count: a wave costs 3 dependent memory latencies (task,
 // offsets, the store) plus 2 per step of its inner loop; an MFMA step covers 32
-// inner indices, a lane-mapped step 8 per lane of the inner slices (at most 2
-// steps: a lane-mapped wave with a longer chain outlasted the split MFMA tiles
-// in the 123-plane-wave step, 4.3 s against 4.0 s with this cap, 4.5 s without
-// lane-mapped tiles).
-static int sgemm_shape(int ml, int nl, int kl) {
+// inner indices, a lane-mapped step 8 per lane of the inner slices (at most
+// `cap` steps: longer ranges go to MFMA tiles split over several waves).  With
+// the operands in cache (packed storage) long lane-mapped chains pay: 1.31 s per
+// 123-PW step with a cap of 16 steps against 1.44 s with 2 and 1.79 s without
+// lane-mapped tiles; with every operand scattered over dense arrays a cap of 2
+// had been the best.
+static int sgemm_shape(int ml, int nl, int kl, long cap) {
   auto cdiv = [](long a, long b) { return (a + b - 1) / b; };
   auto steps = [&](long per) { return std::max(1L, cdiv(kl, per)); };
   const long mfma = cdiv(ml, 16) * cdiv(nl, 16) * (3 + 2 * steps(32));
@@ -891,7 +893,7 @@ static int sgemm_shape(int ml, int nl, int kl) {
   for (int lr = 0; lr <= 6; ++lr)
     for (int lc = 0; lr + lc <= 6; ++lc) {
       const int ls = 6 - lr - lc;
-      if (steps(8L << ls) > 2) continue;   // longer ranges: MFMA tiles split over several waves
+      if (steps(8L << ls) > cap) continue;   // longer ranges: MFMA tiles split over several waves
       const long c = cdiv(ml, 1L << lr) * cdiv(nl, 1L << lc) * (3 + 2 * steps(8L << ls));
       if (c < best) {
         best = c;
@@ -900,6 +902,8 @@ static int sgemm_shape(int ml, int nl, int kl) {
     }
   return shape;
 }
+
+constexpr long kSgemmThinSteps = 16;
 
 // wave latencies of a task by the same count (the order of a merged task list)
 static long sgemm_task_cost(const SgemmTask& t) {
@@ -944,10 +948,12 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
     int p, m0, ml, k0, kl, n0, nl, shape;
   };
   std::vector<Tile> tiles;
-  // FTCC_SGEMM_THIN=0: 16 x 16 MFMA tiles for every block (diagnostics)
+  // FTCC_SGEMM_THIN=0: 16 x 16 MFMA tiles for every block; =N: at most N inner
+  // steps per lane-mapped wave (diagnostics)
   double bytes = 0.0;
   const char* thin_env = std::getenv("FTCC_SGEMM_THIN");
-  const bool thin_ok = !(thin_env && thin_env[0] == '0');
+  const long thin_cap = thin_env ? std::atol(thin_env) : kSgemmThinSteps;
+  const bool thin_ok = thin_cap > 0;
   std::vector<double> pf(np, 0.0);
   std::vector<int> pinst(np);
   double flops = 0.0;
@@ -994,7 +1000,7 @@ bool Executor::contract_blocked(std::vector<Launch>& dst, const PerProb& out, co
       if (kl == 0 && acc) continue;   // nothing to add; a set writes its zeros
       const int m0 = blk.second.first, ml = blk.second.second;
       const int n0 = nb->second.first, nl = nb->second.second;
-      const int shape = thin_ok ? sgemm_shape(ml, nl, kl) : 0;
+      const int shape = thin_ok ? sgemm_shape(ml, nl, kl, thin_cap) : 0;
       const int R = shape ? 1 << (shape & 7) : 16, C = shape ? 1 << ((shape >> 3) & 7) : 16;
       for (int r = 0; r < ml; r += R)
         for (int c = 0; c < nl; c += C)
