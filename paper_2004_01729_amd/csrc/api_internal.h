@@ -110,6 +110,17 @@ struct ftcc_ctx {
   std::vector<std::array<double*, 4>> s_ugrad;
   std::map<std::pair<int, int>, double*> inter, inter_grad, dderived;   // (tensor, problem) / (tensor, inst)
   std::map<const double*, long> buf_elems;    // element counts of the buffers above (shared by executors)
+  // grouped response accumulation (built on first use): one dot per (instance,
+  // node) into resp_vals, the node sums per instance in node order
+  DotProblem* d_resp_dots = nullptr;
+  double* d_resp_vals = nullptr;
+  double* d_resp_w = nullptr;                 // [m] (1/beta) g_x
+  const double** d_de_ptrs = nullptr;         // [B m] derivative energies of the nodes
+  double** d_acc_ptrs = nullptr;              // [B] response accumulators
+  const double** d_ug_src = nullptr;          // [B 4 m] one-body gradients of the nodes
+  double** d_ug_dst = nullptr;                // [B 4] their accumulators
+  long* d_n2 = nullptr;                       // [B] n^2
+  long max_n2 = 0;
   std::map<std::pair<int, int>, double*> derived;
   std::vector<std::array<double*, 4>> ugrad;
   Scratch scratch;

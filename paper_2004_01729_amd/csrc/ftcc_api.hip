@@ -206,6 +206,29 @@ __global__ void momentum_check_kernel(int n, int rank, int dims, const int* __re
   }
 }
 
+// One-body gradients of every node added into the instance accumulators, node
+// by node in order (the sums of one add per node): block row = (instance, block).
+__global__ void ugrad_sum_kernel(int m, const double* const* src, double* const* dst, const long* n2) {
+  const int ik = blockIdx.y;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n2[ik / 4]) return;
+  double v = dst[ik][e];
+  for (int x = 0; x < m; ++x) v = src[(size_t)ik * m + x][e] + v;
+  dst[ik][e] = v;
+}
+
+// acc[i] += the node dots of instance i in node order, then (1/beta) g_x dE_x
+// in node order (the sums the per-node dots and adds gave)
+__global__ void resp_combine_kernel(int B, int m, const double* vals, const double* const* de, const double* w,
+                                    double* const* acc, int slot) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B) return;
+  double s = acc[i][slot];
+  for (int x = 0; x < m; ++x) s = vals[i * m + x] + s;
+  for (int x = 0; x < m; ++x) s = w[x] * de[i * m + x][0] + s;
+  acc[i][slot] = s;
+}
+
 __global__ void zero_u64_kernel(unsigned long long* p, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = 0ull;
@@ -1863,6 +1886,59 @@ int ftcc_get_lambda(ftcc_ctx* c, int i, int k, double* l1, double* l2, double* l
   });
 }
 
+// Descriptors of the grouped response accumulation (collocation panels): the
+// node buffers are fixed for the context, so they are uploaded once.
+static void ensure_resp_groups(ftcc_ctx* c) {
+  if (c->d_resp_dots) return;
+  const int B = c->B, m = c->m, P = c->P;
+  std::vector<DotProblem> ds(B * m);
+  std::vector<const double*> de(B * m), ugs((size_t)B * 4 * m);
+  std::vector<double*> acc(B), ugd((size_t)B * 4);
+  std::vector<long> n2(B);
+  std::vector<double> w(m);
+  c->d_resp_vals = c->dalloc(B * m);
+  for (int x = 0; x < m; ++x) w[x] = c->rule.b[x] / P;
+  for (int i = 0; i < B; ++i) {
+    const long n = c->inst[i].n;
+    n2[i] = n * n;
+    c->max_n2 = std::max(c->max_n2, n2[i]);
+    acc[i] = c->inst[i].acc;
+    for (int k = 0; k < 4; ++k) ugd[i * 4 + k] = c->inst[i].ugrad_acc[k];
+    for (int x = 0; x < m; ++x) {
+      const int q = i * m + x;
+      DotProblem d{};
+      d.X = c->cot[q];
+      d.Y = c->dS[q];
+      d.out = c->d_resp_vals + q;
+      d.len = n * n + n * n * n * n;
+      if (c->inst[i].d_allowed[0]) {   // momentum labels: the allowed elements only
+        d.ia = c->inst[i].d_allowed[0];
+        d.na = c->inst[i].n_allowed[0];
+        d.ib = c->inst[i].d_allowed[1];
+        d.nb = c->inst[i].n_allowed[1];
+        d.second = n * n;
+      }
+      d.alpha = 1.0;
+      d.beta = 0.0;
+      ds[q] = d;
+      de[q] = c->de[q];
+      for (int k = 0; k < 4; ++k) ugs[((size_t)i * 4 + k) * m + x] = c->ugrad[q][k];
+    }
+  }
+  auto up = [c](const void* h, size_t bytes) {
+    double* d = c->dalloc((bytes + 7) / 8);
+    FTCC_HIP(hipMemcpy(d, h, bytes, hipMemcpyHostToDevice));
+    return (void*)d;
+  };
+  c->d_resp_dots = (DotProblem*)up(ds.data(), sizeof(DotProblem) * ds.size());
+  c->d_resp_w = (double*)up(w.data(), sizeof(double) * w.size());
+  c->d_de_ptrs = (const double**)up(de.data(), sizeof(double*) * de.size());
+  c->d_acc_ptrs = (double**)up(acc.data(), sizeof(double*) * acc.size());
+  c->d_ug_src = (const double**)up(ugs.data(), sizeof(double*) * ugs.size());
+  c->d_ug_dst = (double**)up(ugd.data(), sizeof(double*) * ugd.size());
+  c->d_n2 = (long*)up(n2.data(), sizeof(long) * n2.size());
+}
+
 int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, double* dO_deps,
                   const double* const* deri_dtheta, const double* const* dh_dtheta, double* dO_dtheta) {
   return run_guarded([&] {
@@ -1923,39 +1999,13 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
       for (int k = 0; k < 4; ++k) zero_d(c, c->inst[i].ugrad_acc[k], n * n);
     }
     // dot launches: <lamt_x, dS_x> and (g_x/beta) dE_x accumulated into acc[slot]
+    // all (instance, node) dots in one launch, then the node sums per instance
     auto accumulate = [&](int slot) {
-      std::vector<DotProblem> ds;
-      for (int i = 0; i < B; ++i)
-        for (int x = 0; x < m; ++x) {
-          const int q = i * m + x;
-          DotProblem d{};
-          const long n = c->inst[i].n;
-          d.X = c->cot[q];
-          d.Y = c->dS[q];
-          d.out = c->inst[i].acc + slot;
-          d.len = n * n + n * n * n * n;
-          if (c->inst[i].d_allowed[0]) {   // momentum labels: the allowed elements only
-            d.ia = c->inst[i].d_allowed[0];
-            d.na = c->inst[i].n_allowed[0];
-            d.ib = c->inst[i].d_allowed[1];
-            d.nb = c->inst[i].n_allowed[1];
-            d.second = n * n;
-          }
-          d.alpha = 1.0;
-          d.beta = 1.0;
-          ds.push_back(d);
-        }
-      // sequential per problem to keep a fixed summation order into one scalar
-      for (const DotProblem& d : ds) {
-        DotProblem* dd = nullptr;
-        FTCC_HIP(hipMallocAsync((void**)&dd, sizeof(DotProblem), c->stream));
-        FTCC_HIP(hipMemcpyAsync(dd, &d, sizeof(DotProblem), hipMemcpyHostToDevice, c->stream));
-        launch_dot(dd, 1, 64, c->scratch.dot_partial, c->stream);
-        FTCC_HIP(hipFreeAsync(dd, c->stream));
-      }
-      for (int i = 0; i < B; ++i)
-        for (int x = 0; x < m; ++x)
-          launch_axpby(1, c->rule.b[x] / P, c->de[i * m + x], 1.0, c->inst[i].acc + slot, c->stream);
+      ensure_resp_groups(c);
+      launch_dot(c->d_resp_dots, B * m, 64, c->scratch.dot_partial, c->stream);
+      hipLaunchKernelGGL(resp_combine_kernel, dim3((B + 63) / 64), dim3(64), 0, c->stream, B, m,
+                         (const double*)c->d_resp_vals, c->d_de_ptrs, (const double*)c->d_resp_w, c->d_acc_ptrs, slot);
+      FTCC_HIP(hipGetLastError());
     };
     // the same for the orbital-energy direction q: into deps_acc[q] of the
     // instances with more than q orbitals
@@ -2194,12 +2244,10 @@ int ftcc_response(ftcc_ctx* c, double* dO_dmu, double* dO_dbeta, double* dO_dh, 
       tau_run(c, TAU_LAMT, p);   // lambda-tilde of the panel into the cotangent buffers
       if (dO_dh) {
         backward(c);
-        for (int i = 0; i < B; ++i) {
-          const long n = c->inst[i].n;
-          for (int x = 0; x < m; ++x)
-            for (int k = 0; k < 4; ++k)
-              launch_axpby(n * n, 1.0, c->ugrad[i * m + x][k], 1.0, c->inst[i].ugrad_acc[k], c->stream);
-        }
+        ensure_resp_groups(c);
+        hipLaunchKernelGGL(ugrad_sum_kernel, dim3((unsigned)((c->max_n2 + 255) / 256), (unsigned)(4 * B)), dim3(256), 0,
+                           c->stream, m, c->d_ug_src, c->d_ug_dst, (const long*)c->d_n2);
+        FTCC_HIP(hipGetLastError());
       }
       // beta: explicit dependence of the propagator weights (needs S at converged s)
       if (dO_dbeta) {
