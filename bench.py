@@ -55,7 +55,9 @@ if ROOT not in sys.path:
 
 PEAK_FP64_MFMA = 78.6e12      # MI355X dense FP64 matrix, flop/s
 PEAK_HBM = 8.0e12              # MI355X HBM3E, bytes/s
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "gemm128_ueg123_traffic.md")
+# FETCH_SIZE / WRITE_SIZE summaries of the dominant GEMM family, one per workload
+TRAFFIC_PROFILES = {"ueg57": os.path.join(ROOT, "profiles", "gemm128_ueg57_traffic.md"),
+                    "ueg123": os.path.join(ROOT, "profiles", "gemm128_ueg123_traffic.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2004_01729_amd", "csrc", "kernels.hip")
 
 
@@ -72,13 +74,16 @@ def gemm_source_hash():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant GEMM family from the committed
-    FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy); None when
+def measured_traffic(name):
+    """HBM bytes per launch of the dominant GEMM family on workload `name` from
+    the committed FETCH_SIZE / WRITE_SIZE summary of that workload (calibrated
+    against a plain copy); None when there is no summary for the workload or
     the GEMM kernel's source has changed since the counters were taken."""
     import re
+    if name not in TRAFFIC_PROFILES:
+        return None
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(TRAFFIC_PROFILES[name]).read()
         cur = gemm_source_hash()
     except (OSError, ValueError):
         return None
@@ -533,7 +538,7 @@ def step_bench(args, measure_fd_beta=False):
         "peak": PEAK_FP64_MFMA / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP64_MFMA,
-        "traffic": measured_traffic(),
+        "traffic": measured_traffic(args.workload) if not args.momentum else None,
         "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "gemm_mfma_kernel<128,128,16,*,*> (FP64 MFMA 16x16x4)",
         "launches": prof["launches"],
@@ -629,6 +634,11 @@ def first_order_amplitudes(ctx, s):
     return t1, t2
 
 
+def progress(msg):
+    """One progress line on stderr (long phases report as they end)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def m1_bench(args):
     """The default line: residual evaluations per second at the 123-plane-wave
     workload (see the module docstring)."""
@@ -642,15 +652,18 @@ def m1_bench(args):
     S1, S2, E = ctx.eval_residual(0, s.mu, s.beta, t1, t2)     # puts t into every node slot
     del S2
     t_setup = time.perf_counter() - t_setup
+    progress(f"m1: context built and first-order amplitudes set in {t_setup:.1f} s")
     m = opts["nodes_per_panel"]
     for _ in range(args.warmup):
         ctx.time_residual(1)
     torch.cuda.synchronize()
+    progress(f"m1: {args.warmup} warm-up steps done; timing {args.steps} steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ctx.time_residual(1)          # the m node residuals of a panel, replayed graph
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    progress(f"m1: {args.steps} timed steps in {el:.1f} s")
     _, flop_sweep = ctx.time_residual(1)
     # per-launch HIP events on the dominant GEMM family (eager launches of the same lists)
     ctx.kernel_profile(1)
@@ -659,6 +672,7 @@ def m1_bench(args):
         ctx.time_residual(1)
     prof = ctx.kernel_profile(0)
     ctx.close()
+    progress("m1: profiled pass done; the momentum-blocked evaluation of the same residual next")
     blocked = blocked_m1(s, opts, t1, t2, float(E), args.steps, args.warmup)
     evals = args.steps * m
     achieved = prof["flops"] / prof["seconds"] if prof["seconds"] > 0 else 0.0
@@ -668,7 +682,7 @@ def m1_bench(args):
         "peak": PEAK_FP64_MFMA / 1e12,
         "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP64_MFMA,
-        "traffic": measured_traffic(),
+        "traffic": measured_traffic("ueg123"),
         "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "kernel": "gemm_mfma_kernel<128,128,16,*,*> (FP64 MFMA 16x16x4)",
         "launches": prof["launches"],
