@@ -23,13 +23,15 @@ Synthetic: every Hamiltonian is generated from these parameters.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-secondary]
        python bench.py --mode step [--workload ueg57|ueg123|hubbard6|hubbard10] [--momentum]
-       python bench.py --mode residual|copy|batch|numerr|gradient|exc|afm ...
+       python bench.py --mode residual|copy|vendor_gemm|batch|numerr|gradient|exc|afm ...
 
 --mode step times whole steps (thermal set-up + forward march + Lambda +
 response) of one workload.  --mode residual times R back-to-back residual
 evaluations of every node of the last panel at the converged amplitudes;
 --mode copy runs R device-to-device copies of 1 GiB (the byte-counter
-calibration for the traffic figures).  --mode batch runs one step of the
+calibration for the traffic figures); --mode vendor_gemm times the vendor
+library's float64 GEMM (torch.matmul) on plain square products of the
+residuals' GEMM sizes, for comparison only.  --mode batch runs one step of the
 32-instance mixed batch (16 UEG 57-PW points over r_s x Theta, 16 Hubbard rings
 L = 6..14 with random U and T, 20 tau points, occupation threshold 1e-6) in one
 context, and with --per-instance the same instances one context each.
@@ -149,6 +151,35 @@ def residual_throughput(ctx, reps, n_tau):
                 achieved_gbps=by * reps * m / sec / 1e9, frac_hbm=by * reps * m / sec / PEAK_HBM,
                 dispatches_per_forward_pass=plan["dispatches_forward"],
                 dispatches_per_backward_pass=plan["dispatches_backward"], slots=plan["slots"])
+
+
+def vendor_gemm(reps):
+    """For comparison only: the vendor library's float64 GEMM (torch.matmul) on
+    plain square products of the GEMM sizes of the 57- and 123-plane-wave
+    residuals (n^2 = 3249 and 15129), A as stored and transposed, timed with
+    events around `reps` back-to-back calls after one warm-up call."""
+    import torch
+    out = {}
+    for n in (3249, 15129):
+        a = torch.randn(n, n, dtype=torch.float64, device="cuda")
+        b = torch.randn_like(a)
+        c = torch.empty_like(a)
+        for trans in ("NN", "TN"):
+            x = a.t() if trans == "TN" else a
+            torch.matmul(x, b, out=c)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                torch.matmul(x, b, out=c)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tf = 2.0 * n ** 3 / ms / 1e9
+            out[f"{n}_{trans}"] = dict(ms=ms, tflops=tf, frac_fp64_mfma=tf * 1e12 / PEAK_FP64_MFMA)
+        del a, b, c
+        torch.cuda.empty_cache()
+    return dict(mode="vendor_gemm", reps=reps, **out)
 
 
 def copy_calibration(reps, nbytes=1 << 30):
@@ -765,7 +796,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--mode", default="m1",
-                    choices=("m1", "step", "residual", "copy", "batch", "numerr", "afm", "exc", "gradient"))
+                    choices=("m1", "step", "residual", "copy", "vendor_gemm", "batch", "numerr", "afm", "exc",
+                             "gradient"))
     ap.add_argument("--n-tau", type=int, default=0, help="--mode gradient: tau nodes (0: the workload's)")
     ap.add_argument("--tol", type=float, default=0.0, help="--mode gradient: sweep tolerance (0: the workload's)")
     ap.add_argument("--reps", type=int, default=5)
@@ -788,6 +820,9 @@ def main():
         raise SystemExit("no GPU visible")
     if args.mode == "copy":
         print(json.dumps(copy_calibration(args.reps)), flush=True)
+        return
+    if args.mode == "vendor_gemm":
+        print(json.dumps(vendor_gemm(args.reps)), flush=True)
         return
     if args.mode == "exc":
         print(json.dumps(exc_bench()), flush=True)
