@@ -311,3 +311,22 @@ def random_amplitudes(n, seed=0, scale=0.05):
     t2 = rng.standard_normal((n, n, n, n)) * scale
     t2 = 0.5 * (t2 + t2.transpose(1, 0, 3, 2))
     return t1, t2
+
+
+def momentum_masks(labels):
+    """Boolean masks of the t1 and t2 elements that crystal-momentum labels
+    (one integer vector per orbital, no wrap-around) allow: k_i = k_a, and
+    k_i + k_j = k_a + k_b."""
+    lab = np.asarray(labels, dtype=np.int64)
+    base = 4 * int(np.abs(lab).max()) + 1
+    code = (lab[:, 0] * base + lab[:, 1]) * base + lab[:, 2]
+    pair = code[:, None] + code[None, :]
+    return code[:, None] == code[None, :], pair[:, :, None, None] == pair[None, None, :, :]
+
+
+def momentum_allowed_amplitudes(labels, seed=0, scale=0.05):
+    """random_amplitudes(len(labels), seed, scale) with every element that the
+    momentum labels forbid set to zero."""
+    m1, m2 = momentum_masks(labels)
+    t1, t2 = random_amplitudes(len(labels), seed=seed, scale=scale)
+    return t1 * m1, t2 * m2
