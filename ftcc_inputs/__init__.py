@@ -34,7 +34,7 @@ __all__ = [
     "System", "hubbard_ring", "ueg_plane_waves", "ueg_shell_basis",
     "restricted_thermal_hf", "hubbard_config", "ueg_config", "batched_configs",
     "random_amplitudes", "random_hamiltonian", "hubbard_site_basis", "hubbard_unrestricted",
-    "antisymmetric_amplitudes",
+    "antisymmetric_amplitudes", "momentum_masks", "momentum_allowed_amplitudes",
 ]
 
 
