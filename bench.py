@@ -798,7 +798,8 @@ def main():
     ap.add_argument("--mode", default="m1",
                     choices=("m1", "step", "residual", "copy", "vendor_gemm", "batch", "numerr", "afm", "exc",
                              "gradient"))
-    ap.add_argument("--n-tau", type=int, default=0, help="--mode gradient: tau nodes (0: the workload's)")
+    ap.add_argument("--n-tau", type=int, default=0,
+                    help="--mode gradient / residual: tau nodes (0: the workload's)")
     ap.add_argument("--tol", type=float, default=0.0, help="--mode gradient: sweep tolerance (0: the workload's)")
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--per-instance", action="store_true")
@@ -842,14 +843,19 @@ def main():
         return
     if args.mode == "residual":
         s, opts, cfg = workload(args.workload)
+        if args.n_tau > 0:   # a shorter grid (whole panels): the march of its first panels only
+            opts = dict(opts, n_tau=args.n_tau)
+            cfg = dict(cfg, n_tau=args.n_tau)
         ctx = F.Context(1, **opts)
         if args.momentum:
             ctx.set_momentum(0, *s.momentum)
         ctx.set_hamiltonian(0, s.h, s.eri, s.eps)
         ctx.solve(s.mu, s.beta)
+        progress(f"residual: march of {opts['n_tau']} tau nodes done")
         r = residual_throughput(ctx, args.reps, opts["n_tau"])
         ctx.close()
-        print(json.dumps(dict(mode="residual", workload=cfg["workload"], reps=args.reps, **r)), flush=True)
+        print(json.dumps(dict(mode="residual", workload=cfg["workload"], n_tau=opts["n_tau"], reps=args.reps, **r)),
+              flush=True)
         return
     if args.mode == "step":
         line = step_bench(args)
