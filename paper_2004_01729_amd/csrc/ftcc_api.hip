@@ -345,8 +345,8 @@ int run_guarded(const std::function<void()>& f) {
   }
 }
 
-// Progress lines on stderr (one per panel of each phase) when FTCC_TRACE is set:
-// large instances spend minutes per phase.
+// A device buffer shared by the executors under (kind t, key): allocated on first
+// request, checked against the size of every later request.
 double* shared_buf(ftcc_ctx* c, std::map<std::pair<int, int>, double*>& store, int t, int key, long count) {
   auto k = std::make_pair(t, key);
   auto it = store.find(k);
@@ -362,6 +362,8 @@ double* shared_buf(ftcc_ctx* c, std::map<std::pair<int, int>, double*>& store, i
   return p;
 }
 
+// Progress lines on stderr (one per panel of each phase, and one per sweep at
+// level 2) when FTCC_TRACE is set: large instances spend minutes per phase.
 static int trace_level() {
   static const int lv = [] {
     const char* e = std::getenv("FTCC_TRACE");
